@@ -1,0 +1,195 @@
+/*
+ * dd.h -- C ABI of the substructuring Schur-complement solver for nonlocal
+ * FEM systems on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv:2306.00094, section "Matrix formulation of the multi-domain
+ * problem"): the free dofs of the stiffness matrix A are split into the
+ * interiors I_k of K overlapping subdomains and the interface G (the dofs that
+ * lie in two or more subdomains).  With K_II = blockdiag(K_II^k),
+ *
+ *   S = K_GG - sum_k R_k^T K_GI^k (K_II^k)^{-1} K_IG^k R_k   (eq. subSchurComplement,
+ *                                                             summed as in eq. SchurComplement)
+ *   g = b_G  - sum_k R_k^T K_GI^k (K_II^k)^{-1} b_I^k        (eq. subForcing)
+ *   S u_G = g  by preconditioned conjugate gradients,
+ *   u_I^k = (K_II^k)^{-1} (b_I^k - K_IG^k R_k u_G)          (eq. backwardSubstitution)
+ *
+ * where R_k picks the interface dofs coupled to subdomain k.  K_II^k is
+ * non-singular for every subdomain, floating ones included (stated before
+ * eq. splittingBlockCholesky), and is factored once (dd_factor).
+ *
+ * Conventions.
+ *   - All functions return dd_status and never throw across the ABI.
+ *   - Host pointers (H) are read during the call only; device pointers (D)
+ *     are HIP device addresses owned by the caller.
+ *   - Index arrays are int32, 0-based.  Matrices are double precision.
+ *   - All device work of a context runs on the HIP stream given to dd_setup
+ *     (NULL = the default stream).  A context must not be used from two host
+ *     threads at once; independent contexts may run concurrently.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd_ctx dd_ctx;   /* opaque solver context */
+
+typedef enum {
+  DD_OK = 0,
+  DD_EINVAL = 1,   /* malformed argument (message names the field) */
+  DD_ENOMEM = 2,   /* device or host allocation failed */
+  DD_ENOTSPD = 3,  /* Cholesky pivot <= 0 (subdomain, column) or p^T S p <= 0 */
+  DD_ENOCONV = 4,  /* iteration or refinement limit reached; output holds the last iterate */
+  DD_EHIP = 5,     /* HIP runtime error (code in the message) */
+  DD_ESTATE = 6    /* call out of order, e.g. solve before factor */
+} dd_status;
+
+typedef enum {
+  DD_FP64 = 0,     /* FP64 factor, FP64 products, FP64 CG */
+  DD_MIXED = 1     /* FP32 factor and interior solves (FP32 accumulation), FP32 coupling
+                      data with FP64 accumulation, FP64 CG vectors and dots, FP64
+                      full-system residual and iterative-refinement correction */
+} dd_precision;
+
+/* One subdomain, HOST pointers, deep-copied by dd_setup. */
+typedef struct {
+  int32_t n_i;               /* interior dofs of the subdomain (>= 1) */
+  const double *k_ii;        /* n_i*n_i, column-major, symmetric; both triangles given */
+  int32_t n_g;               /* interface dofs coupled to this interior (>= 0) */
+  const int32_t *g_map;      /* n_g: local interface column -> interface index in [0, n_gamma) */
+  const int32_t *kig_rowptr; /* n_i+1: CSR row pointers of K_IG^k (n_i x n_g) */
+  const int32_t *kig_col;    /* nnz: local interface column in [0, n_g) */
+  const double *kig_val;     /* nnz */
+  const int32_t *i_map;      /* n_i: local interior dof -> global dof in [0, n_dof) */
+} dd_subdomain;
+
+/* The partitioned system.  Every global dof is either interior to exactly one
+ * subdomain or an interface dof; interiors of different subdomains must not be
+ * coupled (checked through the sparsity the caller passes). */
+typedef struct {
+  int32_t n_dof;             /* size of the free-dof system A */
+  int32_t n_gamma;           /* interface dofs */
+  int32_t n_sub;             /* number of subdomains K */
+  const dd_subdomain *sub;   /* n_sub entries */
+  const int32_t *gamma_map;  /* n_gamma: interface index -> global dof */
+  const int32_t *kgg_rowptr; /* n_gamma+1: CSR of the global K_GG (n_gamma x n_gamma) */
+  const int32_t *kgg_col;
+  const double *kgg_val;
+} dd_problem;
+
+/* Interior-solve variants for the per-iteration (K_II^k)^{-1} products. */
+typedef enum {
+  DD_APPLY_AUTO = 0,   /* choose by the autotuned table (or INV) */
+  DD_APPLY_INV = 1,    /* product with K_II^{-1} = L^{-T} L^{-1}, formed at factor time */
+  DD_APPLY_TRSM = 2    /* forward and backward triangular sweeps with L */
+} dd_apply;
+
+typedef enum {
+  DD_LAUNCH_AUTO = 0,
+  DD_LAUNCH_KERNELS = 1,     /* one kernel launch per phase, host polls convergence */
+  DD_LAUNCH_PERSISTENT = 2   /* one cooperative kernel runs the whole CG loop */
+} dd_launch;
+
+typedef struct {
+  double tol;            /* stop column c when ||b_c - A u_c||_2 <= tol ||b_c||_2 */
+  int32_t max_it;        /* CG iteration cap per CG solve */
+  int32_t precond;       /* 0 none, 1 exact diag(S) Jacobi */
+  int32_t max_refine;    /* DD_MIXED: outer refinement steps */
+  double inner_tol;      /* DD_MIXED: inner CG stops at ||r_in|| <= inner_tol ||r_outer|| */
+  int32_t fp64_fallback; /* DD_MIXED: 1 = finish stalled columns with the FP64 path */
+  int32_t apply;         /* dd_apply */
+  int32_t launch;        /* dd_launch */
+  int32_t check_every;   /* DD_LAUNCH_KERNELS: host polls convergence every N iterations (0 = auto) */
+  int32_t verify;        /* 1 = compute the true FP64 residual ||b - A u|| / ||b|| into info */
+} dd_solve_opts;
+
+typedef struct {
+  int32_t iters;         /* CG iterations (summed over refinement steps) */
+  int32_t refine_steps;  /* DD_MIXED: outer steps taken */
+  int32_t used_fallback; /* DD_MIXED: 1 if the FP64 path finished this column */
+  int32_t converged;     /* 1 if the tolerance was met */
+  double rel_resid;      /* ||b - A u||_2 / ||b||_2 (FP64) if verify or DD_MIXED, else the
+                            CG recurrence estimate ||r_G||_2 / ||b||_2 */
+} dd_solve_info;
+
+/* Fill opts with defaults: tol 1e-10, max_it 1000, precond 1, max_refine 8,
+ * inner_tol 1e-4, fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1. */
+void dd_default_opts(dd_solve_opts *opts);
+
+/* Device bytes a context for `prob` would hold (matrices, factors for
+ * `prec`, work vectors for max_nrhs right-hand sides).  Validates nothing
+ * beyond the sizes. */
+dd_status dd_footprint(const dd_problem *prob, dd_precision prec, int32_t max_nrhs,
+                       size_t *bytes);
+
+/* Validate `prob` (index ranges, CSR monotonicity, map injectivity, coverage
+ * of every dof, no interior-interior coupling across subdomains), deep-copy it
+ * to the current HIP device and bind the context to `hip_stream`.
+ * max_nrhs in [1, 64]: largest batch dd_solve will accept.  *out is NULL on
+ * error; the message of a failed setup is returned by dd_last_error(NULL). */
+dd_status dd_setup(const dd_problem *prob, void *hip_stream, int32_t max_nrhs,
+                   dd_ctx **out);
+
+/* Factor every K_II^k (batched Cholesky), form the interior-solve operators
+ * and the exact diag(S) preconditioner in precision `prec`.  May be called
+ * again with the other precision; both sets of factors are then kept.
+ * DD_ENOTSPD names the subdomain and column of the first failed pivot. */
+dd_status dd_factor(dd_ctx *ctx, dd_precision prec);
+
+/* Solve A u = b for nrhs columns.  b_dev and u_dev: D, column-major n_dof x
+ * nrhs with leading dimension ld >= n_dof; they may not alias.  Uses the
+ * factors of `prec` (dd_factor(prec) must have run; DD_MIXED falls back to
+ * FP64 factors, computing them on first use, when opts->fp64_fallback).
+ * info_host: H, nrhs entries (may be NULL).  Returns after the solution and
+ * info are complete.  DD_ENOCONV if any column missed the tolerance. */
+dd_status dd_solve(dd_ctx *ctx, dd_precision prec, const double *b_dev, double *u_dev,
+                   int32_t nrhs, int32_t ld, const dd_solve_opts *opts,
+                   dd_solve_info *info_host);
+
+/* q = S p for interface vectors (diagnostic entry; eq. subSchurComplement
+ * summed over subdomains).  p_dev, q_dev: D, column-major n_gamma x nrhs, ld. */
+dd_status dd_schur_apply(dd_ctx *ctx, dd_precision prec, const double *p_dev,
+                         double *q_dev, int32_t nrhs, int32_t ld);
+
+/* Copy the lower Cholesky factor of subdomain k (n_i x n_i column-major,
+ * upper triangle zero) to host memory `out` as doubles (diagnostic entry). */
+dd_status dd_get_factor(dd_ctx *ctx, dd_precision prec, int32_t k, double *out);
+
+/* Copy diag(S) (n_gamma doubles) to host memory (diagnostic entry). */
+dd_status dd_get_schur_diag(dd_ctx *ctx, dd_precision prec, double *out);
+
+/* Per-phase kernel timing of the CG loop (diagnostic entry for profiling).
+ * Phases: one launch each per CG iteration. */
+enum {
+  DD_PHASE_KIG = 0,       /* y = K_IG p                        (all subdomains) */
+  DD_PHASE_INTERIOR = 1,  /* w = K_II^{-1} y                   (all subdomains) */
+  DD_PHASE_GAMMA = 2,     /* q = K_GG p - K_GI w, p^T q, alpha  (interface rows) */
+  DD_PHASE_UPDATE = 3,    /* x, r, z updates, r^T z, r^T r, beta, convergence */
+  DD_NPHASES = 4
+};
+
+/* Enable HIP-event timing of the phases whose bit is set in phase_mask
+ * (0 disables) and reset the accumulators.  An event pair is recorded on
+ * the context's stream around every launch of a timed phase. */
+dd_status dd_set_timing(dd_ctx *ctx, uint32_t phase_mask);
+
+/* Accumulated milliseconds and launch counts per phase since the last
+ * dd_set_timing (ms, launches: H, DD_NPHASES entries each).  Synchronises
+ * the context's stream. */
+dd_status dd_get_timing(dd_ctx *ctx, double *ms, int64_t *launches);
+
+/* Last error message of ctx (or of the last failed dd_setup when ctx is NULL).
+ * The string stays valid until the next call on the same context. */
+const char *dd_last_error(const dd_ctx *ctx);
+
+/* Release every device and host resource of ctx (NULL is accepted). */
+void dd_destroy(dd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_H */

@@ -1,0 +1,882 @@
+// Device code of the substructuring Schur-complement solver (gfx950).
+//
+// Every per-row product is computed by one 64-lane wavefront: lane l takes
+// the row entries l, l+64, l+128, ... in order and the 64 partial sums are
+// combined by an xor butterfly.  A row's result therefore depends only on the
+// row and on the column of right-hand sides it belongs to -- never on how
+// many right-hand sides share the launch, or on the launch shape -- which is
+// what makes a request's result identical alone and inside a batch.
+//
+// Dot products are reduced deterministically: fixed row chunks are reduced
+// in a fixed order (a wave butterfly over 64 rows, or rows in order), and the
+// chunk partials by a fixed two-level tree in the last workgroup to finish
+// (no floating-point atomics).
+//
+// Vectors use the "DD layout": interface vectors are n_gamma x ld and
+// interior vectors NI x ld, row-major with the right-hand-side index fastest
+// (ld = batch width, a power of two <= 64), so a row's entries for all
+// right-hand sides are one contiguous segment.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kRowsE = 64;    // rows per chunk in the element-wise kernels
+constexpr int kMaxLd = 64;    // widest right-hand-side batch
+
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// ---------------------------------------------------------------- state --
+// Per-column CG state, one array of kMaxLd entries per field.
+struct ColState {
+  double *rz;       // r^T z
+  double *alpha;    // step length of the current iteration
+  double *beta;     // direction update of the current iteration
+  double *stop2;    // (tol * ||b||)^2
+  double *nrm2;     // scratch norms
+  int *active;      // 1 while the column iterates
+  int *iters;       // iterations taken
+  int *flag;        // [0]: breakdown (p^T S p <= 0) seen
+};
+
+// Partial-sum buffers and completion counters of the reductions.
+struct RedBuf {
+  double *part0;       // chunk partials, dot 0  (max_chunks x kMaxLd)
+  double *part1;       // chunk partials, dot 1
+  unsigned *counter;   // last-workgroup counters (one per reduction site)
+};
+
+// ---------------------------------------------------------------- trees --
+// Column partial of a chunk: rows 0..63 of lds (stride ld) reduced by the
+// xor butterfly of one wave (a fixed tree, the same for every ld).
+__device__ __forceinline__ double chunk64_sum(const double *lds, int ld, int c) {
+  return wave_sum(lds[lane_id() * ld + c]);
+}
+
+// Chunk partials cross workgroups (and XCDs, whose L2 caches are not kept
+// coherent with each other).  They are written with device-coherent (sc1)
+// stores and read with device-coherent loads; the writing thread waits for
+// its store to complete (s_waitcnt vmcnt(0)) before the workgroup counts
+// itself done.  No L2 write-back or invalidate is needed.
+__device__ __forceinline__ void store_partial(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0) expcnt(7) lgkmcnt(15)
+}
+__device__ __forceinline__ double load_partial(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Final reduction of P chunk partials for column c by one wave: lane t sums
+// partials t, t+64, ... in order, then the butterfly.  Fixed for a given P.
+__device__ __forceinline__ double partials_sum(const double *part, int P, int ld, int c) {
+  double s = 0.0;
+  for (int i = lane_id(); i < P; i += kWave) s += load_partial(part + (size_t)i * ld + c);
+  return wave_sum(s);
+}
+
+// Last-workgroup election after every workgroup stored its partials (with
+// store_partial).  The counter is reset by the elected workgroup.
+__device__ __forceinline__ bool last_block(unsigned *counter, int *lds_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *lds_flag = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  return *lds_flag != 0;
+}
+
+__device__ __forceinline__ void reset_counter(unsigned *counter) {
+  __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------------- row products --
+// Source of gathered vector entries: a plain vector x, or the CG direction
+// formed on the fly, x = z + beta * p_prev (beta per column).
+struct Src {
+  const double *x;       // plain vector (when z == nullptr)
+  const double *z;       // on the fly: z + beta * pp
+  const double *pp;
+  const double *beta;
+};
+
+template <int C>
+__device__ __forceinline__ void src_load(const Src &s, size_t off, const double (&bt)[C],
+                                         double (&out)[C]) {
+  if (s.z) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = fma(bt[c], s.pp[off + c], s.z[off + c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = s.x[off + c];
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) bt[c] = s.z ? s.beta[cp + c] : 0.0;
+}
+
+// acc[c] += sum_k val[k] * x[col[k]][cp + c] over the row, lane-strided.
+// Each lane visits its entries k = b+lane, b+lane+64, ... in increasing order;
+// the loop is unrolled so that up to U gathers are in flight per lane, without
+// changing that order.
+template <int C> struct Unroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
+
+template <int C, typename VT>
+__device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict__ col,
+                                            const VT *__restrict__ val, const Src &x, int ld,
+                                            int cp, double (&acc)[C]) {
+  constexpr int U = Unroll<C>::U;
+  double bt[C];
+  src_beta<C>(x, cp, bt);
+  int k = b + lane_id();
+  for (; k + (U - 1) * kWave < e; k += U * kWave) {
+    double v[U];
+    int cc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = (double)val[k + u * kWave];
+      cc[u] = col[k + u * kWave];
+    }
+    double xv[U][C];
+#pragma unroll
+    for (int u = 0; u < U; ++u) src_load<C>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = tfma(v[u], xv[u][c], acc[c]);
+  }
+  for (; k < e; k += kWave) {
+    double v = (double)val[k];
+    double xv[C];
+    src_load<C>(x, (size_t)col[k] * ld + cp, bt, xv);
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = tfma(v, xv[c], acc[c]);
+  }
+}
+
+// Two-part row: entries [b, s) gather from x1 into acc1, entries [s, e) from
+// x2 into acc2, interleaved in one unrolled loop (each accumulator still sees
+// its entries in increasing order).
+template <int C, typename VT>
+__device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__restrict__ col,
+                                             const VT *__restrict__ val, const Src &x1,
+                                             const Src &x2, int ld, int cp, double (&acc1)[C],
+                                             double (&acc2)[C]) {
+  constexpr int U = Unroll<C>::U;
+  double bt1[C], bt2[C];
+  src_beta<C>(x1, cp, bt1);
+  src_beta<C>(x2, cp, bt2);
+  int k = b + lane_id();
+  for (; k + (U - 1) * kWave < e; k += U * kWave) {
+    double v[U];
+    int cc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = (double)val[k + u * kWave];
+      cc[u] = col[k + u * kWave];
+    }
+    double xv[U][C];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k + u * kWave < s) src_load<C>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
+      else src_load<C>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k + u * kWave < s) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc1[c] = tfma(v[u], xv[u][c], acc1[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc2[c] = tfma(v[u], xv[u][c], acc2[c]);
+      }
+    }
+  }
+  for (; k < e; k += kWave) {
+    double v = (double)val[k];
+    double xv[C];
+    if (k < s) {
+      src_load<C>(x1, (size_t)col[k] * ld + cp, bt1, xv);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc1[c] = tfma(v, xv[c], acc1[c]);
+    } else {
+      src_load<C>(x2, (size_t)col[k] * ld + cp, bt2, xv);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc2[c] = tfma(v, xv[c], acc2[c]);
+    }
+  }
+}
+
+// out = base + sign * A x  for CSR rows (one wave per row).
+// Used for y = K_IG p and for the back-substitution right side b_I - K_IG u_G.
+template <int C, typename VT>
+__global__ void __launch_bounds__(kBlock)
+k_csr_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
+           const VT *__restrict__ val, Src x, int ld,
+           const double *__restrict__ base, double sign, double *__restrict__ out) {
+  int row = blockIdx.x * kWavesPerBlock + wave_id();
+  if (row >= nrows) return;
+  int b = ptr[row], e = ptr[row + 1];
+  for (int cp = 0; cp < ld; cp += C) {
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    csr_row_acc<C, VT>(b, e, col, val, x, ld, cp, acc);
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        size_t o = (size_t)row * ld + cp + c;
+        out[o] = (base ? base[o] : 0.0) + sign * acc[c];
+      }
+    }
+  }
+}
+
+// Dense symmetric interior blocks, one wave per interior row:
+// out_I = base + sign * blockdiag(M_k) y_I.  M_k is K_II^k (residual) or
+// (K_II^k)^{-1} (interior solve).  Row i of a symmetric column-major block
+// is the contiguous column i.  MT: stored type, AT: accumulation type.
+template <int C, typename MT, typename AT>
+__global__ void __launch_bounds__(kBlock)
+k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restrict__ koff,
+             const int *__restrict__ ioff, const int *__restrict__ ni,
+             const int *__restrict__ rowsub, const double *__restrict__ y, int ld,
+             const double *__restrict__ base, double sign, double *__restrict__ out,
+             // optional sparse part (interior residual): out -= K_IG u_G
+             const int *__restrict__ sptr, const int *__restrict__ scol,
+             const double *__restrict__ sval, const double *__restrict__ sx) {
+  int r = blockIdx.x * kWavesPerBlock + wave_id();
+  if (r >= nrows) return;
+  int k = rowsub[r];
+  int i0 = ioff[k];
+  int n = ni[k];
+  const MT *row = blocks + koff[k] + (size_t)(r - i0) * n;
+  const double *yb = y + (size_t)i0 * ld;
+  for (int cp = 0; cp < ld; cp += C) {
+    AT acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = (AT)0;
+    constexpr int U = Unroll<C>::U;
+    int j = lane_id();
+    for (; j + (U - 1) * kWave < n; j += U * kWave) {
+      AT a[U];
+      double yv[U][C];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        a[u] = (AT)row[j + u * kWave];
+        const double *yr = yb + (size_t)(j + u * kWave) * ld + cp;
+#pragma unroll
+        for (int c = 0; c < C; ++c) yv[u][c] = yr[c];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = tfma(a[u], (AT)yv[u][c], acc[c]);
+    }
+    for (; j < n; j += kWave) {
+      AT a = (AT)row[j];
+      const double *yr = yb + (size_t)j * ld + cp;
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = tfma(a, (AT)yr[c], acc[c]);
+    }
+    double sacc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) sacc[c] = 0.0;
+    if (sptr) {
+      Src sxs{sx, nullptr, nullptr, nullptr};
+      csr_row_acc<C, double>(sptr[r], sptr[r + 1], scol, sval, sxs, ld, cp, sacc);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      acc[c] = wave_sum(acc[c]);
+      if (sptr) sacc[c] = wave_sum(sacc[c]);
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        size_t o = (size_t)r * ld + cp + c;
+        out[o] = (base ? base[o] : 0.0) + sign * ((double)acc[c] + sacc[c]);
+      }
+    }
+  }
+}
+
+// Interface rows of [K_GG | K_GI]: per row, entries [ptr, split) are K_GG
+// (columns index p), entries [split, ptr+1) are K_GI (columns index z_I).
+//   out = base + c1 * K_GG p + c2 * K_GI z
+// One wave per row, kGRows rows per workgroup.  With dot != 0 (the CG
+// operator product q = S p), the row's direction entries p_j are stored to
+// pout, the workgroup writes its partial of p^T q (rows summed in order), and
+// the last workgroup computes alpha = rz / (p^T q) for the active columns
+// (CG step length; breakdown when p^T q <= 0).
+constexpr int kGRows = 16;
+template <int C, typename VT>
+__global__ void __launch_bounds__(kGRows * kWave)
+k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
+             const int *__restrict__ col, const VT *__restrict__ val, Src p,
+             const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
+             double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
+             RedBuf red, ColState st) {
+  __shared__ double prod[kGRows * kMaxLd];
+  __shared__ int lflag;
+  const int wv = wave_id(), lane = lane_id();
+  const int j = blockIdx.x * kGRows + wv;
+  const Src zs{z, nullptr, nullptr, nullptr};
+  for (int cp = 0; cp < ld; cp += C) {
+    double a1[C], a2[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) { a1[c] = 0.0; a2[c] = 0.0; }
+    if (j < nrows) {
+      int b = ptr[j], s = split[j], e = ptr[j + 1];
+      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
+      else if (c1 != 0.0) csr_row_acc<C, VT>(b, s, col, val, p, ld, cp, a1);
+      else if (c2 != 0.0) csr_row_acc<C, VT>(s, e, col, val, zs, ld, cp, a2);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      a1[c] = wave_sum(a1[c]);
+      a2[c] = wave_sum(a2[c]);
+    }
+    if (lane == 0) {
+      double bt[C], pj[C];
+      src_beta<C>(p, cp, bt);
+      if (j < nrows && dot) src_load<C>(p, (size_t)j * ld + cp, bt, pj);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        double q = 0.0;
+        if (j < nrows) {
+          size_t o = (size_t)j * ld + cp + c;
+          q = (base ? base[o] : 0.0) + c1 * a1[c] + c2 * a2[c];
+          out[o] = q;
+          if (dot) {
+            if (pout) pout[o] = pj[c];      // this row of the direction, kept for the update
+            q *= pj[c];
+          }
+        }
+        prod[wv * ld + cp + c] = q;
+      }
+    }
+  }
+  if (!dot) return;
+  __syncthreads();
+  for (int c = wv; c < ld; c += kGRows)
+    if (lane == 0) {
+      double s = 0.0;
+      for (int r = 0; r < kGRows; ++r) s += prod[r * ld + c];
+      store_partial(red.part0 + (size_t)blockIdx.x * ld + c, s);
+    }
+  if (!last_block(&red.counter[0], &lflag)) return;
+  for (int c = wv; c < ld; c += kGRows) {
+    double pq = partials_sum(red.part0, gridDim.x, ld, c);
+    if (lane == 0) {
+      double a = 0.0;
+      if (st.active[c]) {
+        if (!(pq > 0.0)) { st.flag[0] = 1; st.active[c] = 0; }
+        else a = st.rz[c] / pq;
+      }
+      st.alpha[c] = a;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) reset_counter(&red.counter[0]);
+}
+
+// ----------------------------------------------------------- CG updates --
+// Chunk of kRowsE interface rows x ld columns per workgroup.
+// mode 0 (init):   x = 0, r given, z = D^{-1} r, p = 0 (so the first
+//                  direction z + 0 * p is z);                 dots: r.z, r.r
+// mode 1 (update): x += a p, r -= a q, z = D^{-1} r (active);  dots: r.z, r.r
+// The last workgroup then updates the column state:
+//   init:   rz = r.z, active = (r.r > stop2) for c < nrhs, iters = 0
+//   update: iters += 1; converged when r.r <= stop2; beta = r.z / rz_old
+// and, when host_nact is given, publishes (number of active columns + 1).
+__global__ void __launch_bounds__(kBlock)
+k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
+            double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
+            double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
+            int use_precond, int *__restrict__ host_nact) {
+  __shared__ double lds[kRowsE * kMaxLd];
+  __shared__ int lflag;
+  const int row0 = blockIdx.x * kRowsE;
+  const int wv = wave_id(), lane = lane_id();
+  // pass 1: element-wise update; products r*z
+  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
+    int lr = e / ld, c = e - lr * ld;
+    int j = row0 + lr;
+    double rz = 0.0;
+    if (j < nrows) {
+      size_t o = (size_t)j * ld + c;
+      double rv = r[o];
+      bool act = mode == 0 ? true : (st.active[c] != 0);
+      if (mode == 1 && act) {
+        double a = st.alpha[c];
+        x[o] = fma(a, p[o], x[o]);
+        rv = fma(-a, q[o], rv);
+        r[o] = rv;
+      }
+      if (mode == 0) x[o] = 0.0;
+      double zv = use_precond ? dinv[j] * rv : rv;
+      if (act) z[o] = zv;
+      else zv = z[o];
+      if (mode == 0) p[o] = 0.0;           // previous direction: none yet (beta = 0)
+      rz = rv * zv;
+    }
+    lds[lr * ld + c] = rz;
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double s = chunk64_sum(lds, ld, c);
+    if (lane == 0) store_partial(red.part0 + (size_t)blockIdx.x * ld + c, s);
+  }
+  __syncthreads();
+  // pass 2: products r*r of the same elements (each thread rereads its own writes)
+  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
+    int lr = e / ld, c = e - lr * ld;
+    int j = row0 + lr;
+    double rr = 0.0;
+    if (j < nrows) { double rv = r[(size_t)j * ld + c]; rr = rv * rv; }
+    lds[lr * ld + c] = rr;
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double s = chunk64_sum(lds, ld, c);
+    if (lane == 0) store_partial(red.part1 + (size_t)blockIdx.x * ld + c, s);
+  }
+  if (!last_block(&red.counter[1], &lflag)) return;
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double rz = partials_sum(red.part0, gridDim.x, ld, c);
+    double rr = partials_sum(red.part1, gridDim.x, ld, c);
+    if (lane == 0) {
+      if (mode == 0) {
+        st.rz[c] = rz;
+        st.iters[c] = 0;
+        st.beta[c] = 0.0;
+        st.active[c] = (c < nrhs && rr > st.stop2[c]) ? 1 : 0;
+      } else if (st.active[c]) {
+        st.iters[c] += 1;
+        st.beta[c] = rz / st.rz[c];
+        st.rz[c] = rz;
+        if (rr <= st.stop2[c]) st.active[c] = 0;
+      }
+      st.nrm2[c] = rr;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int na = 0;
+    for (int c = 0; c < ld; ++c) na += st.active[c];
+    if (st.flag[0]) na = 0;            // breakdown ends the loop
+    if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    reset_counter(&red.counter[1]);
+  }
+}
+
+// stop2[c] = f^2 * v[c]  (v: squared norms)
+__global__ void k_set_stop(int ld, double f2, const double *__restrict__ v, ColState st) {
+  int c = threadIdx.x;
+  if (c < ld) st.stop2[c] = f2 * v[c];
+}
+
+// ------------------------------------------------------- vector helpers --
+// out[i*ld + c] = b[c*ldb + map[i]] for c < nrhs, 0 for padded columns.
+__global__ void k_gather(int n, const int *__restrict__ map, const double *__restrict__ b,
+                         int ldb, int nrhs, int ld, double *__restrict__ out) {
+  size_t total = (size_t)n * ld;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int i = (int)(e / ld), c = (int)(e % ld);
+    out[e] = c < nrhs ? b[(size_t)c * ldb + map[i]] : 0.0;
+  }
+}
+
+// u[c*ldu + map[i]] = in[i*ld + c] for c < nrhs.
+__global__ void k_scatter(int n, const int *__restrict__ map, const double *__restrict__ in,
+                          int ld, int nrhs, double *__restrict__ u, int ldu) {
+  size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e / n), i = (int)(e % n);
+    u[(size_t)c * ldu + map[i]] = in[(size_t)i * ld + c];
+  }
+}
+
+// y[e] += x[e] for the columns whose mask is set (refinement correction).
+__global__ void k_axpy_masked(size_t n, int ld, const double *__restrict__ x,
+                              double *__restrict__ y, const int *__restrict__ mask) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e % ld);
+    if (mask[c]) y[e] += x[e];
+  }
+}
+
+// Fixed-tree column norms: the last workgroup adds sum_rows v^2 into acc[c]
+// (acc zeroed by the host when starting a new norm).
+__global__ void __launch_bounds__(kBlock)
+k_colnorm2(int nrows, int ld, const double *__restrict__ v, RedBuf red, double *acc) {
+  __shared__ double lds[kRowsE * kMaxLd];
+  __shared__ int lflag;
+  const int row0 = blockIdx.x * kRowsE;
+  const int wv = wave_id(), lane = lane_id();
+  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
+    int lr = e / ld, c = e - lr * ld;
+    int j = row0 + lr;
+    double t = 0.0;
+    if (j < nrows) { double a = v[(size_t)j * ld + c]; t = a * a; }
+    lds[lr * ld + c] = t;
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double s = chunk64_sum(lds, ld, c);
+    if (lane == 0) store_partial(red.part0 + (size_t)blockIdx.x * ld + c, s);
+  }
+  if (!last_block(&red.counter[2], &lflag)) return;
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double s = partials_sum(red.part0, gridDim.x, ld, c);
+    if (lane == 0) acc[c] += s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) reset_counter(&red.counter[2]);
+}
+
+// ------------------------------------------------------------- factor --
+// Batched dense Cholesky, one workgroup per subdomain, in place on the
+// column-major block (lower triangle), right-looking with 16-wide panels:
+//   1. factor the 16x16 diagonal block (one wave, LDS),
+//   2. panel solve L21 = A21 L11^{-T} (one thread per row),
+//   3. trailing update A22 -= L21 L21^T on 16x16 tiles with MFMA
+//      (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32) or vector FMA.
+// status[k] receives 1 + the column of the first non-positive pivot.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma16x16x4(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { typedef dbl4 type; };
+template <> struct Vec4<float> { typedef flt4 type; };
+// Row of accumulator register r held by lane group g = lane/16 (column lane%16).
+// A and B operands: lane l holds A[l%16][l/16] and B[l/16][l%16] for both.
+// Output: f32 16x16x4 keeps four consecutive rows per lane group,
+// f64 16x16x4 interleaves them (rows g, g+4, g+8, g+12), as measured on gfx950.
+__device__ __forceinline__ int acc_row(double, int g, int r) { return g + 4 * r; }
+__device__ __forceinline__ int acc_row(float, int g, int r) { return 4 * g + r; }
+
+constexpr int kNB = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_potrf(T *__restrict__ blocks, const long long *__restrict__ koff, const int *__restrict__ ni,
+        int *__restrict__ status, int use_mfma) {
+  __shared__ T D[kNB][kNB + 1];
+  const int k = blockIdx.x;
+  const int n = ni[k];
+  T *A = blocks + koff[k];
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  int fail = 0;
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int kb = min(kNB, n - k0);
+    // 1. diagonal block
+    for (int e = tid; e < kNB * kNB; e += kBlock) {
+      int i = e % kNB, j = e / kNB;
+      D[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + j) * n + k0 + i] : T(0);
+    }
+    __syncthreads();
+    if (wv == 0) {
+      for (int j = 0; j < kb; ++j) {
+        T d = D[j][j];
+        if (!(d > T(0))) {
+          if (lane == 0 && fail == 0) fail = k0 + j + 1;
+          d = T(1);
+        }
+        T piv = sqrt(d);
+        if (lane == 0) D[j][j] = piv;
+        if (lane > j && lane < kb) D[lane][j] = D[lane][j] / piv;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        // rank-1 update of the remaining lower part of the block
+        for (int e = lane; e < kNB * kNB; e += kWave) {
+          int i = e % kNB, l = e / kNB;
+          if (l > j && i >= l && i < kb) D[i][l] -= D[i][j] * D[l][j];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < kNB * kNB; e += kBlock) {
+      int i = e % kNB, j = e / kNB;
+      if (i < kb && j < kb && i >= j) A[(size_t)(k0 + j) * n + k0 + i] = D[i][j];
+    }
+    // 2. panel: rows below the block
+    for (int i = k0 + kb + tid; i < n; i += kBlock) {
+      T xr[kNB];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j) {
+        if (j < kb) {
+          T a = A[(size_t)(k0 + j) * n + i];
+          for (int q = 0; q < j; ++q) a -= xr[q] * D[j][q];
+          xr[j] = a / D[j][j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kNB; ++j)
+        if (j < kb) A[(size_t)(k0 + j) * n + i] = xr[j];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // 3. trailing update on 16x16 tiles of the lower triangle
+    const int t0 = k0 + kb;
+    const int m = n - t0;
+    if (m > 0) {
+      const int T16 = (m + 15) / 16;
+      const int ntiles = T16 * (T16 + 1) / 2;
+      for (int t = wv; t < ntiles; t += kWavesPerBlock) {
+        // tile (ti, tj), tj <= ti, enumerated row by row
+        int ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+        while (ti * (ti + 1) / 2 > t) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        int tj = t - ti * (ti + 1) / 2;
+        int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+        int ci = lane % 16, rq = lane / 16;           // fragment coordinates
+        typename Vec4<T>::type acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+          acc[r] = (i < n && j < n) ? A[(size_t)j * n + i] : T(0);
+        }
+        if (use_mfma) {
+#pragma unroll
+          for (int kk = 0; kk < kNB; kk += 4) {
+            int q = kk + rq;
+            int ia = i0 + ci, jb = j0 + ci;
+            T a = (q < kb && ia < n) ? -A[(size_t)(k0 + q) * n + ia] : T(0);
+            T b = (q < kb && jb < n) ? A[(size_t)(k0 + q) * n + jb] : T(0);
+            acc = mfma16x16x4(a, b, acc);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+            if (i < n && j < n) {
+              T s = acc[r];
+              for (int q = 0; q < kb; ++q)
+                s -= A[(size_t)(k0 + q) * n + i] * A[(size_t)(k0 + q) * n + j];
+              acc[r] = s;
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+          if (i < n && j < n && i >= j) A[(size_t)j * n + i] = acc[r];
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (wv == 0 && lane == 0) status[k] = fail;
+}
+
+// Blocked triangular solves with the factor of one subdomain, applied to an
+// n x ncol block B (element (i,t) at B[i*rs + t*cs]), in place:
+//   forward  L X = B, then backward  L^T Y = X   (Y = K_II^{-1} B).
+// 16-row blocks: the diagonal triangle is solved per column by one thread,
+// the rows beyond it are updated in parallel.
+template <typename LT, typename BT, typename AT>
+__device__ void trsm_llt(const LT *__restrict__ L, int n, BT *B, int rs, int cs, int ncol) {
+  // forward
+  for (int jb = 0; jb < n; jb += kNB) {
+    int nb = min(kNB, n - jb);
+    for (int t = threadIdx.x; t < ncol; t += kBlock) {
+      for (int r = 0; r < nb; ++r) {
+        int i = jb + r;
+        AT s = (AT)B[(size_t)i * rs + (size_t)t * cs];
+        for (int q = 0; q < r; ++q)
+          s -= (AT)L[(size_t)(jb + q) * n + i] * (AT)B[(size_t)(jb + q) * rs + (size_t)t * cs];
+        B[(size_t)i * rs + (size_t)t * cs] = (BT)(s / (AT)L[(size_t)i * n + i]);
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    int rem = n - (jb + nb);
+    for (int e = threadIdx.x; e < rem * ncol; e += kBlock) {
+      int i = jb + nb + e / ncol, t = e % ncol;
+      AT s = (AT)B[(size_t)i * rs + (size_t)t * cs];
+      for (int q = 0; q < nb; ++q)
+        s -= (AT)L[(size_t)(jb + q) * n + i] * (AT)B[(size_t)(jb + q) * rs + (size_t)t * cs];
+      B[(size_t)i * rs + (size_t)t * cs] = (BT)s;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // backward
+  int last = ((n - 1) / kNB) * kNB;
+  for (int jb = last; jb >= 0; jb -= kNB) {
+    int nb = min(kNB, n - jb);
+    for (int t = threadIdx.x; t < ncol; t += kBlock) {
+      for (int r = nb - 1; r >= 0; --r) {
+        int i = jb + r;
+        AT s = (AT)B[(size_t)i * rs + (size_t)t * cs];
+        for (int q = r + 1; q < nb; ++q)
+          s -= (AT)L[(size_t)i * n + jb + q] * (AT)B[(size_t)(jb + q) * rs + (size_t)t * cs];
+        B[(size_t)i * rs + (size_t)t * cs] = (BT)(s / (AT)L[(size_t)i * n + i]);
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int e = threadIdx.x; e < jb * ncol; e += kBlock) {
+      int i = e / ncol, t = e % ncol;
+      AT s = (AT)B[(size_t)i * rs + (size_t)t * cs];
+      const LT *Lc = L + (size_t)i * n + jb;   // L[jb+q][i], q < nb: contiguous
+      for (int q = 0; q < nb; ++q) s -= (AT)Lc[q] * (AT)B[(size_t)(jb + q) * rs + (size_t)t * cs];
+      B[(size_t)i * rs + (size_t)t * cs] = (BT)s;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// K_II^{-1} from the factor, 16 columns of the identity per workgroup:
+// grid (n_sub, column chunks).
+constexpr int kInvCols = 16;
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_inverse(const T *__restrict__ L, T *__restrict__ Kinv, const long long *__restrict__ koff,
+          const int *__restrict__ ni) {
+  const int k = blockIdx.x;
+  const int n = ni[k];
+  const int c0 = blockIdx.y * kInvCols;
+  if (c0 >= n) return;
+  const int ncol = min(kInvCols, n - c0);
+  T *B = Kinv + koff[k] + (size_t)c0 * n;   // columns c0.. of the column-major block
+  for (int e = threadIdx.x; e < n * ncol; e += kBlock) {
+    int i = e % n, t = e / n;
+    B[(size_t)t * n + i] = (i == c0 + t) ? T(1) : T(0);
+  }
+  __threadfence_block();
+  __syncthreads();
+  trsm_llt<T, T, T>(L + koff[k], n, B, 1, n, ncol);
+}
+
+// Make every block exactly symmetric: M = (M + M^T) / 2.
+template <typename T>
+__global__ void k_symmetrize(T *__restrict__ M, const long long *__restrict__ koff,
+                             const int *__restrict__ ni) {
+  const int k = blockIdx.x;
+  const int n = ni[k];
+  T *A = M + koff[k];
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < n * n; e += gridDim.y * blockDim.x) {
+    int i = e % n, j = e / n;
+    if (i > j) {
+      T a = A[(size_t)j * n + i], b = A[(size_t)i * n + j];
+      T m = (a + b) * T(0.5);
+      A[(size_t)j * n + i] = m;
+      A[(size_t)i * n + j] = m;
+    }
+  }
+}
+
+// Per-iteration interior solves by triangular sweeps (variant TRSM):
+// z_I^k = L_k^{-T} L_k^{-1} y_I^k for all columns; grid (n_sub, ld / ncolw).
+template <typename T, typename AT>
+__global__ void __launch_bounds__(kBlock)
+k_trsm_apply(const T *__restrict__ L, const long long *__restrict__ koff,
+             const int *__restrict__ ioff, const int *__restrict__ ni,
+             const double *__restrict__ y, double *__restrict__ z, int ld, int ncolw) {
+  const int k = blockIdx.x;
+  const int n = ni[k];
+  const int c0 = blockIdx.y * ncolw;
+  const size_t base = (size_t)ioff[k] * ld + c0;
+  for (int e = threadIdx.x; e < n * ncolw; e += kBlock) {
+    int i = e / ncolw, t = e % ncolw;
+    z[base + (size_t)i * ld + t] = y[base + (size_t)i * ld + t];
+  }
+  __threadfence_block();
+  __syncthreads();
+  trsm_llt<T, double, AT>(L + koff[k], n, z + base, ld, 1, ncolw);
+}
+
+// Exact diagonal of S (Jacobi preconditioner), one wave per interface row j:
+//   d_j = (K_GG)_jj - sum_{a,b in row j of K_GI, same subdomain} v_a v_b (K_II^k)^{-1}_{ab}
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_schur_diag(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
+             const int *__restrict__ col, const double *__restrict__ val,
+             const T *__restrict__ Kinv, const long long *__restrict__ koff,
+             const int *__restrict__ ioff, const int *__restrict__ ni,
+             const int *__restrict__ rowsub, double *__restrict__ diag,
+             double *__restrict__ dinv, int *__restrict__ bad) {
+  int j = blockIdx.x * kWavesPerBlock + wave_id();
+  if (j >= nrows) return;
+  int b = ptr[j], s = split[j], e = ptr[j + 1];
+  double kjj = 0.0;
+  for (int a = b + lane_id(); a < s; a += kWave)
+    if (col[a] == j) kjj += val[a];
+  kjj = wave_sum(kjj);
+  double acc = 0.0;
+  for (int a = s + lane_id(); a < e; a += kWave) {
+    int ia = col[a];
+    int k = rowsub[ia];
+    int n = ni[k];
+    const T *row = Kinv + koff[k] + (size_t)(ia - ioff[k]) * n;
+    double t = 0.0;
+    for (int b2 = s; b2 < e; ++b2) {
+      int ib = col[b2];
+      if (rowsub[ib] == k) t += (double)row[ib - ioff[k]] * val[b2];
+    }
+    acc += val[a] * t;
+  }
+  acc = wave_sum(acc);
+  if (lane_id() == 0) {
+    double d = kjj - acc;
+    diag[j] = d;
+    if (!(d > 0.0)) { *bad = j + 1; d = 1.0; }
+    dinv[j] = 1.0 / d;
+  }
+}
+
+// FP64 -> FP32 copy (mixed-precision operators).
+__global__ void k_to_f32(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    b[e] = (float)a[e];
+}
+
+template <typename T>
+__global__ void k_copy(size_t n, const T *__restrict__ a, T *__restrict__ b) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    b[e] = a[e];
+}
+
+}  // namespace dd

@@ -1,0 +1,987 @@
+// Host side of the substructuring Schur-complement solver: validation and
+// deep copy of the partitioned system, the batched factorisation, and the
+// solve pipeline (condensation, preconditioned CG on the interface Schur
+// complement, back substitution, mixed-precision refinement), exported
+// through the C ABI declared in include/dd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+#include "dd_kernels.h"
+
+using namespace dd;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Operators of one precision.
+struct Ops {
+  void *L = nullptr;       // factor blocks (T)
+  void *kinv = nullptr;    // inverse blocks (T), exactly symmetric
+  void *ig_val = nullptr;  // K_IG values (T)
+  void *g_val = nullptr;   // [K_GG | K_GI] values (T)
+  double *diag = nullptr;  // diag(S)
+  double *dinv = nullptr;  // 1 / diag(S)
+  bool ready = false;
+};
+
+// Per-column solver state in one allocation, so one copy brings it to the host.
+struct StateBlock {
+  double rz[kMaxLd], alpha[kMaxLd], beta[kMaxLd], stop2[kMaxLd], nrm2[kMaxLd];
+  double bnrm2[kMaxLd], rnrm2[kMaxLd];
+  int active[kMaxLd], iters[kMaxLd], flag[kMaxLd];
+};
+
+struct Work {
+  // interface (n_gamma x ldmax)
+  double *bG, *xG, *rG, *zG, *pG, *qG, *uG, *dG, *tG;
+  // interior (NI x ldmax)
+  double *bI, *yI, *wI, *uI, *dI, *tI;
+  double *bnrm2, *rnrm2;   // ldmax
+};
+
+}  // namespace
+
+struct dd_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_dof = 0, n_gamma = 0, n_sub = 0, NI = 0, max_nrhs = 0, ldmax = 1, max_ni = 0;
+  std::vector<int> ni, ioff;
+  std::vector<long long> koff;
+  long long ktot = 0;
+  size_t nnz_ig = 0, nnz_g = 0;
+  // structure
+  int *d_ni = nullptr, *d_ioff = nullptr, *d_rowsub = nullptr, *d_imap = nullptr,
+      *d_gmap = nullptr;
+  long long *d_koff = nullptr;
+  int *d_ig_ptr = nullptr, *d_ig_col = nullptr;
+  int *d_g_ptr = nullptr, *d_g_split = nullptr, *d_g_col = nullptr;
+  double *d_ig_val64 = nullptr, *d_g_val64 = nullptr, *d_kii64 = nullptr;
+  Ops op[2];
+  Work w{};
+  ColState st{};
+  StateBlock *d_state = nullptr;
+  RedBuf red{};
+  int *d_status = nullptr, *d_bad = nullptr;
+  size_t max_chunks = 0;
+  // host polling
+  int *h_nact = nullptr;          // pinned, mapped
+  int *h_nact_dev = nullptr;
+  int nslots = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  int use_mfma = 1;
+  // optional per-phase kernel timing with HIP events (dd_set_timing)
+  unsigned timing_mask = 0;
+  std::vector<hipEvent_t> tev;          // event pool, pairs (start, stop)
+  std::vector<int> tev_phase;           // phase of each recorded pair
+  size_t tev_used = 0;
+  double t_ms[DD_NPHASES] = {0};
+  long long t_count[DD_NPHASES] = {0};
+  std::string err;
+};
+
+namespace {
+
+dd_status fail(dd_ctx *c, dd_status s, const std::string &m) {
+  if (c) c->err = m; else g_setup_error = m;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail((ctx), DD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_) + \
+                                      " (" + std::to_string((int)e_) + ")");       \
+  } while (0)
+
+template <typename T>
+dd_status dalloc(dd_ctx *c, T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) return fail(c, DD_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  c->allocs.push_back(q);
+  c->bytes += n * sizeof(T);
+  *p = (T *)q;
+  return DD_OK;
+}
+
+template <typename T>
+dd_status upload(dd_ctx *c, T **p, const T *h, size_t n) {
+  dd_status s = dalloc(c, p, n);
+  if (s != DD_OK) return s;
+  if (n) HIPCHK(c, hipMemcpy(*p, h, n * sizeof(T), hipMemcpyHostToDevice));
+  return DD_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    dd_status s_ = (expr);         \
+    if (s_ != DD_OK) return s_;    \
+  } while (0)
+
+unsigned grid_for(size_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
+
+// --------------------------------------------------------------- validation --
+dd_status validate(const dd_problem *p) {
+  if (!p) return fail(nullptr, DD_EINVAL, "problem is NULL");
+  if (p->n_dof < 1) return fail(nullptr, DD_EINVAL, "n_dof < 1");
+  if (p->n_gamma < 0 || p->n_gamma > p->n_dof) return fail(nullptr, DD_EINVAL, "n_gamma out of range");
+  if (p->n_sub < 1 || !p->sub) return fail(nullptr, DD_EINVAL, "n_sub < 1 or sub is NULL");
+  if (p->n_gamma > 0 && (!p->gamma_map || !p->kgg_rowptr))
+    return fail(nullptr, DD_EINVAL, "gamma_map / kgg_rowptr is NULL");
+  std::vector<int> seen(p->n_dof, 0);
+  for (int j = 0; j < p->n_gamma; ++j) {
+    int g = p->gamma_map[j];
+    if (g < 0 || g >= p->n_dof) return fail(nullptr, DD_EINVAL, "gamma_map entry out of range");
+    if (seen[g]++) return fail(nullptr, DD_EINVAL, "gamma_map not injective");
+  }
+  if (p->n_gamma > 0) {
+    if (p->kgg_rowptr[0] != 0) return fail(nullptr, DD_EINVAL, "kgg_rowptr[0] != 0");
+    for (int j = 0; j < p->n_gamma; ++j) {
+      if (p->kgg_rowptr[j + 1] < p->kgg_rowptr[j]) return fail(nullptr, DD_EINVAL, "kgg_rowptr not monotone");
+      for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a)
+        if (p->kgg_col[a] < 0 || p->kgg_col[a] >= p->n_gamma)
+          return fail(nullptr, DD_EINVAL, "kgg_col out of range");
+    }
+  }
+  for (int k = 0; k < p->n_sub; ++k) {
+    const dd_subdomain &s = p->sub[k];
+    std::string tag = "subdomain " + std::to_string(k) + ": ";
+    if (s.n_i < 1) return fail(nullptr, DD_EINVAL, tag + "n_i < 1");
+    if (s.n_g < 0 || s.n_g > p->n_gamma) return fail(nullptr, DD_EINVAL, tag + "n_g out of range");
+    if (!s.k_ii || !s.i_map || !s.kig_rowptr) return fail(nullptr, DD_EINVAL, tag + "NULL array");
+    std::vector<char> gs(p->n_gamma, 0);
+    for (int g = 0; g < s.n_g; ++g) {
+      int v = s.g_map[g];
+      if (v < 0 || v >= p->n_gamma) return fail(nullptr, DD_EINVAL, tag + "g_map entry out of range");
+      if (gs[v]++) return fail(nullptr, DD_EINVAL, tag + "g_map not injective");
+    }
+    for (int i = 0; i < s.n_i; ++i) {
+      int g = s.i_map[i];
+      if (g < 0 || g >= p->n_dof) return fail(nullptr, DD_EINVAL, tag + "i_map entry out of range");
+      if (seen[g]++) return fail(nullptr, DD_EINVAL, tag + "dof " + std::to_string(g) + " assigned twice");
+    }
+    if (s.kig_rowptr[0] != 0) return fail(nullptr, DD_EINVAL, tag + "kig_rowptr[0] != 0");
+    for (int i = 0; i < s.n_i; ++i) {
+      if (s.kig_rowptr[i + 1] < s.kig_rowptr[i]) return fail(nullptr, DD_EINVAL, tag + "kig_rowptr not monotone");
+      for (int a = s.kig_rowptr[i]; a < s.kig_rowptr[i + 1]; ++a)
+        if (s.kig_col[a] < 0 || s.kig_col[a] >= s.n_g) return fail(nullptr, DD_EINVAL, tag + "kig_col out of range");
+    }
+    for (int j = 0; j < s.n_i; ++j)
+      for (int i = 0; i < s.n_i; ++i)
+        if (!std::isfinite(s.k_ii[(size_t)j * s.n_i + i]))
+          return fail(nullptr, DD_EINVAL, tag + "k_ii has a non-finite entry");
+  }
+  for (int g = 0; g < p->n_dof; ++g)
+    if (!seen[g]) return fail(nullptr, DD_EINVAL, "dof " + std::to_string(g) + " is neither interior nor interface");
+  return DD_OK;
+}
+
+size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
+  size_t NI = 0, kt = 0, nig = 0;
+  for (int k = 0; k < p->n_sub; ++k) {
+    NI += p->sub[k].n_i;
+    kt += (size_t)p->sub[k].n_i * p->sub[k].n_i;
+    nig += p->sub[k].kig_rowptr[p->sub[k].n_i];
+  }
+  size_t ngg = p->n_gamma ? (size_t)p->kgg_rowptr[p->n_gamma] : 0;
+  size_t ld = next_pow2(std::max(1, max_nrhs));
+  size_t b = 0;
+  b += NI * 4 * 3 + p->n_gamma * 4 + p->n_sub * 16;                 // maps
+  b += (NI + 1) * 4 + nig * 12 + (p->n_gamma + 1) * 8 + (ngg + nig) * 12;  // CSR (FP64)
+  b += kt * 8;                                                        // K_II
+  size_t s = prec == DD_MIXED ? 4 : 8;
+  b += 2 * kt * s + p->n_gamma * 16;                                  // L, K^-1, diag
+  if (prec == DD_MIXED) b += (nig + ngg + nig) * 4;                   // FP32 values
+  b += (9 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                    // work vectors
+  size_t chunks = std::max<size_t>((p->n_gamma + kGRows - 1) / kGRows,
+                                   (std::max<size_t>(p->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
+  b += 2 * chunks * kMaxLd * 8;
+  return b;
+}
+
+// ------------------------------------------------------------ launchers --
+template <int C, typename VT>
+void launch_csr(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *val,
+                Src x, int ld, const double *base, double sign, double *out) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL((k_csr_rows<C, VT>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
+                     c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
+}
+
+template <typename VT>
+void csr_rows(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *val,
+              Src x, int ld, const double *base, double sign, double *out) {
+  switch (std::min(ld, 16)) {
+    case 1: launch_csr<1, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+    case 2: launch_csr<2, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+    case 4: launch_csr<4, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+    case 8: launch_csr<8, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+    default: launch_csr<16, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+  }
+}
+
+template <int C, typename MT, typename AT>
+void launch_dense(dd_ctx *c, const MT *blocks, const double *y, int ld, const double *base,
+                  double sign, double *out, const int *sptr, const int *scol, const double *sval,
+                  const double *sx) {
+  if (c->NI <= 0) return;
+  hipLaunchKernelGGL((k_dense_rows<C, MT, AT>), dim3(grid_for(c->NI, kWavesPerBlock)),
+                     dim3(kBlock), 0, c->stream, c->NI, blocks, c->d_koff, c->d_ioff, c->d_ni,
+                     c->d_rowsub, y, ld, base, sign, out, sptr, scol, sval, sx);
+}
+
+template <typename MT, typename AT>
+void dense_rows(dd_ctx *c, const MT *blocks, const double *y, int ld, const double *base,
+                double sign, double *out, const int *sptr = nullptr, const int *scol = nullptr,
+                const double *sval = nullptr, const double *sx = nullptr) {
+  switch (std::min(ld, 16)) {
+    case 1: launch_dense<1, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+    case 2: launch_dense<2, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+    case 4: launch_dense<4, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+    case 8: launch_dense<8, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+    default: launch_dense<16, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+  }
+}
+
+template <int C, typename VT>
+void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
+                  const double *base, double c1, double c2, double *out, int dot, double *pout) {
+  if (c->n_gamma <= 0) return;
+  hipLaunchKernelGGL((k_gamma_rows<C, VT>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
+                     c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
+                     base, c1, c2, out, dot, pout, c->red, c->st);
+}
+
+template <typename VT>
+void gamma_rows(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
+                const double *base, double c1, double c2, double *out, int dot, double *pout) {
+  switch (std::min(ld, 16)) {
+    case 1: launch_gamma<1, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    case 2: launch_gamma<2, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    case 4: launch_gamma<4, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    case 8: launch_gamma<8, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    default: launch_gamma<16, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+  }
+}
+
+Src plain(const double *x) { return Src{x, nullptr, nullptr, nullptr}; }
+
+void colnorm2(dd_ctx *c, int nrows, int ld, const double *v, double *acc) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_colnorm2, dim3(grid_for(nrows, kRowsE)), dim3(kBlock), 0, c->stream,
+                     nrows, ld, v, c->red, acc);
+}
+
+// squared column norms of a DD-layout vector pair (interior, interface)
+dd_status dd_norm2(dd_ctx *c, int ld, const double *vI, const double *vG, double *acc) {
+  HIPCHK(c, hipMemsetAsync(acc, 0, kMaxLd * sizeof(double), c->stream));
+  colnorm2(c, c->NI, ld, vI, acc);
+  colnorm2(c, c->n_gamma, ld, vG, acc);
+  return DD_OK;
+}
+
+// z_I = (K_II)^{-1} y_I with the operators of precision `prec`.
+void interior_solve(dd_ctx *c, int prec, int apply, const double *y, double *z, int ld) {
+  if (apply == DD_APPLY_TRSM) {
+    int ncolw = std::min(ld, 16);
+    dim3 grid(c->n_sub, ld / ncolw);
+    if (prec == DD_FP64)
+      hipLaunchKernelGGL((k_trsm_apply<double, double>), grid, dim3(kBlock), 0, c->stream,
+                         (const double *)c->op[0].L, c->d_koff, c->d_ioff, c->d_ni, y, z, ld, ncolw);
+    else
+      hipLaunchKernelGGL((k_trsm_apply<float, float>), grid, dim3(kBlock), 0, c->stream,
+                         (const float *)c->op[1].L, c->d_koff, c->d_ioff, c->d_ni, y, z, ld, ncolw);
+    return;
+  }
+  if (prec == DD_FP64)
+    dense_rows<double, double>(c, (const double *)c->op[0].kinv, y, ld, nullptr, 1.0, z);
+  else
+    dense_rows<float, float>(c, (const float *)c->op[1].kinv, y, ld, nullptr, 1.0, z);
+}
+
+// y = K_IG x (+ base, sign) with the coupling values of `prec`.
+void kig_apply(dd_ctx *c, int prec, Src x, int ld, const double *base, double sign,
+               double *out) {
+  if (prec == DD_FP64)
+    csr_rows<double>(c, c->NI, c->d_ig_ptr, c->d_ig_col, (const double *)c->op[0].ig_val, x, ld,
+                     base, sign, out);
+  else
+    csr_rows<float>(c, c->NI, c->d_ig_ptr, c->d_ig_col, (const float *)c->op[1].ig_val, x, ld,
+                    base, sign, out);
+}
+
+void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const double *base,
+                 double c1, double c2, double *out, int dot = 0, double *pout = nullptr) {
+  if (prec == DD_FP64)
+    gamma_rows<double>(c, (const double *)c->op[0].g_val, p, z, ld, base, c1, c2, out, dot, pout);
+  else
+    gamma_rows<float>(c, (const float *)c->op[1].g_val, p, z, ld, base, c1, c2, out, dot, pout);
+}
+
+// ---------------------------------------------------------------- factor --
+template <typename T>
+dd_status factor_impl(dd_ctx *c, int pi) {
+  Ops &o = c->op[pi];
+  T *L = (T *)o.L, *Kinv = (T *)o.kinv;
+  // copy (and convert) K_II into the factor buffer
+  size_t n = (size_t)c->ktot;
+  if (pi == DD_FP64)
+    hipLaunchKernelGGL((k_copy<double>), dim3(1024), dim3(256), 0, c->stream, n, c->d_kii64, (double *)L);
+  else
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, n, c->d_kii64, (float *)L);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL((k_potrf<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
+                     c->d_ni, c->d_status, c->use_mfma);
+  HIPCHK(c, hipGetLastError());
+  std::vector<int> status(c->n_sub);
+  HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->n_sub; ++k)
+    if (status[k])
+      return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
+                                     std::to_string(status[k] - 1));
+  dim3 ginv(c->n_sub, (c->max_ni + kInvCols - 1) / kInvCols);
+  hipLaunchKernelGGL((k_inverse<T>), ginv, dim3(kBlock), 0, c->stream, (const T *)L, Kinv,
+                     c->d_koff, c->d_ni);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL((k_symmetrize<T>), dim3(c->n_sub, 64), dim3(256), 0, c->stream, Kinv,
+                     c->d_koff, c->d_ni);
+  HIPCHK(c, hipGetLastError());
+  if (pi == DD_MIXED) {
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_ig, c->d_ig_val64,
+                       (float *)o.ig_val);
+    hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_g, c->d_g_val64,
+                       (float *)o.g_val);
+    HIPCHK(c, hipGetLastError());
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream));
+  if (c->n_gamma > 0)
+    hipLaunchKernelGGL((k_schur_diag<T>), dim3(grid_for(c->n_gamma, kWavesPerBlock)), dim3(kBlock),
+                       0, c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col,
+                       c->d_g_val64, (const T *)Kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub,
+                       o.diag, o.dinv, c->d_bad);
+  HIPCHK(c, hipGetLastError());
+  int bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad)
+    return fail(c, DD_ENOTSPD, "diag(S) not positive at interface row " + std::to_string(bad - 1));
+  o.ready = true;
+  return DD_OK;
+}
+
+dd_status ensure_ops(dd_ctx *c, int pi) {
+  Ops &o = c->op[pi];
+  if (o.L) return DD_OK;
+  size_t s = pi == DD_FP64 ? 8 : 4;
+  void *p;
+  auto al = [&](void **dst, size_t bytes) -> dd_status {
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 1));
+    if (e != hipSuccess) return fail(c, DD_ENOMEM, "hipMalloc of factor storage failed");
+    c->allocs.push_back(p);
+    c->bytes += bytes;
+    *dst = p;
+    return DD_OK;
+  };
+  TRY(al(&o.L, c->ktot * s));
+  TRY(al(&o.kinv, c->ktot * s));
+  TRY(al((void **)&o.diag, c->n_gamma * 8));
+  TRY(al((void **)&o.dinv, c->n_gamma * 8));
+  if (pi == DD_FP64) {
+    o.ig_val = c->d_ig_val64;
+    o.g_val = c->d_g_val64;
+  } else {
+    TRY(al(&o.ig_val, c->nnz_ig * 4));
+    TRY(al(&o.g_val, c->nnz_g * 4));
+  }
+  return DD_OK;
+}
+
+// ----------------------------------------------------------- phase timing --
+struct PhaseTimer {
+  dd_ctx *c;
+  int phase;
+  bool on;
+  PhaseTimer(dd_ctx *c_, int ph) : c(c_), phase(ph), on((c_->timing_mask >> ph) & 1u) {
+    if (!on) return;
+    if (c->tev_used + 2 > c->tev.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+        c->tev.push_back(e);
+      }
+      c->tev_phase.resize(c->tev.size() / 2, 0);
+    }
+    (void)hipEventRecord(c->tev[c->tev_used], c->stream);
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    (void)hipEventRecord(c->tev[c->tev_used + 1], c->stream);
+    c->tev_phase[c->tev_used / 2] = phase;
+    c->tev_used += 2;
+  }
+};
+
+// Accumulate the recorded pairs (the stream must be idle).
+void collect_timing(dd_ctx *c) {
+  for (size_t i = 0; i + 1 < c->tev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->tev[i], c->tev[i + 1]) == hipSuccess) {
+      c->t_ms[c->tev_phase[i / 2]] += ms;
+      c->t_count[c->tev_phase[i / 2]] += 1;
+    }
+  }
+  c->tev_used = 0;
+}
+
+// ------------------------------------------------------------------ solve --
+struct CoreOpts {
+  int max_it;
+  int precond;
+  int apply;
+  int check_every;
+};
+
+// One substructuring solve on DD-layout data:
+//   g = bG - K_GI K_II^{-1} bI;  CG on S x = g until ||r_c||^2 <= stop2[c];
+//   uI = K_II^{-1} (bI - K_IG x);  uG = x.
+// stop2 must be set on the device before the call.  iters[c] and active[c]
+// are left in the column state.
+dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, double *uI,
+                     double *uG, int ld, int nrhs, const CoreOpts &o) {
+  Work &w = c->w;
+  const Ops &op = c->op[prec];
+  HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
+  // condensation (eq. subForcing summed over subdomains): r = bG - K_GI K_II^{-1} bI
+  interior_solve(c, prec, o.apply, bI, w.wI, ld);
+  gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
+  // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
+  double *pA = w.pG, *pB = w.xG;
+  unsigned ge = c->n_gamma > 0 ? grid_for(c->n_gamma, kRowsE) : 0;
+  if (c->n_gamma > 0)
+    hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 0, c->n_gamma, ld, nrhs,
+                       op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr);
+  HIPCHK(c, hipGetLastError());
+  // host polling with a lag: iteration `it` writes h_nact[it % nslots] = active + 1
+  const int lag = std::min(8, std::max(1, o.check_every > 0 ? o.check_every : 2));
+  std::vector<int> ring_it(c->nslots, -1);
+  int it = 0;
+  int observed = 0;       // last iteration whose result the host has seen
+  bool stop = c->n_gamma == 0;
+  while (!stop && it < o.max_it) {
+    ++it;
+    // direction p = z + beta p_prev, formed where it is gathered
+    Src P{nullptr, w.zG, pA, c->st.beta};
+    // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
+    {
+      PhaseTimer t(c, DD_PHASE_KIG);
+      kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI);
+    }
+    {
+      PhaseTimer t(c, DD_PHASE_INTERIOR);
+      interior_solve(c, prec, o.apply, w.yI, w.wI, ld);
+    }
+    {
+      PhaseTimer t(c, DD_PHASE_GAMMA);
+      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, pB);
+    }
+    int slot = it % c->nslots;
+    c->h_nact[slot] = 0;
+    {
+      PhaseTimer t(c, DD_PHASE_UPDATE);
+      hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
+                         op.dinv, uG, w.rG, w.zG, pB, w.qG, c->red, c->st, o.precond,
+                         c->h_nact_dev + slot);
+    }
+    std::swap(pA, pB);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
+    ring_it[slot] = it;
+    // look at iteration it - lag (blocking), never more than nslots in flight
+    int target = it - lag;
+    while (observed < target) {
+      int s2 = (observed + 1) % c->nslots;
+      HIPCHK(c, hipEventSynchronize(c->ev[s2]));
+      ++observed;
+      int v = ((volatile int *)c->h_nact)[s2];
+      if (v == 1) { stop = true; break; }
+    }
+  }
+  // back substitution (eq. backwardSubstitution): uI = K_II^{-1} (bI - K_IG uG)
+  kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
+  interior_solve(c, prec, o.apply, w.yI, uI, ld);
+  HIPCHK(c, hipGetLastError());
+  return DD_OK;
+}
+
+dd_status fetch_state(dd_ctx *c, StateBlock *h) {
+  HIPCHK(c, hipMemcpyAsync(h, c->d_state, sizeof(StateBlock), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->tev_used) collect_timing(c);
+  if (h->flag[0]) return fail(c, DD_ENOTSPD, "CG breakdown: p^T S p <= 0");
+  return DD_OK;
+}
+
+// FP64 full-system residual in DD layout: rI = bI - K_II uI - K_IG uG,
+// rG = bG - K_GI uI - K_GG uG.
+void full_residual(dd_ctx *c, const double *bI, const double *bG, const double *uI,
+                   const double *uG, double *rI, double *rG, int ld) {
+  dense_rows<double, double>(c, c->d_kii64, uI, ld, bI, -1.0, rI, c->d_ig_ptr, c->d_ig_col,
+                             c->d_ig_val64, uG);
+  gamma_rows<double>(c, c->d_g_val64, plain(uG), uI, ld, bG, -1.0, -1.0, rG, 0, nullptr);
+}
+
+}  // namespace
+
+// =================================================================== C ABI ==
+extern "C" {
+
+void dd_default_opts(dd_solve_opts *o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->max_it = 1000;
+  o->precond = 1;
+  o->max_refine = 8;
+  o->inner_tol = 1e-4;
+  o->fp64_fallback = 1;
+  o->apply = DD_APPLY_AUTO;
+  o->launch = DD_LAUNCH_AUTO;
+  o->check_every = 0;
+  o->verify = 1;
+}
+
+const char *dd_last_error(const dd_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_setup_error.c_str();
+}
+
+dd_status dd_footprint(const dd_problem *prob, dd_precision prec, int32_t max_nrhs, size_t *bytes) {
+  if (!prob || !bytes || !prob->sub || prob->n_sub < 1) return fail(nullptr, DD_EINVAL, "bad arguments");
+  if (max_nrhs < 1 || max_nrhs > kMaxLd) return fail(nullptr, DD_EINVAL, "max_nrhs out of [1, 64]");
+  *bytes = footprint_bytes(prob, prec, max_nrhs);
+  return DD_OK;
+}
+
+void dd_destroy(dd_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void *p : c->allocs) (void)hipFree(p);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  if (c->h_nact) (void)hipHostFree(c->h_nact);
+  delete c;
+}
+
+dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_ctx **out) {
+  if (!out) return fail(nullptr, DD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_nrhs < 1 || max_nrhs > kMaxLd) return fail(nullptr, DD_EINVAL, "max_nrhs out of [1, 64]");
+  dd_status vs = validate(p);
+  if (vs != DD_OK) return vs;
+  dd_ctx *c = new (std::nothrow) dd_ctx();
+  if (!c) return fail(nullptr, DD_ENOMEM, "host allocation failed");
+  auto bail = [&](dd_status s) {
+    g_setup_error = c->err;
+    dd_destroy(c);
+    return s;
+  };
+  c->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&c->device);
+  c->n_dof = p->n_dof;
+  c->n_gamma = p->n_gamma;
+  c->n_sub = p->n_sub;
+  c->max_nrhs = max_nrhs;
+  c->ldmax = next_pow2(max_nrhs);
+  if (const char *e = getenv("DD_NO_MFMA")) c->use_mfma = atoi(e) ? 0 : 1;
+  // host-side structure
+  c->ni.resize(c->n_sub);
+  c->ioff.resize(c->n_sub);
+  c->koff.resize(c->n_sub);
+  long long kt = 0;
+  int NI = 0;
+  for (int k = 0; k < c->n_sub; ++k) {
+    c->ni[k] = p->sub[k].n_i;
+    c->ioff[k] = NI;
+    c->koff[k] = kt;
+    NI += p->sub[k].n_i;
+    kt += (long long)p->sub[k].n_i * p->sub[k].n_i;
+    c->max_ni = std::max(c->max_ni, p->sub[k].n_i);
+  }
+  c->NI = NI;
+  c->ktot = kt;
+  std::vector<int> rowsub(NI), imap(NI);
+  std::vector<double> kii(kt);
+  std::vector<int> igptr(NI + 1, 0), igcol;
+  std::vector<double> igval;
+  for (int k = 0; k < c->n_sub; ++k) {
+    const dd_subdomain &s = p->sub[k];
+    memcpy(&kii[c->koff[k]], s.k_ii, sizeof(double) * (size_t)s.n_i * s.n_i);
+    for (int i = 0; i < s.n_i; ++i) {
+      int r = c->ioff[k] + i;
+      rowsub[r] = k;
+      imap[r] = s.i_map[i];
+      for (int a = s.kig_rowptr[i]; a < s.kig_rowptr[i + 1]; ++a) {
+        igcol.push_back(s.g_map[s.kig_col[a]]);
+        igval.push_back(s.kig_val[a]);
+      }
+      igptr[r + 1] = (int)igcol.size();
+    }
+  }
+  // interface rows: [K_GG entries | K_GI entries (transposes of K_IG^k)]
+  std::vector<std::vector<std::pair<int, double>>> gi(c->n_gamma);
+  for (int r = 0; r < NI; ++r)
+    for (int a = igptr[r]; a < igptr[r + 1]; ++a) gi[igcol[a]].push_back({r, igval[a]});
+  std::vector<int> gptr(c->n_gamma + 1, 0), gsplit(c->n_gamma, 0), gcol;
+  std::vector<double> gval;
+  for (int j = 0; j < c->n_gamma; ++j) {
+    for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a) {
+      gcol.push_back(p->kgg_col[a]);
+      gval.push_back(p->kgg_val[a]);
+    }
+    gsplit[j] = (int)gcol.size();
+    // gi[j] is already ordered by interior row (rows visited in order)
+    for (auto &e : gi[j]) {
+      gcol.push_back(e.first);
+      gval.push_back(e.second);
+    }
+    gptr[j + 1] = (int)gcol.size();
+  }
+  c->nnz_ig = igcol.size();
+  c->nnz_g = gcol.size();
+  std::vector<int> ni32(c->ni.begin(), c->ni.end());
+  dd_status s;
+  if ((s = upload(c, &c->d_ni, ni32.data(), c->n_sub)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_ioff, c->ioff.data(), c->n_sub)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_koff, c->koff.data(), c->n_sub)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_rowsub, rowsub.data(), NI)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_imap, imap.data(), NI)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_gmap, p->gamma_map, c->n_gamma)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_kii64, kii.data(), kt)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_ig_ptr, igptr.data(), NI + 1)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_ig_col, igcol.data(), igcol.size())) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_ig_val64, igval.data(), igval.size())) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_g_ptr, gptr.data(), c->n_gamma + 1)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_g_split, gsplit.data(), c->n_gamma)) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_g_col, gcol.data(), gcol.size())) != DD_OK) return bail(s);
+  if ((s = upload(c, &c->d_g_val64, gval.data(), gval.size())) != DD_OK) return bail(s);
+  // work vectors
+  size_t nG = (size_t)std::max(1, c->n_gamma) * c->ldmax, nI = (size_t)std::max(1, NI) * c->ldmax;
+  Work &w = c->w;
+  double **gv[] = {&w.bG, &w.xG, &w.rG, &w.zG, &w.pG, &w.qG, &w.uG, &w.dG, &w.tG};
+  for (double **q : gv)
+    if ((s = dalloc(c, q, nG)) != DD_OK) return bail(s);
+  double **iv[] = {&w.bI, &w.yI, &w.wI, &w.uI, &w.dI, &w.tI};
+  for (double **q : iv)
+    if ((s = dalloc(c, q, nI)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_state, 1)) != DD_OK) return bail(s);
+  {
+    StateBlock *sb = c->d_state;
+    w.bnrm2 = sb->bnrm2;
+    w.rnrm2 = sb->rnrm2;
+    c->st.rz = sb->rz;
+    c->st.alpha = sb->alpha;
+    c->st.beta = sb->beta;
+    c->st.stop2 = sb->stop2;
+    c->st.nrm2 = sb->nrm2;
+    c->st.active = sb->active;
+    c->st.iters = sb->iters;
+    c->st.flag = sb->flag;
+    if (hipMemset(sb, 0, sizeof(StateBlock)) != hipSuccess) {
+      c->err = "hipMemset failed";
+      return bail(DD_EHIP);
+    }
+  }
+  c->max_chunks = std::max((size_t)(c->n_gamma + kGRows - 1) / kGRows,
+                           (size_t)(std::max(c->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
+  if ((s = dalloc(c, &c->red.part0, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->red.part1, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_bad, 1)) != DD_OK) return bail(s);
+  if (hipMemset(c->red.counter, 0, 8 * sizeof(unsigned)) != hipSuccess) {
+    c->err = "hipMemset failed";
+    return bail(DD_EHIP);
+  }
+  c->nslots = 16;
+  if (hipHostMalloc((void **)&c->h_nact, c->nslots * sizeof(int), hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer((void **)&c->h_nact_dev, c->h_nact, 0) != hipSuccess) {
+    c->err = "pinned host allocation failed";
+    return bail(DD_ENOMEM);
+  }
+  c->ev.resize(c->nslots);
+  for (auto &e : c->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      c->err = "hipEventCreate failed";
+      return bail(DD_EHIP);
+    }
+  *out = c;
+  return DD_OK;
+}
+
+dd_status dd_factor(dd_ctx *c, dd_precision prec) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  c->err.clear();
+  TRY(ensure_ops(c, prec));
+  c->op[prec].ready = false;
+  return prec == DD_FP64 ? factor_impl<double>(c, DD_FP64) : factor_impl<float>(c, DD_MIXED);
+}
+
+dd_status dd_schur_apply(dd_ctx *c, dd_precision prec, const double *p_dev, double *q_dev,
+                         int32_t nrhs, int32_t ld) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  if (nrhs < 1 || nrhs > c->max_nrhs) return fail(c, DD_EINVAL, "nrhs out of [1, max_nrhs]");
+  if (ld < c->n_gamma || !p_dev || !q_dev) return fail(c, DD_EINVAL, "bad p/q or ld");
+  int L = next_pow2(nrhs);
+  Work &w = c->w;
+  std::vector<int> id(c->n_gamma);
+  for (int j = 0; j < c->n_gamma; ++j) id[j] = j;
+  int *d_id = nullptr;
+  HIPCHK(c, hipMalloc(&d_id, std::max<size_t>(1, id.size()) * sizeof(int)));
+  HIPCHK(c, hipMemcpy(d_id, id.data(), id.size() * sizeof(int), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_gather, dim3(256), dim3(256), 0, c->stream, c->n_gamma, d_id, p_dev, ld, nrhs, L, w.tG);
+  kig_apply(c, prec, plain(w.tG), L, nullptr, 1.0, w.yI);
+  interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);
+  gamma_apply(c, prec, plain(w.tG), w.wI, L, nullptr, 1.0, -1.0, w.qG);
+  hipLaunchKernelGGL(k_scatter, dim3(256), dim3(256), 0, c->stream, c->n_gamma, d_id, w.qG, L, nrhs, q_dev, ld);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(d_id);
+  return DD_OK;
+}
+
+dd_status dd_get_factor(dd_ctx *c, dd_precision prec, int32_t k, double *out) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  if (k < 0 || k >= c->n_sub || !out) return fail(c, DD_EINVAL, "bad subdomain index or out");
+  size_t n = c->ni[k], nn = n * n;
+  if (prec == DD_FP64) {
+    HIPCHK(c, hipMemcpy(out, (double *)c->op[0].L + c->koff[k], nn * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(nn);
+    HIPCHK(c, hipMemcpy(f.data(), (float *)c->op[1].L + c->koff[k], nn * 4, hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < nn; ++e) out[e] = f[e];
+  }
+  for (size_t j = 0; j < n; ++j)
+    for (size_t i = 0; i < j; ++i) out[j * n + i] = 0.0;
+  return DD_OK;
+}
+
+dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  c->timing_mask = phase_mask & ((1u << DD_NPHASES) - 1u);
+  for (int i = 0; i < DD_NPHASES; ++i) {
+    c->t_ms[i] = 0.0;
+    c->t_count[i] = 0;
+  }
+  c->tev_used = 0;
+  return DD_OK;
+}
+
+dd_status dd_get_timing(dd_ctx *c, double *ms, int64_t *launches) {
+  if (!c || !ms || !launches) return fail(c, DD_EINVAL, "NULL argument");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->tev_used) collect_timing(c);
+  for (int i = 0; i < DD_NPHASES; ++i) {
+    ms[i] = c->t_ms[i];
+    launches[i] = c->t_count[i];
+  }
+  return DD_OK;
+}
+
+dd_status dd_get_schur_diag(dd_ctx *c, dd_precision prec, double *out) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  if (!out) return fail(c, DD_EINVAL, "out is NULL");
+  HIPCHK(c, hipMemcpy(out, c->op[prec].diag, c->n_gamma * 8, hipMemcpyDeviceToHost));
+  return DD_OK;
+}
+
+dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_dev, int32_t nrhs,
+                   int32_t ld, const dd_solve_opts *opts, dd_solve_info *info) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (nrhs < 1 || nrhs > c->max_nrhs) return fail(c, DD_EINVAL, "nrhs out of [1, max_nrhs]");
+  if (ld < c->n_dof || !b_dev || !u_dev) return fail(c, DD_EINVAL, "bad b/u or ld < n_dof");
+  if (b_dev == u_dev) return fail(c, DD_EINVAL, "b and u alias");
+  dd_solve_opts o;
+  if (opts) o = *opts; else dd_default_opts(&o);
+  if (!(o.tol > 0.0) || o.max_it < 1) return fail(c, DD_EINVAL, "tol <= 0 or max_it < 1");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  if (prec == DD_MIXED && (o.max_refine < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0))
+    return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in (0,1)");
+  const int L = next_pow2(nrhs);
+  CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
+              o.check_every};
+  Work &w = c->w;
+  // gather b into the DD layout
+  hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->NI * L, 256))), dim3(256), 0,
+                     c->stream, c->NI, c->d_imap, b_dev, ld, nrhs, L, w.bI);
+  if (c->n_gamma > 0)
+    hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->n_gamma * L, 256))), dim3(256),
+                       0, c->stream, c->n_gamma, c->d_gmap, b_dev, ld, nrhs, L, w.bG);
+  HIPCHK(c, hipGetLastError());
+  TRY(dd_norm2(c, L, w.bI, w.bG, w.bnrm2));
+  std::vector<double> bn2(kMaxLd, 0.0), rn2(kMaxLd, 0.0);
+  std::vector<int> its(kMaxLd, 0), conv(kMaxLd, 0), steps(kMaxLd, 0), fb(kMaxLd, 0);
+  dd_status result = DD_OK;
+
+  auto read_iters = [&](std::vector<int> &dst, bool add) -> dd_status {
+    StateBlock h;
+    TRY(fetch_state(c, &h));
+    for (int j = 0; j < nrhs; ++j) dst[j] = add ? dst[j] + h.iters[j] : h.iters[j];
+    return DD_OK;
+  };
+
+  if (prec == DD_FP64) {
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(kMaxLd), 0, c->stream, L, o.tol * o.tol, w.bnrm2, c->st);
+    dd_status s = core_solve(c, DD_FP64, w.bI, w.bG, w.uI, w.uG, L, nrhs, co);
+    if (s != DD_OK) return s;
+    if (o.verify) {
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
+    }
+    StateBlock h;
+    TRY(fetch_state(c, &h));
+    for (int j = 0; j < nrhs; ++j) {
+      its[j] = h.iters[j];
+      conv[j] = !h.active[j];
+      bn2[j] = h.bnrm2[j];
+      rn2[j] = o.verify ? h.rnrm2[j] : h.nrm2[j];
+    }
+  } else {
+    // Mixed precision iterative refinement on the full system (FP64 residual):
+    //   r = b - A u;  inner DD solve with FP32 operators to inner_tol;  u += d.
+    HIPCHK(c, hipMemsetAsync(w.uI, 0, (size_t)c->NI * L * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(w.uG, 0, (size_t)c->n_gamma * L * 8, c->stream));
+    HIPCHK(c, hipMemcpy(bn2.data(), w.bnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
+    std::vector<double> prev(kMaxLd, -1.0);
+    std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0);
+    for (int j = nrhs; j < kMaxLd; ++j) done[j] = 1;
+    std::vector<int> mask(kMaxLd, 0);
+    int *dmask = nullptr;
+    HIPCHK(c, hipMalloc(&dmask, kMaxLd * sizeof(int)));
+    struct Free { int *p; ~Free() { if (p) (void)hipFree(p); } } fr{dmask};
+    for (int step = 0;; ++step) {
+      // FP64 residual (step 0: r = b)
+      if (step == 0) {
+        HIPCHK(c, hipMemcpyAsync(w.tI, w.bI, (size_t)c->NI * L * 8, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(w.tG, w.bG, (size_t)c->n_gamma * L * 8, hipMemcpyDeviceToDevice, c->stream));
+      } else {
+        full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      }
+      TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
+      HIPCHK(c, hipMemcpy(rn2.data(), w.rnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
+      bool any = false;
+      for (int j = 0; j < nrhs; ++j) {
+        if (done[j]) continue;
+        if (rn2[j] <= o.tol * o.tol * bn2[j]) { done[j] = 1; conv[j] = 1; continue; }
+        if (prev[j] >= 0.0 && rn2[j] > 0.25 * prev[j]) {   // reduction worse than 0.5 in norm
+          if (++stall[j] >= 2) { done[j] = 1; need_fb[j] = 1; continue; }
+        }
+        if (step >= o.max_refine) { done[j] = 1; need_fb[j] = 1; continue; }
+        prev[j] = rn2[j];
+        any = true;
+      }
+      if (!any) break;
+      // inner solve on the residual; finished columns get a zero right-hand side
+      for (int j = 0; j < kMaxLd; ++j) mask[j] = done[j] ? 0 : 1;
+      HIPCHK(c, hipMemcpyAsync(dmask, mask.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      std::vector<double> st2(kMaxLd, 0.0);
+      for (int j = 0; j < kMaxLd; ++j) st2[j] = mask[j] ? o.inner_tol * o.inner_tol * rn2[j] : 0.0;
+      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+      for (int j = 0; j < nrhs; ++j)
+        if (!mask[j]) {
+          HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
+          if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
+        }
+      dd_status s = core_solve(c, DD_MIXED, w.tI, w.tG, w.dI, w.dG, L, nrhs, co);
+      if (s != DD_OK) return s;
+      TRY(read_iters(its, true));
+      for (int j = 0; j < nrhs; ++j) if (mask[j]) steps[j] += 1;
+      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->NI * L, L, w.dI, w.uI, dmask);
+      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->n_gamma * L, L, w.dG, w.uG, dmask);
+      HIPCHK(c, hipGetLastError());
+    }
+    // FP64 fallback for columns whose refinement stalled
+    bool anyfb = false;
+    for (int j = 0; j < nrhs; ++j) anyfb |= (need_fb[j] != 0);
+    if (anyfb && o.fp64_fallback) {
+      if (!c->op[DD_FP64].ready) {
+        dd_status s = dd_factor(c, DD_FP64);
+        if (s != DD_OK) return s;
+      }
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      for (int j = 0; j < kMaxLd; ++j) mask[j] = (j < nrhs && need_fb[j]) ? 1 : 0;
+      HIPCHK(c, hipMemcpyAsync(dmask, mask.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      std::vector<double> st2(kMaxLd, 0.0);
+      for (int j = 0; j < kMaxLd; ++j) st2[j] = mask[j] ? o.tol * o.tol * bn2[j] : 0.0;
+      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+      for (int j = 0; j < nrhs; ++j)
+        if (!mask[j]) {
+          HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
+          if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
+        }
+      dd_status s = core_solve(c, DD_FP64, w.tI, w.tG, w.dI, w.dG, L, nrhs, co);
+      if (s != DD_OK) return s;
+      TRY(read_iters(its, true));
+      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->NI * L, L, w.dI, w.uI, dmask);
+      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->n_gamma * L, L, w.dG, w.uG, dmask);
+      for (int j = 0; j < nrhs; ++j) if (mask[j]) fb[j] = 1;
+    }
+    // final FP64 residual
+    full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+    TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
+    HIPCHK(c, hipMemcpy(rn2.data(), w.rnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < nrhs; ++j) conv[j] = rn2[j] <= o.tol * o.tol * bn2[j] * (1.0 + 1e-12);
+  }
+  // scatter the DD-layout solution into u
+  hipLaunchKernelGGL(k_scatter, dim3(std::min(4096u, grid_for((size_t)c->NI * nrhs, 256))), dim3(256), 0,
+                     c->stream, c->NI, c->d_imap, w.uI, L, nrhs, u_dev, ld);
+  if (c->n_gamma > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(4096u, grid_for((size_t)c->n_gamma * nrhs, 256))), dim3(256),
+                       0, c->stream, c->n_gamma, c->d_gmap, w.uG, L, nrhs, u_dev, ld);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < nrhs; ++j) {
+    if (!conv[j]) result = DD_ENOCONV;
+    if (info) {
+      info[j].iters = its[j];
+      info[j].refine_steps = steps[j];
+      info[j].used_fallback = fb[j];
+      info[j].converged = conv[j];
+      info[j].rel_resid = bn2[j] > 0.0 ? std::sqrt(rn2[j] / bn2[j]) : std::sqrt(rn2[j]);
+    }
+  }
+  if (result == DD_ENOCONV) c->err = "tolerance not reached for at least one column";
+  return result;
+}
+
+}  // extern "C"

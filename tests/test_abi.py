@@ -1,0 +1,106 @@
+"""The C-ABI library: it loads without a GPU, exports every entry point that
+include/dd.h declares (the Python binding uses the same names), and its
+host-side validation rejects malformed input.  No device work is started."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2306_00094_amd as dd
+    if not os.path.exists(dd.LIB_PATH):
+        from paper_2306_00094_amd import _build
+        _build.build()
+    return dd, dd.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dd_setup", "dd_factor", "dd_solve", "dd_destroy", "dd_footprint",
+                     "dd_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    dd, so = lib
+    out = subprocess.run(["nm", "-D", "--defined-only", dd.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(so, name)
+    assert sorted(dd.EXPORTED) == declared_functions()
+
+
+def test_default_opts(lib):
+    dd, _ = lib
+    o = dd.dd_default_opts()
+    assert (o.tol, o.max_it, o.precond, o.max_refine, o.inner_tol, o.fp64_fallback,
+            o.apply, o.launch, o.check_every, o.verify) == (1e-10, 1000, 1, 8, 1e-4, 1, 0, 0, 0, 1)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return W.build(W.spec_1d(n=64, strips=2)).dd
+
+
+def test_footprint_counts_matrices_and_factors(lib, small):
+    dd, _ = lib
+    b64 = dd.dd_footprint(small, dd.DD_FP64, 1)
+    b32 = dd.dd_footprint(small, dd.DD_MIXED, 1)
+    kii = sum(k.size for k in small.kii) * 8
+    assert b64 >= 3 * kii                          # K_II, factor, inverse
+    assert b32 >= kii + 2 * kii // 2
+    assert dd.dd_footprint(small, dd.DD_FP64, 64) > b64
+
+
+def _copy(dd):
+    import copy
+    return copy.deepcopy(dd)
+
+
+@pytest.mark.parametrize("breaker,msg", [
+    (lambda p: p.i_maps.__setitem__(0, np.concatenate([p.i_maps[0][:-1], p.i_maps[0][:1]])),
+     "assigned twice"),
+    (lambda p: p.g_maps.__setitem__(0, p.g_maps[0] + p.n_gamma), "g_map entry out of range"),
+    (lambda p: p.__setattr__("gamma_map", p.gamma_map[::-1][:-1].copy()), "n_gamma"),
+    (lambda p: p.i_maps.__setitem__(1, p.i_maps[1][:-1]), "neither interior nor interface"),
+])
+def test_setup_rejects_malformed_input(lib, small, breaker, msg):
+    dd, _ = lib
+    p = _copy(small)
+    breaker(p)
+    if msg == "n_gamma":
+        p.n_gamma = len(p.gamma_map)
+        msg = "out of range"
+    if msg == "neither interior nor interface":
+        p.kii[1] = p.kii[1][:-1, :-1].copy()
+        p.kig[1] = p.kig[1][:-1]
+    with pytest.raises(dd.DDError) as ei:
+        dd.dd_setup(p, stream=0, max_nrhs=1)
+    assert ei.value.status == dd.DD_EINVAL
+    assert msg in str(ei.value) or "out of range" in str(ei.value)
+
+
+def test_setup_rejects_bad_batch_width(lib, small):
+    dd, _ = lib
+    for m in (0, 65):
+        with pytest.raises(dd.DDError) as ei:
+            dd.dd_setup(small, stream=0, max_nrhs=m)
+        assert ei.value.status == dd.DD_EINVAL

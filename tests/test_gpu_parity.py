@@ -1,0 +1,158 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Gates: FP64 path error <= 1e-10 relative to the monolithic FP64 solution,
+mixed path error <= 1e-8 after refinement; factors, diag(S) and the Schur
+operator element by element against the oracle.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dd():
+    import paper_2306_00094_amd as dd
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dd.load_library()          # raises if the HIP library is missing
+    return dd
+
+
+SMALL = {
+    "1d-4strips": lambda: workloads.spec_1d(n=256, strips=4, nrhs=2),
+    "1d-ragged": lambda: workloads.spec_1d(n=100, delta=0.07, strips=3, nrhs=3),
+    "2d-const": lambda: workloads.spec_2d_const(n=32, cuts=(2, 2), nrhs=3),
+    "2d-const-3x2": lambda: workloads.spec_2d_const(n=40, cuts=(3, 2), nrhs=2),
+    "2d-frac": lambda: workloads.spec_2d_frac(n=32, cuts=(2, 2), nrhs=2),
+    "2d-pd": lambda: workloads.spec_2d_pd(n=40, delta=0.1, cuts=(3, 3), jitter=0.2, nrhs=2),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def problem(name):
+    spec = SMALL[name]()
+    wl = workloads.build(spec)
+    b = workloads.rhs(spec)
+    uref = oracle.monolithic_solve(wl.asm.A, b)
+    return wl, b, uref
+
+
+def to_dev(b):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(b).T)).to("cuda:0").contiguous()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_factor_parity(name, prec):
+    dd = _dd()
+    wl, _, _ = problem(name)
+    print(f"case factor {name} prec={prec}", flush=True)
+    s = dd.Solver(wl.dd, max_nrhs=1)
+    s.factor(prec)
+    tol = 1e-12 if prec == dd.DD_FP64 else 2e-5
+    for k in range(wl.dd.n_sub):
+        K = wl.dd.kii[k]
+        L_ref = np.linalg.cholesky(K)
+        L = s.factor_block(k, prec)
+        err = np.abs(L - L_ref).max() / np.abs(L_ref).max()
+        assert err <= tol, (k, err)
+    d_ref = oracle.DDOracle(wl.dd).schur_diag()
+    d = s.schur_diag(prec)
+    derr = np.abs(d - d_ref).max() / np.abs(d_ref).max()
+    assert derr <= (1e-12 if prec == dd.DD_FP64 else 1e-4), derr
+    s.close()
+
+
+def test_factor_vector_vs_mfma(monkeypatch):
+    """The MFMA trailing update and the vector-FMA one give the same factor."""
+    dd = _dd()
+    wl, _, _ = problem("2d-const-3x2")
+    print("case factor mfma/vector", flush=True)
+    s1 = dd.Solver(wl.dd)
+    s1.factor(dd.DD_FP64)
+    monkeypatch.setenv("DD_NO_MFMA", "1")
+    s2 = dd.Solver(wl.dd)
+    s2.factor(dd.DD_FP64)
+    for k in range(wl.dd.n_sub):
+        a, b = s1.factor_block(k), s2.factor_block(k)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    s1.close()
+    s2.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_schur_apply_parity(name):
+    dd = _dd()
+    wl, _, _ = problem(name)
+    print(f"case schur_apply {name}", flush=True)
+    orc = oracle.DDOracle(wl.dd)
+    rng = np.random.default_rng(7)
+    P = rng.uniform(-1, 1, size=(wl.dd.n_gamma, 3))
+    Q_ref = orc.schur_apply(P)
+    s = dd.Solver(wl.dd, max_nrhs=3)
+    s.factor(dd.DD_FP64)
+    Q = s.schur_apply(to_dev(P)).cpu().numpy().T
+    err = np.abs(Q - Q_ref).max() / np.abs(Q_ref).max()
+    assert err <= 1e-12, err
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("apply", [1, 2])
+def test_solve_fp64(name, apply):
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case solve fp64 {name} apply={apply}", flush=True)
+    nrhs = b.shape[1]
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s.factor(dd.DD_FP64)
+    opts = dd.dd_default_opts(tol=1e-14, apply=apply)
+    res = s.solve(to_dev(b), prec=dd.DD_FP64, opts=opts)
+    u = res.u.cpu().numpy().T
+    err = oracle.rel_err(u, uref)
+    assert err.max() <= 1e-10, err
+    # iteration counts match the oracle's CG (same preconditioner and stopping rule)
+    _, its, _ = oracle.DDOracle(wl.dd).solve(b, tol=1e-14)
+    got = np.array([i["iters"] for i in res.info])
+    assert np.all(np.abs(got - its) <= 2), (got, its)
+    assert all(i["converged"] for i in res.info)
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_solve_mixed(name):
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case solve mixed {name}", flush=True)
+    nrhs = b.shape[1]
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s.factor(dd.DD_MIXED)
+    opts = dd.dd_default_opts(tol=1e-12)
+    res = s.solve(to_dev(b), prec=dd.DD_MIXED, opts=opts)
+    u = res.u.cpu().numpy().T
+    err = oracle.rel_err(u, uref)
+    print("  err", err, res.info, flush=True)
+    assert err.max() <= 1e-8, err
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_invariance(prec):
+    """Each column solved inside a batch equals the same column solved alone."""
+    dd = _dd()
+    wl, b, _ = problem("2d-const")
+    print(f"case batch invariance prec={prec}", flush=True)
+    s = dd.Solver(wl.dd, max_nrhs=3)
+    s.factor(prec)
+    opts = dd.dd_default_opts(tol=1e-12)
+    ub = s.solve(to_dev(b), prec=prec, opts=opts).u.cpu().numpy()
+    for j in range(b.shape[1]):
+        uj = s.solve(to_dev(b[:, j:j + 1]), prec=prec, opts=opts).u.cpu().numpy()
+        assert np.array_equal(uj[0], ub[j]), j
+    s.close()
