@@ -87,10 +87,42 @@ __device__ __forceinline__ double load_partial(const double *p) {
 
 // Final reduction of P chunk partials for column c by one wave: lane t sums
 // partials t, t+64, ... in order, then the butterfly.  Fixed for a given P.
+// Loads are issued in batches of 8 so they overlap.
 __device__ __forceinline__ double partials_sum(const double *part, int P, int ld, int c) {
   double s = 0.0;
-  for (int i = lane_id(); i < P; i += kWave) s += load_partial(part + (size_t)i * ld + c);
+  for (int i0 = lane_id(); i0 < P; i0 += 8 * kWave) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int i = i0 + u * kWave;
+      v[u] = i < P ? load_partial(part + (size_t)i * ld + c) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   return wave_sum(s);
+}
+
+// Two reductions of the same shape at once (their loads overlap).
+__device__ __forceinline__ void partials_sum2(const double *pa, const double *pb, int P, int ld,
+                                              int c, double &ra, double &rb) {
+  double sa = 0.0, sb = 0.0;
+  for (int i0 = lane_id(); i0 < P; i0 += 8 * kWave) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int i = i0 + u * kWave;
+      va[u] = i < P ? load_partial(pa + (size_t)i * ld + c) : 0.0;
+      vb[u] = i < P ? load_partial(pb + (size_t)i * ld + c) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sa += va[u];
+      sb += vb[u];
+    }
+  }
+  ra = wave_sum(sa);
+  rb = wave_sum(sb);
 }
 
 // Last-workgroup election after every workgroup stored its partials (with
@@ -138,9 +170,10 @@ __device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) 
 }
 
 // acc[c] += sum_k val[k] * x[col[k]][cp + c] over the row, lane-strided.
-// Each lane visits its entries k = b+lane, b+lane+64, ... in increasing order;
-// the loop is unrolled so that up to U gathers are in flight per lane, without
-// changing that order.
+// Each lane visits its entries k = b+lane, b+lane+64, ... in increasing order.
+// The loop issues U slots per pass with masked loads: a slot past the row end
+// adds fma(0, 0, acc) = acc exactly, so the sum is bit-identical to the plain
+// loop while U gathers are in flight per lane.
 template <int C> struct Unroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
 
 template <int C, typename VT>
@@ -150,35 +183,35 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
   constexpr int U = Unroll<C>::U;
   double bt[C];
   src_beta<C>(x, cp, bt);
-  int k = b + lane_id();
-  for (; k + (U - 1) * kWave < e; k += U * kWave) {
+  for (int k = b + lane_id(); k < e; k += U * kWave) {
     double v[U];
     int cc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = (double)val[k + u * kWave];
-      cc[u] = col[k + u * kWave];
+      int idx = k + u * kWave;
+      bool ok = idx < e;
+      v[u] = ok ? (double)val[idx] : 0.0;
+      cc[u] = ok ? col[idx] : -1;
     }
     double xv[U][C];
 #pragma unroll
-    for (int u = 0; u < U; ++u) src_load<C>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
+    for (int u = 0; u < U; ++u) {
+      if (cc[u] >= 0) src_load<C>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
+      else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int c = 0; c < C; ++c) acc[c] = tfma(v[u], xv[u][c], acc[c]);
   }
-  for (; k < e; k += kWave) {
-    double v = (double)val[k];
-    double xv[C];
-    src_load<C>(x, (size_t)col[k] * ld + cp, bt, xv);
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = tfma(v, xv[c], acc[c]);
-  }
 }
 
 // Two-part row: entries [b, s) gather from x1 into acc1, entries [s, e) from
-// x2 into acc2, interleaved in one unrolled loop (each accumulator still sees
-// its entries in increasing order).
+// x2 into acc2, in one masked loop (each accumulator sees its entries in
+// increasing order; slots of the other part add exact zeros).
 template <int C, typename VT>
 __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__restrict__ col,
                                              const VT *__restrict__ val, const Src &x1,
@@ -188,43 +221,39 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
   double bt1[C], bt2[C];
   src_beta<C>(x1, cp, bt1);
   src_beta<C>(x2, cp, bt2);
-  int k = b + lane_id();
-  for (; k + (U - 1) * kWave < e; k += U * kWave) {
+  for (int k = b + lane_id(); k < e; k += U * kWave) {
     double v[U];
     int cc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = (double)val[k + u * kWave];
-      cc[u] = col[k + u * kWave];
+      int idx = k + u * kWave;
+      bool ok = idx < e;
+      v[u] = ok ? (double)val[idx] : 0.0;
+      cc[u] = ok ? col[idx] : -1;
     }
     double xv[U][C];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (k + u * kWave < s) src_load<C>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
-      else src_load<C>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
+      int idx = k + u * kWave;
+      if (cc[u] < 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
+      } else if (idx < s) {
+        src_load<C>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
+      } else {
+        src_load<C>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (k + u * kWave < s) {
+      int idx = k + u * kWave;
+      double v1 = idx < s ? v[u] : 0.0;
+      double v2 = idx < s ? 0.0 : v[u];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc1[c] = tfma(v[u], xv[u][c], acc1[c]);
-      } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc2[c] = tfma(v[u], xv[u][c], acc2[c]);
+      for (int c = 0; c < C; ++c) {
+        acc1[c] = tfma(v1, xv[u][c], acc1[c]);
+        acc2[c] = tfma(v2, xv[u][c], acc2[c]);
       }
-    }
-  }
-  for (; k < e; k += kWave) {
-    double v = (double)val[k];
-    double xv[C];
-    if (k < s) {
-      src_load<C>(x1, (size_t)col[k] * ld + cp, bt1, xv);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc1[c] = tfma(v, xv[c], acc1[c]);
-    } else {
-      src_load<C>(x2, (size_t)col[k] * ld + cp, bt2, xv);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc2[c] = tfma(v, xv[c], acc2[c]);
     }
   }
 }
@@ -281,27 +310,22 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = (AT)0;
     constexpr int U = Unroll<C>::U;
-    int j = lane_id();
-    for (; j + (U - 1) * kWave < n; j += U * kWave) {
+    for (int j = lane_id(); j < n; j += U * kWave) {
       AT a[U];
       double yv[U][C];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        a[u] = (AT)row[j + u * kWave];
-        const double *yr = yb + (size_t)(j + u * kWave) * ld + cp;
+        int jj = j + u * kWave;
+        bool ok = jj < n;
+        a[u] = ok ? (AT)row[jj] : (AT)0;
+        const double *yr = yb + (size_t)(ok ? jj : 0) * ld + cp;
 #pragma unroll
-        for (int c = 0; c < C; ++c) yv[u][c] = yr[c];
+        for (int c = 0; c < C; ++c) yv[u][c] = ok ? yr[c] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = tfma(a[u], (AT)yv[u][c], acc[c]);
-    }
-    for (; j < n; j += kWave) {
-      AT a = (AT)row[j];
-      const double *yr = yb + (size_t)j * ld + cp;
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = tfma(a, (AT)yr[c], acc[c]);
     }
     double sacc[C];
 #pragma unroll
@@ -418,7 +442,7 @@ __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
-            int use_precond, int *__restrict__ host_nact) {
+            int use_precond, int *__restrict__ host_nact, int init_p_is_z) {
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ int lflag;
   const int row0 = blockIdx.x * kRowsE;
@@ -442,7 +466,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       double zv = use_precond ? dinv[j] * rv : rv;
       if (act) z[o] = zv;
       else zv = z[o];
-      if (mode == 0) p[o] = 0.0;           // previous direction: none yet (beta = 0)
+      if (mode == 0) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
       rz = rv * zv;
     }
     lds[lr * ld + c] = rz;
@@ -468,8 +492,8 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
   }
   if (!last_block(&red.counter[1], &lflag)) return;
   for (int c = wv; c < ld; c += kWavesPerBlock) {
-    double rz = partials_sum(red.part0, gridDim.x, ld, c);
-    double rr = partials_sum(red.part1, gridDim.x, ld, c);
+    double rz, rr;
+    partials_sum2(red.part0, red.part1, gridDim.x, ld, c, rz, rr);
     if (lane == 0) {
       if (mode == 0) {
         st.rz[c] = rz;
@@ -499,6 +523,18 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
 __global__ void k_set_stop(int ld, double f2, const double *__restrict__ v, ColState st) {
   int c = threadIdx.x;
   if (c < ld) st.stop2[c] = f2 * v[c];
+}
+
+// p = z + beta p for the active columns (when the direction is kept in memory
+// instead of being formed where it is gathered).
+__global__ void __launch_bounds__(kBlock)
+k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p,
+               ColState st) {
+  size_t n = (size_t)nrows * ld;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+    int c = (int)(e % ld);
+    if (st.active[c]) p[e] = fma(st.beta[c], p[e], z[e]);
+  }
 }
 
 // ------------------------------------------------------- vector helpers --

@@ -88,6 +88,7 @@ struct dd_ctx {
   std::vector<void *> allocs;
   size_t bytes = 0;
   int use_mfma = 1;
+  int direction_kernel = 0;   // 1: keep p in memory, update it with its own kernel
   // optional per-phase kernel timing with HIP events (dd_set_timing)
   unsigned timing_mask = 0;
   std::vector<hipEvent_t> tev;          // event pool, pairs (start, stop)
@@ -482,7 +483,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   unsigned ge = c->n_gamma > 0 ? grid_for(c->n_gamma, kRowsE) : 0;
   if (c->n_gamma > 0)
     hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 0, c->n_gamma, ld, nrhs,
-                       op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr);
+                       op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr,
+                       c->direction_kernel);
   HIPCHK(c, hipGetLastError());
   // host polling with a lag: iteration `it` writes h_nact[it % nslots] = active + 1
   const int lag = std::min(8, std::max(1, o.check_every > 0 ? o.check_every : 2));
@@ -492,8 +494,9 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   bool stop = c->n_gamma == 0;
   while (!stop && it < o.max_it) {
     ++it;
-    // direction p = z + beta p_prev, formed where it is gathered
-    Src P{nullptr, w.zG, pA, c->st.beta};
+    // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
+    const bool dk = c->direction_kernel != 0;
+    Src P = dk ? plain(pA) : Src{nullptr, w.zG, pA, c->st.beta};
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     {
       PhaseTimer t(c, DD_PHASE_KIG);
@@ -505,17 +508,23 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     {
       PhaseTimer t(c, DD_PHASE_GAMMA);
-      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, pB);
+      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, dk ? nullptr : pB);
     }
     int slot = it % c->nslots;
     c->h_nact[slot] = 0;
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
-                         op.dinv, uG, w.rG, w.zG, pB, w.qG, c->red, c->st, o.precond,
-                         c->h_nact_dev + slot);
+                         op.dinv, uG, w.rG, w.zG, dk ? pA : pB, w.qG, c->red, c->st, o.precond,
+                         c->h_nact_dev + slot, 0);
     }
-    std::swap(pA, pB);
+    if (dk) {
+      unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
+      hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,
+                         w.zG, pA, c->st);
+    } else {
+      std::swap(pA, pB);
+    }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
     ring_it[slot] = it;
@@ -615,6 +624,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   c->max_nrhs = max_nrhs;
   c->ldmax = next_pow2(max_nrhs);
   if (const char *e = getenv("DD_NO_MFMA")) c->use_mfma = atoi(e) ? 0 : 1;
+  if (const char *e = getenv("DD_DIRECTION_KERNEL")) c->direction_kernel = atoi(e) ? 1 : 0;
   // host-side structure
   c->ni.resize(c->n_sub);
   c->ioff.resize(c->n_sub);
