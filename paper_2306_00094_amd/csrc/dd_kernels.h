@@ -55,7 +55,7 @@ struct ColState {
   double *nrm2;     // scratch norms
   int *active;      // 1 while the column iterates
   int *iters;       // iterations taken
-  int *flag;        // [0]: breakdown (p^T S p <= 0) seen
+  int *flag;        // [0]: breakdown (p^T S p <= 0) seen; [1]: iterate (persistent launch)
 };
 
 // Partial-sum buffers and completion counters of the reductions.
@@ -143,7 +143,8 @@ __device__ __forceinline__ void reset_counter(unsigned *counter) {
 
 // ----------------------------------------------------------- row products --
 // Source of gathered vector entries: a plain vector x, or the CG direction
-// formed on the fly, x = z + beta * p_prev (beta per column).
+// formed on the fly, x = z + beta * p_prev (beta per column).  Which of the
+// two is fixed at compile time (OTF), so a plain source holds no beta.
 struct Src {
   const double *x;       // plain vector (when z == nullptr)
   const double *z;       // on the fly: z + beta * pp
@@ -151,10 +152,10 @@ struct Src {
   const double *beta;
 };
 
-template <int C>
+template <int C, bool OTF>
 __device__ __forceinline__ void src_load(const Src &s, size_t off, const double (&bt)[C],
                                          double (&out)[C]) {
-  if (s.z) {
+  if (OTF) {
 #pragma unroll
     for (int c = 0; c < C; ++c) out[c] = fma(bt[c], s.pp[off + c], s.z[off + c]);
   } else {
@@ -163,10 +164,10 @@ __device__ __forceinline__ void src_load(const Src &s, size_t off, const double 
   }
 }
 
-template <int C>
+template <int C, bool OTF>
 __device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) {
 #pragma unroll
-  for (int c = 0; c < C; ++c) bt[c] = s.z ? s.beta[cp + c] : 0.0;
+  for (int c = 0; c < C; ++c) bt[c] = OTF ? s.beta[cp + c] : 0.0;
 }
 
 // acc[c] += sum_k val[k] * x[col[k]][cp + c] over the row, lane-strided.
@@ -176,13 +177,12 @@ __device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) 
 // loop while U gathers are in flight per lane.
 template <int C> struct Unroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
 
-template <int C, typename VT>
+template <int C, typename VT, bool OTF, int U = Unroll<C>::U>
 __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict__ col,
                                             const VT *__restrict__ val, const Src &x, int ld,
                                             int cp, double (&acc)[C]) {
-  constexpr int U = Unroll<C>::U;
   double bt[C];
-  src_beta<C>(x, cp, bt);
+  src_beta<C, OTF>(x, cp, bt);
   for (int k = b + lane_id(); k < e; k += U * kWave) {
     double v[U];
     int cc[U];
@@ -196,7 +196,7 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
     double xv[U][C];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (cc[u] >= 0) src_load<C>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
+      if (cc[u] >= 0) src_load<C, OTF>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
       else {
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
@@ -212,15 +212,14 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
 // Two-part row: entries [b, s) gather from x1 into acc1, entries [s, e) from
 // x2 into acc2, in one masked loop (each accumulator sees its entries in
 // increasing order; slots of the other part add exact zeros).
-template <int C, typename VT>
+template <int C, typename VT, bool OTF1, int U = Unroll<C>::U>
 __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__restrict__ col,
                                              const VT *__restrict__ val, const Src &x1,
                                              const Src &x2, int ld, int cp, double (&acc1)[C],
                                              double (&acc2)[C]) {
-  constexpr int U = Unroll<C>::U;
   double bt1[C], bt2[C];
-  src_beta<C>(x1, cp, bt1);
-  src_beta<C>(x2, cp, bt2);
+  src_beta<C, OTF1>(x1, cp, bt1);
+  src_beta<C, false>(x2, cp, bt2);
   for (int k = b + lane_id(); k < e; k += U * kWave) {
     double v[U];
     int cc[U];
@@ -239,9 +238,9 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
       } else if (idx < s) {
-        src_load<C>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
+        src_load<C, OTF1>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
       } else {
-        src_load<C>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
+        src_load<C, false>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
       }
     }
 #pragma unroll
@@ -260,7 +259,7 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
 
 // out = base + sign * A x  for CSR rows (one wave per row).
 // Used for y = K_IG p and for the back-substitution right side b_I - K_IG u_G.
-template <int C, typename VT>
+template <int C, typename VT, bool OTF>
 __global__ void __launch_bounds__(kBlock)
 k_csr_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
            const VT *__restrict__ val, Src x, int ld,
@@ -272,7 +271,7 @@ k_csr_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
-    csr_row_acc<C, VT>(b, e, col, val, x, ld, cp, acc);
+    csr_row_acc<C, VT, OTF>(b, e, col, val, x, ld, cp, acc);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
     if (lane_id() == 0) {
@@ -332,7 +331,7 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
     for (int c = 0; c < C; ++c) sacc[c] = 0.0;
     if (sptr) {
       Src sxs{sx, nullptr, nullptr, nullptr};
-      csr_row_acc<C, double>(sptr[r], sptr[r + 1], scol, sval, sxs, ld, cp, sacc);
+      csr_row_acc<C, double, false>(sptr[r], sptr[r + 1], scol, sval, sxs, ld, cp, sacc);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -358,7 +357,7 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
 // the last workgroup computes alpha = rz / (p^T q) for the active columns
 // (CG step length; breakdown when p^T q <= 0).
 constexpr int kGRows = 16;
-template <int C, typename VT>
+template <int C, typename VT, bool OTF>
 __global__ void __launch_bounds__(kGRows * kWave)
 k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
@@ -376,9 +375,9 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
     for (int c = 0; c < C; ++c) { a1[c] = 0.0; a2[c] = 0.0; }
     if (j < nrows) {
       int b = ptr[j], s = split[j], e = ptr[j + 1];
-      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
-      else if (c1 != 0.0) csr_row_acc<C, VT>(b, s, col, val, p, ld, cp, a1);
-      else if (c2 != 0.0) csr_row_acc<C, VT>(s, e, col, val, zs, ld, cp, a2);
+      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT, OTF>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
+      else if (c1 != 0.0) csr_row_acc<C, VT, OTF>(b, s, col, val, p, ld, cp, a1);
+      else if (c2 != 0.0) csr_row_acc<C, VT, false>(s, e, col, val, zs, ld, cp, a2);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -387,8 +386,8 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
     }
     if (lane == 0) {
       double bt[C], pj[C];
-      src_beta<C>(p, cp, bt);
-      if (j < nrows && dot) src_load<C>(p, (size_t)j * ld + cp, bt, pj);
+      src_beta<C, OTF>(p, cp, bt);
+      if (j < nrows && dot) src_load<C, OTF>(p, (size_t)j * ld + cp, bt, pj);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         double q = 0.0;
@@ -514,6 +513,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     int na = 0;
     for (int c = 0; c < ld; ++c) na += st.active[c];
     if (st.flag[0]) na = 0;            // breakdown ends the loop
+    st.flag[1] = na > 0 ? 1 : 0;       // loop decision for the persistent launch
     if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     reset_counter(&red.counter[1]);
   }

@@ -17,6 +17,7 @@
 
 #include "dd.h"
 #include "dd_kernels.h"
+#include "dd_persistent.h"
 
 using namespace dd;
 
@@ -89,6 +90,10 @@ struct dd_ctx {
   size_t bytes = 0;
   int use_mfma = 1;
   int direction_kernel = 0;   // 1: keep p in memory, update it with its own kernel
+  int num_cu = 0;
+  unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
+  long long spin_limit = 1ll << 20;
+  int last_launch = DD_LAUNCH_KERNELS;
   // optional per-phase kernel timing with HIP events (dd_set_timing)
   unsigned timing_mask = 0;
   std::vector<hipEvent_t> tev;          // event pool, pairs (start, stop)
@@ -227,8 +232,12 @@ template <int C, typename VT>
 void launch_csr(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *val,
                 Src x, int ld, const double *base, double sign, double *out) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL((k_csr_rows<C, VT>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
-                     c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
+  if (x.z)
+    hipLaunchKernelGGL((k_csr_rows<C, VT, true>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
+                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
+  else
+    hipLaunchKernelGGL((k_csr_rows<C, VT, false>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
+                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
 }
 
 template <typename VT>
@@ -270,20 +279,24 @@ template <int C, typename VT>
 void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                   const double *base, double c1, double c2, double *out, int dot, double *pout) {
   if (c->n_gamma <= 0) return;
-  hipLaunchKernelGGL((k_gamma_rows<C, VT>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
-                     c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
-                     base, c1, c2, out, dot, pout, c->red, c->st);
+  if (p.z)
+    hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
+                       c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
+                       base, c1, c2, out, dot, pout, c->red, c->st);
+  else
+    hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
+                       c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
+                       base, c1, c2, out, dot, pout, c->red, c->st);
 }
 
 template <typename VT>
 void gamma_rows(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                 const double *base, double c1, double c2, double *out, int dot, double *pout) {
-  switch (std::min(ld, 16)) {
+  switch (std::min(ld, 8)) {
     case 1: launch_gamma<1, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
     case 2: launch_gamma<2, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
     case 4: launch_gamma<4, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
-    case 8: launch_gamma<8, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
-    default: launch_gamma<16, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    default: launch_gamma<8, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
   }
 }
 
@@ -463,7 +476,47 @@ struct CoreOpts {
   int precond;
   int apply;
   int check_every;
+  int launch;
 };
+
+// ------------------------------------------------------ persistent launch --
+template <int C, typename VT, typename MT, typename AT>
+dd_status launch_persistent_t(dd_ctx *c, PArgs<VT, MT> &a) {
+  auto kern = k_pcg_persistent<C, VT, MT, AT>;
+  int nb = 0;
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kPBlock, 0));
+  if (nb < 1) return fail(c, DD_EHIP, "persistent kernel does not fit on a compute unit");
+  int grid = nb * c->num_cu;
+  HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->stream));
+  void *args[] = {(void *)&a};
+  HIPCHK(c, hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(kPBlock), args, 0,
+                                       c->stream));
+  return DD_OK;
+}
+
+template <typename VT, typename MT, typename AT>
+dd_status launch_persistent(dd_ctx *c, int prec, int ld, int nrhs, int max_it, int precond,
+                            double *x, double *pA, double *pB) {
+  const Ops &op = c->op[prec];
+  Work &w = c->w;
+  PArgs<VT, MT> a;
+  a.NI = c->NI; a.nG = c->n_gamma; a.ld = ld; a.nrhs = nrhs; a.max_it = max_it;
+  a.use_precond = precond;
+  a.ig_ptr = c->d_ig_ptr; a.ig_col = c->d_ig_col; a.ig_val = (const VT *)op.ig_val;
+  a.kinv = (const MT *)op.kinv; a.koff = c->d_koff; a.ioff = c->d_ioff; a.ni = c->d_ni;
+  a.rowsub = c->d_rowsub;
+  a.g_ptr = c->d_g_ptr; a.g_split = c->d_g_split; a.g_col = c->d_g_col; a.g_val = (const VT *)op.g_val;
+  a.dinv = op.dinv;
+  a.x = x; a.r = w.rG; a.z = w.zG; a.pA = pA; a.pB = pB; a.q = w.qG; a.y = w.yI; a.w = w.wI;
+  a.red = c->red; a.st = c->st; a.go = c->st.flag + 1;
+  a.bar = GridBar{c->d_bar, c->d_bar + 1, c->d_bar + 2, c->spin_limit};
+  switch (std::min(ld, 8)) {
+    case 1: return launch_persistent_t<1, VT, MT, AT>(c, a);
+    case 2: return launch_persistent_t<2, VT, MT, AT>(c, a);
+    case 4: return launch_persistent_t<4, VT, MT, AT>(c, a);
+    default: return launch_persistent_t<8, VT, MT, AT>(c, a);
+  }
+}
 
 // One substructuring solve on DD-layout data:
 //   g = bG - K_GI K_II^{-1} bI;  CG on S x = g until ||r_c||^2 <= stop2[c];
@@ -486,6 +539,22 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
                        op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr,
                        c->direction_kernel);
   HIPCHK(c, hipGetLastError());
+  if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
+    dd_status ps = prec == DD_FP64
+                       ? launch_persistent<double, double, double>(c, prec, ld, nrhs, o.max_it, o.precond, uG, pA, pB)
+                       : launch_persistent<float, float, float>(c, prec, ld, nrhs, o.max_it, o.precond, uG, pA, pB);
+    if (ps != DD_OK) return ps;
+    unsigned abort_flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&abort_flag, c->d_bar + 2, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (abort_flag) return fail(c, DD_EHIP, "persistent CG kernel aborted: a grid barrier wait exceeded its limit");
+    c->last_launch = DD_LAUNCH_PERSISTENT;
+    kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
+    interior_solve(c, prec, o.apply, w.yI, uI, ld);
+    HIPCHK(c, hipGetLastError());
+    return DD_OK;
+  }
+  c->last_launch = DD_LAUNCH_KERNELS;
   // host polling with a lag: iteration `it` writes h_nact[it % nslots] = active + 1
   const int lag = std::min(8, std::max(1, o.check_every > 0 ? o.check_every : 2));
   std::vector<int> ring_it(c->nslots, -1);
@@ -496,6 +565,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     ++it;
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
     const bool dk = c->direction_kernel != 0;
+    (void)0;
     Src P = dk ? plain(pA) : Src{nullptr, w.zG, pA, c->st.beta};
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     {
@@ -625,6 +695,11 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   c->ldmax = next_pow2(max_nrhs);
   if (const char *e = getenv("DD_NO_MFMA")) c->use_mfma = atoi(e) ? 0 : 1;
   if (const char *e = getenv("DD_DIRECTION_KERNEL")) c->direction_kernel = atoi(e) ? 1 : 0;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (c->num_cu <= 0) c->num_cu = 1;
+  }
   // host-side structure
   c->ni.resize(c->n_sub);
   c->ioff.resize(c->n_sub);
@@ -729,6 +804,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if ((s = dalloc(c, &c->red.part1, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bad, 1)) != DD_OK) return bail(s);
   if (hipMemset(c->red.counter, 0, 8 * sizeof(unsigned)) != hipSuccess) {
     c->err = "hipMemset failed";
@@ -849,7 +925,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in (0,1)");
   const int L = next_pow2(nrhs);
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
-              o.check_every};
+              o.check_every, o.launch == DD_LAUNCH_PERSISTENT ? DD_LAUNCH_PERSISTENT : DD_LAUNCH_KERNELS};
   Work &w = c->w;
   // gather b into the DD layout
   hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->NI * L, 256))), dim3(256), 0,

@@ -156,3 +156,23 @@ def test_batch_invariance(prec):
         uj = s.solve(to_dev(b[:, j:j + 1]), prec=prec, opts=opts).u.cpu().numpy()
         assert np.array_equal(uj[0], ub[j]), j
     s.close()
+
+
+@pytest.mark.parametrize("name", ["1d-ragged", "2d-const", "2d-pd"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_persistent_launch_matches_kernels(name, prec):
+    """One cooperative persistent kernel for the CG loop gives the same
+    solution, bit for bit, as one launch per phase."""
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case persistent {name} prec={prec}", flush=True)
+    nrhs = b.shape[1]
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s.factor(prec)
+    o1 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS)
+    o2 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_PERSISTENT)
+    r1 = s.solve(to_dev(b), prec=prec, opts=o1)
+    r2 = s.solve(to_dev(b), prec=prec, opts=o2)
+    assert [i["iters"] for i in r1.info] == [i["iters"] for i in r2.info]
+    assert np.array_equal(r1.u.cpu().numpy(), r2.u.cpu().numpy())
+    s.close()
