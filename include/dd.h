@@ -91,7 +91,8 @@ typedef enum {
 typedef enum {
   DD_LAUNCH_AUTO = 0,
   DD_LAUNCH_KERNELS = 1,     /* one kernel launch per phase, host polls convergence */
-  DD_LAUNCH_PERSISTENT = 2   /* one cooperative kernel runs the whole CG loop */
+  DD_LAUNCH_PERSISTENT = 2,  /* one cooperative kernel runs the whole CG loop */
+  DD_LAUNCH_GRAPH = 3        /* check_every CG iterations captured in one hipGraph, replayed */
 } dd_launch;
 
 typedef struct {
@@ -161,6 +162,60 @@ dd_status dd_get_factor(dd_ctx *ctx, dd_precision prec, int32_t k, double *out);
 
 /* Copy diag(S) (n_gamma doubles) to host memory (diagnostic entry). */
 dd_status dd_get_schur_diag(dd_ctx *ctx, dd_precision prec, double *out);
+
+/* Schedule chosen by the autotuner (dd_autotune). */
+typedef struct {
+  int32_t apply;             /* dd_apply */
+  int32_t launch;            /* dd_launch */
+  int32_t direction_kernel;  /* 1: direction kept in memory by its own kernel, 0: formed on the fly */
+  int32_t check_every;       /* polling lag (kernels) or iterations per graph (graph) */
+  double ms_per_solve;       /* measured time of one solve of the batch with this schedule */
+  int32_t candidates;        /* schedules timed */
+} dd_tune_result;
+
+/* Autotuner: time every candidate schedule of the CG loop on this context and
+ * precision for a batch of nrhs synthetic right-hand sides (launch mode,
+ * interior-solve variant, direction handling, polling lag), keep the fastest,
+ * and use it for later dd_solve calls of that precision and batch width whose
+ * opts leave apply and launch at AUTO.  base: tolerances used while timing
+ * (NULL = defaults).  The factors of `prec` must exist.  out may be NULL. */
+dd_status dd_autotune(dd_ctx *ctx, dd_precision prec, int32_t nrhs, const dd_solve_opts *base,
+                      dd_tune_result *out);
+
+/* ------------------------------------------------------------------------
+ * Continuous batching (serving).  A context keeps a resident CG state with up
+ * to max_nrhs slots (right-hand-side columns).  Requests are admitted into
+ * free slots between CG iterations, every slot iterates independently (its
+ * arithmetic does not depend on the other slots, so a result is the same
+ * alone and in a mix), finished slots are retired, and their slots reused.
+ * While a batch is open, dd_solve / dd_autotune on the context return
+ * DD_ESTATE.  Slot states: */
+enum { DD_SLOT_FREE = 0, DD_SLOT_RUNNING = 1, DD_SLOT_DONE = 2, DD_SLOT_FALLBACK = 3 };
+/* DD_SLOT_DONE: result ready (converged or at the iteration cap, see info);
+ * DD_SLOT_FALLBACK: mixed-precision refinement stalled; the request should be
+ * solved with FP64 factors (e.g. dd_solve on another context). */
+
+/* Open a batch: precision and tolerances (opts) for every slot. */
+dd_status dd_batch_begin(dd_ctx *ctx, dd_precision prec, const dd_solve_opts *opts);
+
+/* Admit ncol right-hand sides (b_dev: D, column-major n_dof x ncol, leading
+ * dimension ld) into the free slots slots[0..ncol) (H). */
+dd_status dd_batch_admit(dd_ctx *ctx, const int32_t *slots, int32_t ncol, const double *b_dev,
+                         int32_t ld);
+
+/* Advance every running slot by up to iters CG iterations, then finish,
+ * refine or restart the slots whose CG converged.  state_host (H, max_nrhs
+ * entries, may be NULL) receives the slot states. */
+dd_status dd_batch_step(dd_ctx *ctx, int32_t iters, int32_t *state_host);
+
+/* Copy the solutions of DONE slots to u_dev (D, column-major n_dof x ncol,
+ * leading dimension ld), fill info_host (H, ncol entries, may be NULL) and
+ * free the slots. */
+dd_status dd_batch_retire(dd_ctx *ctx, const int32_t *slots, int32_t ncol, double *u_dev,
+                          int32_t ld, dd_solve_info *info_host);
+
+/* Close the batch (all slots are freed). */
+dd_status dd_batch_end(dd_ctx *ctx);
 
 /* Per-phase kernel timing of the CG loop (diagnostic entry for profiling).
  * Phases: one launch each per CG iteration. */

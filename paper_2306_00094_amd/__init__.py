@@ -21,14 +21,16 @@ LIB_PATH = os.path.join(HERE, "_dd.so")
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_ENOTSPD, DD_ENOCONV, DD_EHIP, DD_ESTATE = range(7)
 DD_FP64, DD_MIXED = 0, 1
 DD_APPLY_AUTO, DD_APPLY_INV, DD_APPLY_TRSM = 0, 1, 2
-DD_LAUNCH_AUTO, DD_LAUNCH_KERNELS, DD_LAUNCH_PERSISTENT = 0, 1, 2
+DD_LAUNCH_AUTO, DD_LAUNCH_KERNELS, DD_LAUNCH_PERSISTENT, DD_LAUNCH_GRAPH = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_ENOTSPD", 4: "DD_ENOCONV",
                 5: "DD_EHIP", 6: "DD_ESTATE"}
 
 EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solve",
-            "dd_schur_apply", "dd_get_factor", "dd_get_schur_diag", "dd_set_timing",
-            "dd_get_timing", "dd_last_error", "dd_destroy"]
+            "dd_schur_apply", "dd_get_factor", "dd_get_schur_diag", "dd_autotune",
+            "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
+            "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy"]
+DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
 DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE = range(4)
 DD_NPHASES = 4
 
@@ -63,6 +65,12 @@ class dd_solve_info(ctypes.Structure):
                 ("rel_resid", ctypes.c_double)]
 
 
+class dd_tune_result(ctypes.Structure):
+    _fields_ = [("apply", ctypes.c_int32), ("launch", ctypes.c_int32),
+                ("direction_kernel", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("ms_per_solve", ctypes.c_double), ("candidates", ctypes.c_int32)]
+
+
 class DDError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -92,6 +100,14 @@ def load_library(path: str = LIB_PATH):
     lib.dd_schur_apply.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_int32]
     lib.dd_get_factor.argtypes = [vp, ctypes.c_int, ctypes.c_int32, _f64p]
     lib.dd_get_schur_diag.argtypes = [vp, ctypes.c_int, _f64p]
+    lib.dd_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(dd_solve_opts),
+                                ctypes.POINTER(dd_tune_result)]
+    lib.dd_batch_begin.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dd_solve_opts)]
+    lib.dd_batch_admit.argtypes = [vp, _i32p, ctypes.c_int32, vp, ctypes.c_int32]
+    lib.dd_batch_step.argtypes = [vp, ctypes.c_int32, _i32p]
+    lib.dd_batch_retire.argtypes = [vp, _i32p, ctypes.c_int32, vp, ctypes.c_int32,
+                                    ctypes.POINTER(dd_solve_info)]
+    lib.dd_batch_end.argtypes = [vp]
     lib.dd_set_timing.argtypes = [vp, ctypes.c_uint32]
     lib.dd_get_timing.argtypes = [vp, _f64p, ctypes.POINTER(ctypes.c_int64)]
     lib.dd_last_error.argtypes = [vp]
@@ -99,7 +115,9 @@ def load_library(path: str = LIB_PATH):
     lib.dd_destroy.argtypes = [vp]
     lib.dd_destroy.restype = None
     for name in ("dd_footprint", "dd_setup", "dd_factor", "dd_solve", "dd_schur_apply",
-                 "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing"):
+                 "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
+                 "dd_autotune", "dd_batch_begin", "dd_batch_admit", "dd_batch_step",
+                 "dd_batch_retire", "dd_batch_end"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -223,6 +241,52 @@ def dd_get_schur_diag(ctx, prec: int, n_gamma: int) -> np.ndarray:
     return out
 
 
+def dd_autotune(ctx, prec: int, nrhs: int, opts: dd_solve_opts | None = None) -> dict:
+    """Time the candidate CG schedules and keep the fastest (used by AUTO solves)."""
+    lib = load_library()
+    r = dd_tune_result()
+    _check(lib, lib.dd_autotune(ctx, prec, nrhs, ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(r)), ctx)
+    return dict(apply=r.apply, launch=r.launch, direction_kernel=r.direction_kernel,
+                check_every=r.check_every, ms_per_solve=r.ms_per_solve, candidates=r.candidates)
+
+
+def dd_batch_begin(ctx, prec: int, opts: dd_solve_opts | None = None) -> None:
+    lib = load_library()
+    _check(lib, lib.dd_batch_begin(ctx, prec, ctypes.byref(opts) if opts is not None else None), ctx)
+
+
+def _i32arr(v):
+    a = (ctypes.c_int32 * len(v))(*[int(x) for x in v])
+    return a
+
+
+def dd_batch_admit(ctx, slots, b, ld: int) -> None:
+    """b: torch float64 CUDA tensor with len(slots) right-hand sides (column-major, ld)."""
+    lib = load_library()
+    _check(lib, lib.dd_batch_admit(ctx, _i32arr(slots), len(slots), _dev_ptr(b), ld), ctx)
+
+
+def dd_batch_step(ctx, iters: int, max_nrhs: int) -> list:
+    lib = load_library()
+    st = (ctypes.c_int32 * max_nrhs)()
+    _check(lib, lib.dd_batch_step(ctx, iters, st), ctx)
+    return list(st)
+
+
+def dd_batch_retire(ctx, slots, u, ld: int) -> list:
+    lib = load_library()
+    infos = (dd_solve_info * len(slots))()
+    _check(lib, lib.dd_batch_retire(ctx, _i32arr(slots), len(slots), _dev_ptr(u), ld, infos), ctx)
+    return [dict(iters=i.iters, refine_steps=i.refine_steps, used_fallback=i.used_fallback,
+                 converged=i.converged, rel_resid=i.rel_resid) for i in infos]
+
+
+def dd_batch_end(ctx) -> None:
+    lib = load_library()
+    _check(lib, lib.dd_batch_end(ctx), ctx)
+
+
 def dd_set_timing(ctx, phase_mask: int) -> None:
     lib = load_library()
     _check(lib, lib.dd_set_timing(ctx, phase_mask), ctx)
@@ -283,6 +347,9 @@ class Solver:
             u = torch.empty((nrhs, ld), dtype=torch.float64, device=b.device)
         st, info = dd_solve(self.ctx, prec, b, u, nrhs, ld, opts, raise_on_noconv)
         return SolveResult(u[:, :self.n_dof], st, info)
+
+    def autotune(self, prec: int = DD_FP64, nrhs: int = 1, opts: dd_solve_opts | None = None) -> dict:
+        return dd_autotune(self.ctx, prec, nrhs, opts)
 
     def schur_apply(self, p, prec: int = DD_FP64):
         torch = self.torch

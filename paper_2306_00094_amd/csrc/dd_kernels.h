@@ -358,8 +358,7 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
 // (CG step length; breakdown when p^T q <= 0).
 constexpr int kGRows = 16;
 template <int C, typename VT, bool OTF>
-__global__ void __launch_bounds__(kGRows * kWave)
-k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
+__device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
@@ -428,6 +427,18 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
   if (threadIdx.x == 0) reset_counter(&red.counter[0]);
 }
 
+template <int C, typename VT, bool OTF>
+__global__ void __launch_bounds__(kGRows * kWave)
+k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
+             const int *__restrict__ col, const VT *__restrict__ val, Src p,
+             const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
+             double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
+             RedBuf red, ColState st) {
+  gamma_rows_body<C, VT, OTF>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2, out, dot,
+                              pout, red, st);
+}
+
+
 // ----------------------------------------------------------- CG updates --
 // Chunk of kRowsE interface rows x ld columns per workgroup.
 // mode 0 (init):   x = 0, r given, z = D^{-1} r, p = 0 (so the first
@@ -441,7 +452,8 @@ __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
-            int use_precond, int *__restrict__ host_nact, int init_p_is_z) {
+            int use_precond, int *__restrict__ host_nact, int init_p_is_z,
+            const int *__restrict__ mask = nullptr) {
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ int lflag;
   const int row0 = blockIdx.x * kRowsE;
@@ -453,19 +465,21 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     double rz = 0.0;
     if (j < nrows) {
       size_t o = (size_t)j * ld + c;
-      double rv = r[o];
-      bool act = mode == 0 ? true : (st.active[c] != 0);
+      bool init = mode == 0 || (mode == 2 && mask[c]);
+      double rv = (mode == 2 && init) ? q[o] : r[o];     // mode 2: new residual in q
+      if (mode == 2 && init) r[o] = rv;
+      bool act = init ? true : (mode == 1 && st.active[c] != 0);
       if (mode == 1 && act) {
         double a = st.alpha[c];
         x[o] = fma(a, p[o], x[o]);
         rv = fma(-a, q[o], rv);
         r[o] = rv;
       }
-      if (mode == 0) x[o] = 0.0;
+      if (init) x[o] = 0.0;
       double zv = use_precond ? dinv[j] * rv : rv;
       if (act) z[o] = zv;
       else zv = z[o];
-      if (mode == 0) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
+      if (init) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
       rz = rv * zv;
     }
     lds[lr * ld + c] = rz;
@@ -494,18 +508,18 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     double rz, rr;
     partials_sum2(red.part0, red.part1, gridDim.x, ld, c, rz, rr);
     if (lane == 0) {
-      if (mode == 0) {
+      if (mode == 0 || (mode == 2 && mask[c])) {
         st.rz[c] = rz;
         st.iters[c] = 0;
         st.beta[c] = 0.0;
-        st.active[c] = (c < nrhs && rr > st.stop2[c]) ? 1 : 0;
-      } else if (st.active[c]) {
+        st.active[c] = ((mode == 2 || c < nrhs) && rr > st.stop2[c]) ? 1 : 0;
+      } else if (mode == 1 && st.active[c]) {
         st.iters[c] += 1;
         st.beta[c] = rz / st.rz[c];
         st.rz[c] = rz;
         if (rr <= st.stop2[c]) st.active[c] = 0;
       }
-      st.nrm2[c] = rr;
+      if (mode != 2 || mask[c]) st.nrm2[c] = rr;
     }
   }
   __syncthreads();
@@ -597,6 +611,69 @@ k_colnorm2(int nrows, int ld, const double *__restrict__ v, RedBuf red, double *
   }
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(&red.counter[2]);
+}
+
+// Deterministic synthetic right-hand sides for the autotuner: entry (i, c) of
+// an n x nrhs column-major block, uniform in [-1, 1) from a 64-bit mix of
+// (seed, c, i) (SplitMix64 finaliser).
+__global__ void k_fill_rhs(int n, int nrhs, int ld, unsigned long long seed, double *__restrict__ b) {
+  size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e / n), i = (int)(e % n);
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (1ull + (unsigned long long)c * n + i);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    b[(size_t)c * ld + i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+// Column moves for continuous batching (column-major user blocks, DD-layout
+// slots): dst[i*ld + slot[j]] = src[j*lds + map[i]]  (gather),
+// dst[j*ldd + map[i]] = src[i*ld + slot[j]]           (scatter).
+__global__ void k_gather_cols(int n, const int *__restrict__ map, const double *__restrict__ src,
+                              int lds, int ncol, const int *__restrict__ slot, int ld,
+                              double *__restrict__ dst) {
+  size_t total = (size_t)n * ncol;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int j = (int)(e / n), i = (int)(e % n);
+    dst[(size_t)i * ld + slot[j]] = src[(size_t)j * lds + map[i]];
+  }
+}
+
+__global__ void k_scatter_cols(int n, const int *__restrict__ map, const double *__restrict__ src,
+                               int ld, int ncol, const int *__restrict__ slot,
+                               double *__restrict__ dst, int ldd) {
+  size_t total = (size_t)n * ncol;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int j = (int)(e / n), i = (int)(e % n);
+    dst[(size_t)j * ldd + map[i]] = src[(size_t)i * ld + slot[j]];
+  }
+}
+
+// y[:, c] = a * y[:, c] + x[:, c] for the masked columns (a = 0: copy, x = null: scale)
+__global__ void k_cols_update(size_t n, int ld, double a, const double *__restrict__ x,
+                              double *__restrict__ y, const int *__restrict__ mask) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e % ld);
+    if (mask[c]) y[e] = a * y[e] + (x ? x[e] : 0.0);
+  }
+}
+
+// Move a DD-layout block from column stride lo to column stride ln (ln, lo
+// powers of two; columns >= min(lo, ln) of the destination are zeroed).
+__global__ void k_relayout(int n, int lo, int ln, const double *__restrict__ src,
+                           double *__restrict__ dst) {
+  size_t total = (size_t)n * ln;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int i = (int)(e / ln), c = (int)(e % ln);
+    dst[e] = c < lo ? src[(size_t)i * lo + c] : 0.0;
+  }
 }
 
 // ------------------------------------------------------------- factor --

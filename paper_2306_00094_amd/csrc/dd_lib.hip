@@ -94,6 +94,28 @@ struct dd_ctx {
   unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
   long long spin_limit = 1ll << 20;
   int last_launch = DD_LAUNCH_KERNELS;
+  struct GraphEntry {
+    int prec, ld, apply, precond, dk, iters;
+    double *x;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool capturing = false;
+  // autotuned schedules per precision and batch width (log2)
+  struct Tuned { bool set = false; int apply = 0, launch = 0, dk = 0, check_every = 0; double ms = 0; };
+  Tuned tuned[2][7];
+  // continuous batching
+  struct Batch {
+    bool on = false;
+    int prec = 0;
+    dd_solve_opts o{};
+    int ld = 1;
+    int state[kMaxLd] = {0}, its[kMaxLd] = {0}, steps[kMaxLd] = {0}, conv[kMaxLd] = {0};
+    int stall[kMaxLd] = {0};
+    double bn2[kMaxLd] = {0}, rn2[kMaxLd] = {0}, prev[kMaxLd] = {0}, stop2[kMaxLd] = {0};
+    int *d_mask = nullptr, *d_slots = nullptr;
+  } batch;
+  hipStream_t cap_stream = nullptr;   // capture only (the legacy default stream cannot capture)
   // optional per-phase kernel timing with HIP events (dd_set_timing)
   unsigned timing_mask = 0;
   std::vector<hipEvent_t> tev;          // event pool, pairs (start, stop)
@@ -279,14 +301,15 @@ template <int C, typename VT>
 void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                   const double *base, double c1, double c2, double *out, int dot, double *pout) {
   if (c->n_gamma <= 0) return;
-  if (p.z)
-    hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
-                       c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
-                       base, c1, c2, out, dot, pout, c->red, c->st);
-  else
-    hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), dim3(grid_for(c->n_gamma, kGRows)), dim3(kGRows * kWave), 0,
-                       c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col, val, p, z, ld,
-                       base, c1, c2, out, dot, pout, c->red, c->st);
+  dim3 g(grid_for(c->n_gamma, kGRows)), b(kGRows * kWave);
+  {
+    if (p.z)
+      hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+    else
+      hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+  }
 }
 
 template <typename VT>
@@ -438,7 +461,8 @@ struct PhaseTimer {
   dd_ctx *c;
   int phase;
   bool on;
-  PhaseTimer(dd_ctx *c_, int ph) : c(c_), phase(ph), on((c_->timing_mask >> ph) & 1u) {
+  PhaseTimer(dd_ctx *c_, int ph)
+      : c(c_), phase(ph), on(((c_->timing_mask >> ph) & 1u) && !c_->capturing) {
     if (!on) return;
     if (c->tev_used + 2 > c->tev.size()) {
       for (int i = 0; i < 256; ++i) {
@@ -561,12 +585,12 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   int it = 0;
   int observed = 0;       // last iteration whose result the host has seen
   bool stop = c->n_gamma == 0;
-  while (!stop && it < o.max_it) {
-    ++it;
+  // one CG iteration (S p, alpha, updates, beta); nact_dst receives
+  // (active columns + 1) from the update kernel when non-null
+  auto iteration = [&](double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
     const bool dk = c->direction_kernel != 0;
-    (void)0;
-    Src P = dk ? plain(pA) : Src{nullptr, w.zG, pA, c->st.beta};
+    Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     {
       PhaseTimer t(c, DD_PHASE_KIG);
@@ -578,34 +602,98 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     {
       PhaseTimer t(c, DD_PHASE_GAMMA);
-      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, dk ? nullptr : pB);
+      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, dk ? nullptr : pB_);
     }
-    int slot = it % c->nslots;
-    c->h_nact[slot] = 0;
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
-                         op.dinv, uG, w.rG, w.zG, dk ? pA : pB, w.qG, c->red, c->st, o.precond,
-                         c->h_nact_dev + slot, 0);
+                         op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, c->red, c->st, o.precond,
+                         nact_dst, 0);
     }
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,
-                         w.zG, pA, c->st);
+                         w.zG, pA_, c->st);
     } else {
-      std::swap(pA, pB);
+      std::swap(pA_, pB_);
     }
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
-    ring_it[slot] = it;
-    // look at iteration it - lag (blocking), never more than nslots in flight
-    int target = it - lag;
-    while (observed < target) {
-      int s2 = (observed + 1) % c->nslots;
-      HIPCHK(c, hipEventSynchronize(c->ev[s2]));
-      ++observed;
-      int v = ((volatile int *)c->h_nact)[s2];
-      if (v == 1) { stop = true; break; }
+    return DD_OK;
+  };
+  if (o.launch == DD_LAUNCH_GRAPH && !stop) {
+    // G iterations per graph (even, so the direction buffers return to place)
+    int G = std::max(2, std::min(32, o.check_every > 0 ? o.check_every : 4));
+    G += G & 1;
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : c->graphs)
+      if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
+          g.dk == c->direction_kernel && g.iters == G && g.x == uG)
+        exec = g.exec;
+    if (!exec) {
+      if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipStream_t user = c->stream;
+      c->stream = c->cap_stream;     // kernels are recorded, not run
+      hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (eb != hipSuccess) {
+        c->stream = user;
+        return fail(c, DD_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+      }
+      c->capturing = true;
+      dd_status cs = DD_OK;
+      double *qa = pA, *qb = pB;
+      for (int i = 0; i < G && cs == DD_OK; ++i)
+        cs = iteration(qa, qb, i == G - 1 ? c->h_nact_dev : nullptr);
+      c->capturing = false;
+      hipGraph_t graph = nullptr;
+      hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
+      c->stream = user;
+      if (cs != DD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cs;
+      }
+      if (ee != hipSuccess)
+        return fail(c, DD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+      ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ee != hipSuccess)
+        return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
+      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, uG, exec});
+    }
+    // replay; look at the result of launch n - 1 while launch n runs.  The
+    // number of active columns only decreases, so a later value is as good.
+    ((volatile int *)c->h_nact)[0] = 0;
+    int launches = 0;
+    const int max_launch = (o.max_it + G - 1) / G;
+    while (launches < max_launch) {
+      HIPCHK(c, hipGraphLaunch(exec, c->stream));
+      HIPCHK(c, hipEventRecord(c->ev[launches % c->nslots], c->stream));
+      ++launches;
+      if (launches >= 2) {
+        HIPCHK(c, hipEventSynchronize(c->ev[(launches - 2) % c->nslots]));
+        if (((volatile int *)c->h_nact)[0] == 1) break;
+      }
+    }
+    c->last_launch = DD_LAUNCH_GRAPH;
+  } else {
+    while (!stop && it < o.max_it) {
+      ++it;
+      int slot = it % c->nslots;
+      c->h_nact[slot] = 0;
+      TRY(iteration(pA, pB, c->h_nact_dev + slot));
+      HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
+      ring_it[slot] = it;
+      // look at iteration it - lag (blocking), never more than nslots in flight
+      int target = it - lag;
+      while (observed < target) {
+        int s2 = (observed + 1) % c->nslots;
+        HIPCHK(c, hipEventSynchronize(c->ev[s2]));
+        ++observed;
+        int v = ((volatile int *)c->h_nact)[s2];
+        if (v == 1) {
+          stop = true;
+          break;
+        }
+      }
     }
   }
   // back substitution (eq. backwardSubstitution): uI = K_II^{-1} (bI - K_IG uG)
@@ -669,6 +757,8 @@ void dd_destroy(dd_ctx *c) {
   for (void *p : c->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->h_nact) (void)hipHostFree(c->h_nact);
   delete c;
 }
@@ -805,6 +895,8 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->batch.d_mask, kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->batch.d_slots, kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bad, 1)) != DD_OK) return bail(s);
   if (hipMemset(c->red.counter, 0, 8 * sizeof(unsigned)) != hipSuccess) {
     c->err = "hipMemset failed";
@@ -878,6 +970,347 @@ dd_status dd_get_factor(dd_ctx *c, dd_precision prec, int32_t k, double *out) {
   return DD_OK;
 }
 
+dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve_opts *base,
+                      dd_tune_result *out) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (c->batch.on) return fail(c, DD_ESTATE, "a batch is open on this context");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  if (nrhs < 1 || nrhs > c->max_nrhs) return fail(c, DD_EINVAL, "nrhs out of [1, max_nrhs]");
+  dd_solve_opts o;
+  if (base) o = *base; else dd_default_opts(&o);
+  double *b = nullptr, *u = nullptr;
+  size_t n = (size_t)c->n_dof * nrhs;
+  HIPCHK(c, hipMalloc(&b, n * sizeof(double)));
+  if (hipMalloc(&u, n * sizeof(double)) != hipSuccess) {
+    (void)hipFree(b);
+    return fail(c, DD_ENOMEM, "autotune buffers");
+  }
+  struct Free2 { double *a, *b; ~Free2() { (void)hipFree(a); (void)hipFree(b); } } fr{b, u};
+  hipLaunchKernelGGL(k_fill_rhs, dim3(256), dim3(256), 0, c->stream, c->n_dof, nrhs, c->n_dof,
+                     0x5eedull, b);
+  HIPCHK(c, hipGetLastError());
+  struct Cand { int apply, launch, dk, ce; };
+  std::vector<Cand> cands;
+  for (int dk = 0; dk < 2; ++dk) {
+    for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, dk, lag});
+    for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, dk, g});
+  }
+  cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2});
+  cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0});
+  const int saved_dk = c->direction_kernel;
+  int lg = 0;
+  while ((1 << lg) < next_pow2(nrhs)) ++lg;
+  c->tuned[prec][lg].set = false;
+  double best = 1e30;
+  Cand bc = cands[0];
+  for (const Cand &cd : cands) {
+    dd_solve_opts oc = o;
+    oc.apply = cd.apply;
+    oc.launch = cd.launch;
+    oc.check_every = cd.ce;
+    c->direction_kernel = cd.dk;
+    dd_status s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);   // warm-up (captures graphs)
+    if (s != DD_OK && s != DD_ENOCONV) continue;
+    const int reps = 3;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps && s == DD_OK; ++r) s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);
+    auto t1 = std::chrono::steady_clock::now();
+    if (s != DD_OK && s != DD_ENOCONV) continue;
+    double ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / reps;
+    if (ms < best) {
+      best = ms;
+      bc = cd;
+    }
+  }
+  c->direction_kernel = saved_dk;
+  c->err.clear();
+  auto &t = c->tuned[prec][lg];
+  t.set = true;
+  t.apply = bc.apply;
+  t.launch = bc.launch;
+  t.dk = bc.dk;
+  t.check_every = bc.ce;
+  t.ms = best;
+  if (out) {
+    out->apply = bc.apply;
+    out->launch = bc.launch;
+    out->direction_kernel = bc.dk;
+    out->check_every = bc.ce;
+    out->ms_per_solve = best;
+    out->candidates = (int)cands.size();
+  }
+  return DD_OK;
+}
+
+// ------------------------------------------------------------ batching --
+namespace {
+
+unsigned grid1d(size_t n) { return std::max(1u, std::min(4096u, grid_for(n, 256))); }
+
+dd_status batch_mask(dd_ctx *c, const int *m) {
+  HIPCHK(c, hipMemcpyAsync(c->batch.d_mask, m, kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  return DD_OK;
+}
+
+// Change the column stride of the resident vectors (results per column are
+// unaffected: the arithmetic of a column does not depend on the stride).
+dd_status batch_relayout(dd_ctx *c, int ln) {
+  auto &B = c->batch;
+  if (ln == B.ld) return DD_OK;
+  Work &w = c->w;
+  double **gv[] = {&w.bG, &w.uG, &w.tG, &w.rG, &w.zG, &w.pG, &w.dG};
+  double **iv[] = {&w.bI, &w.uI, &w.tI};
+  for (double **v : gv) {
+    hipLaunchKernelGGL(k_relayout, dim3(grid1d((size_t)c->n_gamma * ln)), dim3(256), 0, c->stream,
+                       c->n_gamma, B.ld, ln, *v, w.qG);
+    std::swap(*v, w.qG);
+  }
+  for (double **v : iv) {
+    hipLaunchKernelGGL(k_relayout, dim3(grid1d((size_t)c->NI * ln)), dim3(256), 0, c->stream, c->NI,
+                       B.ld, ln, *v, w.yI);
+    std::swap(*v, w.yI);
+  }
+  HIPCHK(c, hipGetLastError());
+  B.ld = ln;
+  return DD_OK;
+}
+
+int batch_need_ld(const dd_ctx *c) {
+  int hi = 0;
+  for (int j = 0; j < kMaxLd; ++j)
+    if (c->batch.state[j] != DD_SLOT_FREE) hi = j + 1;
+  return next_pow2(std::max(1, hi));
+}
+
+// Start the CG of the masked columns on the right-hand side (rI, rG):
+// condensation, then the masked CG initialisation; the CG right-hand side's
+// interior part is kept in tI for the back substitution.
+dd_status batch_start_cg(dd_ctx *c, const int *mask, const double *rI, const double *rG) {
+  auto &B = c->batch;
+  Work &w = c->w;
+  const Ops &op = c->op[B.prec];
+  const int ld = B.ld;
+  TRY(batch_mask(c, mask));
+  if (rI != w.tI)
+    hipLaunchKernelGGL(k_cols_update, dim3(grid1d((size_t)c->NI * ld)), dim3(256), 0, c->stream,
+                       (size_t)c->NI * ld, ld, 0.0, rI, w.tI, B.d_mask);
+  interior_solve(c, B.prec, DD_APPLY_INV, w.tI, w.wI, ld);
+  gamma_apply(c, B.prec, plain(nullptr), w.wI, ld, rG, 0.0, -1.0, w.qG);
+  std::vector<double> st2(B.stop2, B.stop2 + kMaxLd);
+  HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+  if (c->n_gamma > 0)
+    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(c->n_gamma, kRowsE)), dim3(kBlock), 0, c->stream, 2,
+                       c->n_gamma, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, c->red, c->st,
+                       B.o.precond, (int *)nullptr, 0, (const int *)B.d_mask);
+  HIPCHK(c, hipGetLastError());
+  return DD_OK;
+}
+
+}  // namespace
+
+dd_status dd_batch_begin(dd_ctx *c, dd_precision prec, const dd_solve_opts *opts) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (c->batch.on) return fail(c, DD_ESTATE, "a batch is already open");
+  if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
+  if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
+  auto &B = c->batch;
+  int *dm = B.d_mask, *ds = B.d_slots;
+  B = dd_ctx::Batch();
+  B.d_mask = dm;
+  B.d_slots = ds;
+  if (opts) B.o = *opts; else dd_default_opts(&B.o);
+  if (!(B.o.tol > 0.0) || B.o.max_it < 1) return fail(c, DD_EINVAL, "tol <= 0 or max_it < 1");
+  B.prec = prec;
+  B.ld = 1;
+  B.on = true;
+  HIPCHK(c, hipMemsetAsync(c->st.active, 0, kMaxLd * sizeof(int), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->st.flag, 0, 2 * sizeof(int), c->stream));
+  return DD_OK;
+}
+
+dd_status dd_batch_end(dd_ctx *c) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->batch.on = false;
+  HIPCHK(c, hipMemsetAsync(c->st.active, 0, kMaxLd * sizeof(int), c->stream));
+  return DD_OK;
+}
+
+dd_status dd_batch_admit(dd_ctx *c, const int32_t *slots, int32_t ncol, const double *b_dev, int32_t ld) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  auto &B = c->batch;
+  if (!B.on) return fail(c, DD_ESTATE, "no batch is open");
+  if (ncol < 1 || !slots || !b_dev || ld < c->n_dof) return fail(c, DD_EINVAL, "bad admit arguments");
+  std::vector<int> mask(kMaxLd, 0);
+  for (int j = 0; j < ncol; ++j) {
+    int sl = slots[j];
+    if (sl < 0 || sl >= c->max_nrhs) return fail(c, DD_EINVAL, "slot out of [0, max_nrhs)");
+    if (B.state[sl] != DD_SLOT_FREE || mask[sl]) return fail(c, DD_EINVAL, "slot not free");
+    mask[sl] = 1;
+  }
+  for (int j = 0; j < ncol; ++j) B.state[slots[j]] = DD_SLOT_RUNNING;
+  TRY(batch_relayout(c, batch_need_ld(c)));
+  const int L = B.ld;
+  Work &w = c->w;
+  HIPCHK(c, hipMemcpyAsync(B.d_slots, slots, ncol * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid1d((size_t)c->NI * ncol)), dim3(256), 0, c->stream, c->NI,
+                     c->d_imap, b_dev, ld, ncol, B.d_slots, L, w.bI);
+  if (c->n_gamma)
+    hipLaunchKernelGGL(k_gather_cols, dim3(grid1d((size_t)c->n_gamma * ncol)), dim3(256), 0, c->stream,
+                       c->n_gamma, c->d_gmap, b_dev, ld, ncol, B.d_slots, L, w.bG);
+  TRY(batch_mask(c, mask.data()));
+  hipLaunchKernelGGL(k_cols_update, dim3(grid1d((size_t)c->NI * L)), dim3(256), 0, c->stream,
+                     (size_t)c->NI * L, L, 0.0, (const double *)nullptr, w.uI, B.d_mask);
+  hipLaunchKernelGGL(k_cols_update, dim3(grid1d((size_t)c->n_gamma * L)), dim3(256), 0, c->stream,
+                     (size_t)c->n_gamma * L, L, 0.0, (const double *)nullptr, w.uG, B.d_mask);
+  TRY(dd_norm2(c, L, w.bI, w.bG, w.bnrm2));
+  std::vector<double> bn(kMaxLd);
+  HIPCHK(c, hipMemcpyAsync(bn.data(), w.bnrm2, kMaxLd * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < kMaxLd; ++j)
+    if (mask[j]) {
+      B.bn2[j] = bn[j];
+      B.rn2[j] = bn[j];
+      B.its[j] = B.steps[j] = B.conv[j] = B.stall[j] = 0;
+      B.prev[j] = -1.0;
+      double t = B.prec == DD_FP64 ? B.o.tol : B.o.inner_tol;
+      B.stop2[j] = t * t * bn[j];
+    }
+  return batch_start_cg(c, mask.data(), w.bI, w.bG);
+}
+
+dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  auto &B = c->batch;
+  if (!B.on) return fail(c, DD_ESTATE, "no batch is open");
+  Work &w = c->w;
+  const Ops &op = c->op[B.prec];
+  const int L = B.ld;
+  const int prec = B.prec;
+  bool any = false;
+  for (int j = 0; j < kMaxLd; ++j) any |= B.state[j] == DD_SLOT_RUNNING;
+  if (any && iters > 0 && c->n_gamma > 0) {
+    unsigned ge = grid_for(c->n_gamma, kRowsE);
+    double *pA = w.pG, *pB = w.xG;
+    for (int it = 0; it < iters; ++it) {
+      Src P{nullptr, w.zG, pA, c->st.beta};
+      kig_apply(c, prec, P, L, nullptr, 1.0, w.yI);
+      interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);
+      gamma_apply(c, prec, P, w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, pB);
+      hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, L, kMaxLd,
+                         op.dinv, w.dG, w.rG, w.zG, pB, w.qG, c->red, c->st, B.o.precond,
+                         (int *)nullptr, 0, (const int *)nullptr);
+      std::swap(pA, pB);
+    }
+    // keep the current direction in pG (the buffer the next step reads)
+    if (pA != w.pG) std::swap(w.pG, w.xG);
+    HIPCHK(c, hipGetLastError());
+  }
+  StateBlock h;
+  TRY(fetch_state(c, &h));
+  // slots whose CG finished: back substitution of the correction and update of u
+  std::vector<int> fin(kMaxLd, 0);
+  bool anyfin = false;
+  for (int j = 0; j < kMaxLd; ++j) {
+    if (B.state[j] != DD_SLOT_RUNNING) continue;
+    bool stopped = !h.active[j];
+    if (stopped || h.iters[j] >= B.o.max_it) {
+      fin[j] = 1;
+      anyfin = true;
+    }
+  }
+  if (anyfin) {
+    TRY(batch_mask(c, fin.data()));
+    kig_apply(c, prec, plain(w.dG), L, w.tI, -1.0, w.yI);
+    interior_solve(c, prec, DD_APPLY_INV, w.yI, w.dI, L);
+    hipLaunchKernelGGL(k_axpy_masked, dim3(grid1d((size_t)c->NI * L)), dim3(256), 0, c->stream,
+                       (size_t)c->NI * L, L, w.dI, w.uI, B.d_mask);
+    hipLaunchKernelGGL(k_axpy_masked, dim3(grid1d((size_t)c->n_gamma * L)), dim3(256), 0, c->stream,
+                       (size_t)c->n_gamma * L, L, w.dG, w.uG, B.d_mask);
+    HIPCHK(c, hipGetLastError());
+    for (int j = 0; j < kMaxLd; ++j)
+      if (fin[j]) {
+        B.its[j] += h.iters[j];
+        B.steps[j] += 1;
+      }
+    if (prec == DD_FP64) {
+      for (int j = 0; j < kMaxLd; ++j)
+        if (fin[j]) {
+          B.state[j] = DD_SLOT_DONE;
+          B.conv[j] = h.nrm2[j] <= B.stop2[j];
+          B.rn2[j] = h.nrm2[j];
+        }
+    } else {
+      // FP64 residual of the finished columns; refine, finish or fall back
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.yI, w.qG, L);
+      TRY(dd_norm2(c, L, w.yI, w.qG, w.rnrm2));
+      std::vector<double> rn(kMaxLd);
+      HIPCHK(c, hipMemcpyAsync(rn.data(), w.rnrm2, kMaxLd * 8, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      std::vector<int> again(kMaxLd, 0);
+      bool anyagain = false;
+      for (int j = 0; j < kMaxLd; ++j) {
+        if (!fin[j]) continue;
+        B.rn2[j] = rn[j];
+        if (rn[j] <= B.o.tol * B.o.tol * B.bn2[j]) {
+          B.state[j] = DD_SLOT_DONE;
+          B.conv[j] = 1;
+          continue;
+        }
+        if (B.prev[j] >= 0.0 && rn[j] > 0.25 * B.prev[j]) ++B.stall[j];
+        if (B.stall[j] >= 2 || B.steps[j] >= B.o.max_refine) {
+          B.state[j] = B.o.fp64_fallback ? DD_SLOT_FALLBACK : DD_SLOT_DONE;
+          B.conv[j] = 0;
+          continue;
+        }
+        B.prev[j] = rn[j];
+        B.stop2[j] = B.o.inner_tol * B.o.inner_tol * rn[j];
+        again[j] = 1;
+        anyagain = true;
+      }
+      if (anyagain) TRY(batch_start_cg(c, again.data(), w.yI, w.qG));
+    }
+  }
+  if (state_host)
+    for (int j = 0; j < c->max_nrhs; ++j) state_host[j] = B.state[j];
+  return DD_OK;
+}
+
+dd_status dd_batch_retire(dd_ctx *c, const int32_t *slots, int32_t ncol, double *u_dev, int32_t ld,
+                          dd_solve_info *info) {
+  if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  auto &B = c->batch;
+  if (!B.on) return fail(c, DD_ESTATE, "no batch is open");
+  if (ncol < 1 || !slots || (!u_dev && ncol) || ld < c->n_dof) return fail(c, DD_EINVAL, "bad retire arguments");
+  for (int j = 0; j < ncol; ++j) {
+    int sl = slots[j];
+    if (sl < 0 || sl >= kMaxLd || B.state[sl] == DD_SLOT_FREE || B.state[sl] == DD_SLOT_RUNNING)
+      return fail(c, DD_EINVAL, "slot is not finished");
+  }
+  Work &w = c->w;
+  HIPCHK(c, hipMemcpyAsync(B.d_slots, slots, ncol * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_scatter_cols, dim3(grid1d((size_t)c->NI * ncol)), dim3(256), 0, c->stream, c->NI,
+                     c->d_imap, w.uI, B.ld, ncol, B.d_slots, u_dev, ld);
+  if (c->n_gamma)
+    hipLaunchKernelGGL(k_scatter_cols, dim3(grid1d((size_t)c->n_gamma * ncol)), dim3(256), 0, c->stream,
+                       c->n_gamma, c->d_gmap, w.uG, B.ld, ncol, B.d_slots, u_dev, ld);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < ncol; ++j) {
+    int sl = slots[j];
+    if (info) {
+      info[j].iters = B.its[sl];
+      info[j].refine_steps = B.prec == DD_MIXED ? B.steps[sl] : 0;
+      info[j].used_fallback = 0;
+      info[j].converged = B.conv[sl];
+      info[j].rel_resid = B.bn2[sl] > 0 ? std::sqrt(B.rn2[sl] / B.bn2[sl]) : std::sqrt(B.rn2[sl]);
+    }
+    B.state[sl] = DD_SLOT_FREE;
+  }
+  return batch_relayout(c, batch_need_ld(c));
+}
+
 dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask) {
   if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
   c->timing_mask = phase_mask & ((1u << DD_NPHASES) - 1u);
@@ -912,6 +1345,7 @@ dd_status dd_get_schur_diag(dd_ctx *c, dd_precision prec, double *out) {
 dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_dev, int32_t nrhs,
                    int32_t ld, const dd_solve_opts *opts, dd_solve_info *info) {
   if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (c->batch.on) return fail(c, DD_ESTATE, "a batch is open on this context");
   c->err.clear();
   if (prec != DD_FP64 && prec != DD_MIXED) return fail(c, DD_EINVAL, "unknown precision");
   if (nrhs < 1 || nrhs > c->max_nrhs) return fail(c, DD_EINVAL, "nrhs out of [1, max_nrhs]");
@@ -924,8 +1358,27 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   if (prec == DD_MIXED && (o.max_refine < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0))
     return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in (0,1)");
   const int L = next_pow2(nrhs);
+  struct RestoreDk {
+    dd_ctx *c;
+    int v;
+    ~RestoreDk() { c->direction_kernel = v; }
+  } restore_dk{c, c->direction_kernel};
+  {
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    const auto &t = c->tuned[prec][lg];
+    if (t.set && (o.apply == DD_APPLY_AUTO || o.launch == DD_LAUNCH_AUTO)) {
+      if (o.apply == DD_APPLY_AUTO) o.apply = t.apply;
+      if (o.launch == DD_LAUNCH_AUTO) {
+        o.launch = t.launch;
+        c->direction_kernel = t.dk;
+        if (o.check_every == 0) o.check_every = t.check_every;
+      }
+    }
+  }
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
-              o.check_every, o.launch == DD_LAUNCH_PERSISTENT ? DD_LAUNCH_PERSISTENT : DD_LAUNCH_KERNELS};
+              o.check_every,
+              (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS};
   Work &w = c->w;
   // gather b into the DD layout
   hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->NI * L, 256))), dim3(256), 0,

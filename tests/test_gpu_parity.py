@@ -176,3 +176,46 @@ def test_persistent_launch_matches_kernels(name, prec):
     assert [i["iters"] for i in r1.info] == [i["iters"] for i in r2.info]
     assert np.array_equal(r1.u.cpu().numpy(), r2.u.cpu().numpy())
     s.close()
+
+
+@pytest.mark.parametrize("name", ["1d-ragged", "2d-const", "2d-pd"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_launch_matches_kernels(name, prec):
+    """CG iterations captured in a hipGraph and replayed give the same
+    solution, bit for bit, as stream launches (converged columns are frozen,
+    so extra replayed iterations change nothing)."""
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case graph {name} prec={prec}", flush=True)
+    nrhs = b.shape[1]
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s.factor(prec)
+    o1 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS)
+    o2 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_GRAPH, check_every=4)
+    r1 = s.solve(to_dev(b), prec=prec, opts=o1)
+    for _ in range(3):          # replays of the cached graph, eager work in between
+        r2 = s.solve(to_dev(b), prec=prec, opts=o2)
+        assert [i["iters"] for i in r1.info] == [i["iters"] for i in r2.info]
+        assert np.array_equal(r1.u.cpu().numpy(), r2.u.cpu().numpy())
+        r1 = s.solve(to_dev(b), prec=prec, opts=o1)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_then_auto_solve(prec):
+    """The autotuner times its candidate schedules, records the fastest, and
+    AUTO solves then use it and still meet the parity gate."""
+    dd = _dd()
+    wl, b, uref = problem("2d-const-3x2")
+    print(f"case autotune prec={prec}", flush=True)
+    nrhs = b.shape[1]
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s.factor(prec)
+    res = s.autotune(prec, nrhs, dd.dd_default_opts(tol=1e-12))
+    print("  tuned", res, flush=True)
+    assert res["candidates"] >= 8 and res["ms_per_solve"] > 0
+    assert res["launch"] in (1, 2, 3) and res["apply"] in (1, 2)
+    r = s.solve(to_dev(b), prec=prec, opts=dd.dd_default_opts(tol=1e-12))
+    err = oracle.rel_err(r.u.cpu().numpy().T, uref)
+    assert err.max() <= (1e-10 if prec == 0 else 1e-8)
+    s.close()
