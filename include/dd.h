@@ -224,7 +224,8 @@ enum {
   DD_PHASE_INTERIOR = 1,  /* w = K_II^{-1} y                   (all subdomains) */
   DD_PHASE_GAMMA = 2,     /* q = K_GG p - K_GI w, p^T q, alpha  (interface rows) */
   DD_PHASE_UPDATE = 3,    /* x, r, z updates, r^T z, r^T r, beta, convergence */
-  DD_NPHASES = 4
+  DD_PHASE_LOOP = 4,      /* one graph replay or one persistent CG launch (whole iterations) */
+  DD_NPHASES = 5
 };
 
 /* Enable HIP-event timing of the phases whose bit is set in phase_mask

@@ -31,8 +31,8 @@ EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solv
             "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
             "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy"]
 DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
-DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE = range(4)
-DD_NPHASES = 4
+DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE, DD_PHASE_LOOP = range(5)
+DD_NPHASES = 5
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

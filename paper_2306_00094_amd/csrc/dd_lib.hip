@@ -513,8 +513,11 @@ dd_status launch_persistent_t(dd_ctx *c, PArgs<VT, MT> &a) {
   int grid = nb * c->num_cu;
   HIPCHK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->stream));
   void *args[] = {(void *)&a};
-  HIPCHK(c, hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(kPBlock), args, 0,
-                                       c->stream));
+  {
+    PhaseTimer t(c, DD_PHASE_LOOP);
+    HIPCHK(c, hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(kPBlock), args, 0,
+                                         c->stream));
+  }
   return DD_OK;
 }
 
@@ -665,7 +668,10 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     int launches = 0;
     const int max_launch = (o.max_it + G - 1) / G;
     while (launches < max_launch) {
-      HIPCHK(c, hipGraphLaunch(exec, c->stream));
+      {
+        PhaseTimer t(c, DD_PHASE_LOOP);
+        HIPCHK(c, hipGraphLaunch(exec, c->stream));
+      }
       HIPCHK(c, hipEventRecord(c->ev[launches % c->nslots], c->stream));
       ++launches;
       if (launches >= 2) {
