@@ -39,6 +39,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
+// The same butterfly within aligned groups of G lanes (G a power of two <= 64):
+// every lane of a group receives the group's sum.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -62,8 +70,20 @@ struct ColState {
 struct RedBuf {
   double *part0;       // chunk partials, dot 0  (max_chunks x kMaxLd)
   double *part1;       // chunk partials, dot 1
+  double *part2;       // chunk partials of p^T q from the interface-row kernel
+  double *part3;       // group sums of part2 (kPGroup chunks per group)
   unsigned *counter;   // last-workgroup counters (one per reduction site)
+  unsigned *gcount;    // one completion counter per chunk group (kCounterStride apart)
 };
+
+// Two-level reduction of the interface-row chunk partials: groups of kPGroup
+// consecutive chunks are summed by the wave butterfly (chunk m of the group
+// in lane m; missing chunks of the last group add zeros) into part3 by the
+// last workgroup of the group to finish; consumers sum the group values with
+// partials_sum.  Per-group counters keep same-address atomics to kPGroup per
+// counter instead of one per workgroup of the whole grid.
+constexpr int kPGroup = 64;
+constexpr int kCounterStride = 32;    // counters 128 bytes apart
 
 // ---------------------------------------------------------------- trees --
 // Column partial of a chunk: rows 0..63 of lds (stride ld) reduced by the
@@ -141,6 +161,24 @@ __device__ __forceinline__ void reset_counter(unsigned *counter) {
   __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Last of `members` workgroups to arrive at counter (after storing partials).
+__device__ __forceinline__ bool last_of(unsigned *counter, unsigned members, int *lds_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *lds_flag = (prev == members - 1);
+  }
+  __syncthreads();
+  return *lds_flag != 0;
+}
+
+// Sum of chunk partials g*kPGroup .. g*kPGroup+63 (those < P) of column c.
+__device__ __forceinline__ double chunk_group_sum(const double *part, int P, int ld, int c, int g) {
+  const int m = g * kPGroup + lane_id();
+  double v = m < P ? load_partial(part + (size_t)m * ld + c) : 0.0;
+  return wave_sum(v);
+}
+
 // ----------------------------------------------------------- row products --
 // Source of gathered vector entries: a plain vector x, or the CG direction
 // formed on the fly, x = z + beta * p_prev (beta per column).  Which of the
@@ -171,37 +209,54 @@ __device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) 
 }
 
 // acc[c] += sum_k val[k] * x[col[k]][cp + c] over the row, lane-strided.
-// Each lane visits its entries k = b+lane, b+lane+64, ... in increasing order.
-// The loop issues U slots per pass with masked loads: a slot past the row end
-// adds fma(0, 0, acc) = acc exactly, so the sum is bit-identical to the plain
-// loop while U gathers are in flight per lane.
+// A row is processed by an aligned group of G lanes (G = 64: the whole wave;
+// G = 32: half a wave, two rows per wave).  Lane s of the group visits its
+// entries k = b+s, b+s+G, b+s+2G, ... in increasing order.  The loop handles U
+// slots per pass with masked loads: a slot past the row end adds
+// fma(0, 0, acc) = acc exactly, so the sum is bit-identical to the plain
+// strided loop for every U.  The column indices and values of the next pass
+// are loaded while the current pass's gathers are in flight, so a pass costs
+// about one memory round trip instead of two (PIPE; costs registers).
 template <int C> struct Unroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
 
-template <int C, typename VT, bool OTF, int U = Unroll<C>::U>
+template <int U, int G, typename VT>
+__device__ __forceinline__ void load_slots(int k, int e, const int *__restrict__ col,
+                                           const VT *__restrict__ val, double (&v)[U],
+                                           int (&cc)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    int idx = k + u * G;
+    bool ok = idx < e;
+    v[u] = ok ? (double)val[idx] : 0.0;
+    cc[u] = ok ? col[idx] : -1;
+  }
+}
+
+template <int C, typename VT, bool OTF, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
 __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict__ col,
                                             const VT *__restrict__ val, const Src &x, int ld,
                                             int cp, double (&acc)[C]) {
   double bt[C];
   src_beta<C, OTF>(x, cp, bt);
-  for (int k = b + lane_id(); k < e; k += U * kWave) {
+  int k = b + (lane_id() & (G - 1));
+  double vn[U];
+  int cn[U];
+  if (PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
+  while (k < e) {
+    if (!PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
     double v[U];
-    int cc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int idx = k + u * kWave;
-      bool ok = idx < e;
-      v[u] = ok ? (double)val[idx] : 0.0;
-      cc[u] = ok ? col[idx] : -1;
-    }
     double xv[U][C];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (cc[u] >= 0) src_load<C, OTF>(x, (size_t)cc[u] * ld + cp, bt, xv[u]);
+      v[u] = vn[u];
+      if (cn[u] >= 0) src_load<C, OTF>(x, (size_t)cn[u] * ld + cp, bt, xv[u]);
       else {
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
       }
     }
+    k += U * G;
+    if (PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -212,7 +267,7 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
 // Two-part row: entries [b, s) gather from x1 into acc1, entries [s, e) from
 // x2 into acc2, in one masked loop (each accumulator sees its entries in
 // increasing order; slots of the other part add exact zeros).
-template <int C, typename VT, bool OTF1, int U = Unroll<C>::U>
+template <int C, typename VT, bool OTF1, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
 __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__restrict__ col,
                                              const VT *__restrict__ val, const Src &x1,
                                              const Src &x2, int ld, int cp, double (&acc1)[C],
@@ -220,32 +275,33 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
   double bt1[C], bt2[C];
   src_beta<C, OTF1>(x1, cp, bt1);
   src_beta<C, false>(x2, cp, bt2);
-  for (int k = b + lane_id(); k < e; k += U * kWave) {
+  int k = b + (lane_id() & (G - 1));
+  double vn[U];
+  int cn[U];
+  if (PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
+  while (k < e) {
+    if (!PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
     double v[U];
-    int cc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int idx = k + u * kWave;
-      bool ok = idx < e;
-      v[u] = ok ? (double)val[idx] : 0.0;
-      cc[u] = ok ? col[idx] : -1;
-    }
     double xv[U][C];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int idx = k + u * kWave;
-      if (cc[u] < 0) {
+      int idx = k + u * G;
+      v[u] = vn[u];
+      if (cn[u] < 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
       } else if (idx < s) {
-        src_load<C, OTF1>(x1, (size_t)cc[u] * ld + cp, bt1, xv[u]);
+        src_load<C, OTF1>(x1, (size_t)cn[u] * ld + cp, bt1, xv[u]);
       } else {
-        src_load<C, false>(x2, (size_t)cc[u] * ld + cp, bt2, xv[u]);
+        src_load<C, false>(x2, (size_t)cn[u] * ld + cp, bt2, xv[u]);
       }
     }
+    const int k0 = k;
+    k += U * G;
+    if (PIPE) load_slots<U, G>(k, e, col, val, vn, cn);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int idx = k + u * kWave;
+      int idx = k0 + u * G;
       double v1 = idx < s ? v[u] : 0.0;
       double v2 = idx < s ? 0.0 : v[u];
 #pragma unroll
@@ -351,42 +407,57 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
 // Interface rows of [K_GG | K_GI]: per row, entries [ptr, split) are K_GG
 // (columns index p), entries [split, ptr+1) are K_GI (columns index z_I).
 //   out = base + c1 * K_GG p + c2 * K_GI z
-// One wave per row, kGRows rows per workgroup.  With dot != 0 (the CG
-// operator product q = S p), the row's direction entries p_j are stored to
-// pout, the workgroup writes its partial of p^T q (rows summed in order), and
-// the last workgroup computes alpha = rz / (p^T q) for the active columns
-// (CG step length; breakdown when p^T q <= 0).
-constexpr int kGRows = 16;
-template <int C, typename VT, bool OTF>
+// A group of G lanes per row (G = 32: two rows per wave), NW waves per
+// workgroup: a workgroup covers NW * 64 / G consecutive rows.  With dot != 0
+// (the CG operator product q = S p), the row's direction entries p_j are
+// stored to pout and the workgroup writes its partial of p^T q (its rows
+// summed in order) to red.part2; the last workgroup of each group of
+// kPGroup chunks writes the group sum to red.part3.  The group sums are
+// reduced by every workgroup of the following update kernel in the same
+// fixed order, so no workgroup here waits for the whole grid (one counter for
+// the whole grid serialises its same-address atomics over every workgroup).
+constexpr int kGRows = 4;                         // waves per workgroup
+constexpr int kGLanes = 32;                       // lanes per interface row
+constexpr int kGRowsPerWave = kWave / kGLanes;
+constexpr int kGChunk = kGRows * kGRowsPerWave;   // rows per workgroup / partial
+template <int C> struct GUnroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
+
+template <int C, typename VT, bool OTF, int G = kGLanes, int U = GUnroll<C>::U, bool PIPE = false,
+          int NW = kGRows>
 __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
              RedBuf red, ColState st) {
-  __shared__ double prod[kGRows * kMaxLd];
-  __shared__ int lflag;
+  constexpr int RPW = kWave / G, CH = NW * RPW;
+  __shared__ double prod[CH * kMaxLd];
   const int wv = wave_id(), lane = lane_id();
-  const int j = blockIdx.x * kGRows + wv;
+  const int jl = wv * RPW + lane / G;          // row within the chunk
+  const bool head = (lane & (G - 1)) == 0;
+  const int j = blockIdx.x * CH + jl;
   const Src zs{z, nullptr, nullptr, nullptr};
+  int b = 0, s = 0, e = 0;
+  if (j < nrows) { b = ptr[j]; s = split[j]; e = ptr[j + 1]; }
   for (int cp = 0; cp < ld; cp += C) {
-    double a1[C], a2[C];
+    double a1[C], a2[C], pj[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) { a1[c] = 0.0; a2[c] = 0.0; }
+    for (int c = 0; c < C; ++c) { a1[c] = 0.0; a2[c] = 0.0; pj[c] = 0.0; }
+    if (dot && head && j < nrows) {     // this row's direction entries, loaded early
+      double bt[C];
+      src_beta<C, OTF>(p, cp, bt);
+      src_load<C, OTF>(p, (size_t)j * ld + cp, bt, pj);
+    }
     if (j < nrows) {
-      int b = ptr[j], s = split[j], e = ptr[j + 1];
-      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT, OTF>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
-      else if (c1 != 0.0) csr_row_acc<C, VT, OTF>(b, s, col, val, p, ld, cp, a1);
-      else if (c2 != 0.0) csr_row_acc<C, VT, false>(s, e, col, val, zs, ld, cp, a2);
+      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT, OTF, U, G, PIPE>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
+      else if (c1 != 0.0) csr_row_acc<C, VT, OTF, U, G, PIPE>(b, s, col, val, p, ld, cp, a1);
+      else if (c2 != 0.0) csr_row_acc<C, VT, false, U, G, PIPE>(s, e, col, val, zs, ld, cp, a2);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      a1[c] = wave_sum(a1[c]);
-      a2[c] = wave_sum(a2[c]);
+      a1[c] = group_sum<G>(a1[c]);
+      a2[c] = group_sum<G>(a2[c]);
     }
-    if (lane == 0) {
-      double bt[C], pj[C];
-      src_beta<C, OTF>(p, cp, bt);
-      if (j < nrows && dot) src_load<C, OTF>(p, (size_t)j * ld + cp, bt, pj);
+    if (head) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         double q = 0.0;
@@ -399,43 +470,42 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
             q *= pj[c];
           }
         }
-        prod[wv * ld + cp + c] = q;
+        prod[jl * ld + cp + c] = q;
       }
     }
   }
   if (!dot) return;
   __syncthreads();
-  for (int c = wv; c < ld; c += kGRows)
+  for (int c = wv; c < ld; c += NW)
     if (lane == 0) {
-      double s = 0.0;
-      for (int r = 0; r < kGRows; ++r) s += prod[r * ld + c];
-      store_partial(red.part0 + (size_t)blockIdx.x * ld + c, s);
+      double sum = 0.0;
+      for (int r = 0; r < CH; ++r) sum += prod[r * ld + c];
+      store_partial(red.part2 + (size_t)blockIdx.x * ld + c, sum);
     }
-  if (!last_block(&red.counter[0], &lflag)) return;
-  for (int c = wv; c < ld; c += kGRows) {
-    double pq = partials_sum(red.part0, gridDim.x, ld, c);
-    if (lane == 0) {
-      double a = 0.0;
-      if (st.active[c]) {
-        if (!(pq > 0.0)) { st.flag[0] = 1; st.active[c] = 0; }
-        else a = st.rz[c] / pq;
-      }
-      st.alpha[c] = a;
-    }
+  // the last workgroup of this chunk group writes the group sum
+  const int grp = blockIdx.x / kPGroup;
+  const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
+  __shared__ int lflag;
+  unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
+  if (!last_of(cnt, (unsigned)members, &lflag)) return;
+  for (int c = wv; c < ld; c += NW) {
+    double g = chunk_group_sum(red.part2, gridDim.x, ld, c, grp);
+    if (lane == 0) store_partial(red.part3 + (size_t)grp * ld + c, g);
   }
   __syncthreads();
-  if (threadIdx.x == 0) reset_counter(&red.counter[0]);
+  if (threadIdx.x == 0) reset_counter(cnt);
 }
 
-template <int C, typename VT, bool OTF>
-__global__ void __launch_bounds__(kGRows * kWave)
+template <int C, typename VT, bool OTF, int G = kGLanes, int U = GUnroll<C>::U, bool PIPE = false,
+          int NW = kGRows>
+__global__ void __launch_bounds__(NW * kWave)
 k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
              RedBuf red, ColState st) {
-  gamma_rows_body<C, VT, OTF>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2, out, dot,
-                              pout, red, st);
+  gamma_rows_body<C, VT, OTF, G, U, PIPE, NW>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2,
+                                              out, dot, pout, red, st);
 }
 
 
@@ -443,7 +513,11 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 // Chunk of kRowsE interface rows x ld columns per workgroup.
 // mode 0 (init):   x = 0, r given, z = D^{-1} r, p = 0 (so the first
 //                  direction z + 0 * p is z);                 dots: r.z, r.r
-// mode 1 (update): x += a p, r -= a q, z = D^{-1} r (active);  dots: r.z, r.r
+// mode 1 (update): a = rz / p^T q from the npq group sums of the interface-row
+//                  kernel (every workgroup reduces them in the same order, so
+//                  all compute the same a; p^T q <= 0 is a breakdown and
+//                  stops the column), then
+//                  x += a p, r -= a q, z = D^{-1} r (active);  dots: r.z, r.r
 // The last workgroup then updates the column state:
 //   init:   rz = r.z, active = (r.r > stop2) for c < nrhs, iters = 0
 //   update: iters += 1; converged when r.r <= stop2; beta = r.z / rz_old
@@ -453,11 +527,29 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
             int use_precond, int *__restrict__ host_nact, int init_p_is_z,
-            const int *__restrict__ mask = nullptr) {
+            const int *__restrict__ mask = nullptr, int npq = 0) {
   __shared__ double lds[kRowsE * kMaxLd];
+  __shared__ double salpha[kMaxLd];
+  __shared__ int sact[kMaxLd];
   __shared__ int lflag;
   const int row0 = blockIdx.x * kRowsE;
   const int wv = wave_id(), lane = lane_id();
+  if (mode == 1) {
+    for (int c = wv; c < ld; c += kWavesPerBlock) {
+      double pq = partials_sum(red.part3, npq, ld, c);
+      if (lane == 0) {
+        int act = st.active[c];
+        double a = 0.0;
+        if (act) {
+          if (!(pq > 0.0)) act = 0;
+          else a = st.rz[c] / pq;
+        }
+        salpha[c] = a;
+        sact[c] = act;
+      }
+    }
+    __syncthreads();
+  }
   // pass 1: element-wise update; products r*z
   for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
     int lr = e / ld, c = e - lr * ld;
@@ -468,9 +560,9 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       bool init = mode == 0 || (mode == 2 && mask[c]);
       double rv = (mode == 2 && init) ? q[o] : r[o];     // mode 2: new residual in q
       if (mode == 2 && init) r[o] = rv;
-      bool act = init ? true : (mode == 1 && st.active[c] != 0);
+      bool act = init ? true : (mode == 1 && sact[c] != 0);
       if (mode == 1 && act) {
-        double a = st.alpha[c];
+        double a = salpha[c];
         x[o] = fma(a, p[o], x[o]);
         rv = fma(-a, q[o], rv);
         r[o] = rv;
@@ -513,11 +605,17 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         st.iters[c] = 0;
         st.beta[c] = 0.0;
         st.active[c] = ((mode == 2 || c < nrhs) && rr > st.stop2[c]) ? 1 : 0;
-      } else if (mode == 1 && st.active[c]) {
-        st.iters[c] += 1;
-        st.beta[c] = rz / st.rz[c];
-        st.rz[c] = rz;
-        if (rr <= st.stop2[c]) st.active[c] = 0;
+      } else if (mode == 1) {
+        st.alpha[c] = salpha[c];
+        if (st.active[c] && !sact[c]) {     // breakdown: p^T q <= 0
+          st.active[c] = 0;
+          st.flag[0] = 1;
+        } else if (sact[c]) {
+          st.iters[c] += 1;
+          st.beta[c] = rz / st.rz[c];
+          st.rz[c] = rz;
+          if (rr <= st.stop2[c]) st.active[c] = 0;
+        }
       }
       if (mode != 2 || mask[c]) st.nrm2[c] = rr;
     }

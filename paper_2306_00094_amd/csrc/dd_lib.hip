@@ -81,6 +81,7 @@ struct dd_ctx {
   RedBuf red{};
   int *d_status = nullptr, *d_bad = nullptr;
   size_t max_chunks = 0;
+  int gamma_parts = 0;                  // p^T q group sums written by the last interface-row launch
   // host polling
   int *h_nact = nullptr;          // pinned, mapped
   int *h_nact_dev = nullptr;
@@ -243,9 +244,10 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   b += 2 * kt * s + p->n_gamma * 16;                                  // L, K^-1, diag
   if (prec == DD_MIXED) b += (nig + ngg + nig) * 4;                   // FP32 values
   b += (9 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                    // work vectors
-  size_t chunks = std::max<size_t>((p->n_gamma + kGRows - 1) / kGRows,
+  size_t chunks = std::max<size_t>((p->n_gamma + kGChunk - 1) / kGChunk,
                                    (std::max<size_t>(p->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
-  b += 2 * chunks * kMaxLd * 8;
+  b += 3 * chunks * kMaxLd * 8;
+  b += (chunks / kPGroup + 1) * (kMaxLd * 8 + kCounterStride * 4);
   return b;
 }
 
@@ -301,7 +303,8 @@ template <int C, typename VT>
 void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                   const double *base, double c1, double c2, double *out, int dot, double *pout) {
   if (c->n_gamma <= 0) return;
-  dim3 g(grid_for(c->n_gamma, kGRows)), b(kGRows * kWave);
+  dim3 g(grid_for(c->n_gamma, kGChunk)), b(kGRows * kWave);
+  if (dot) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums
   {
     if (p.z)
       hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
@@ -611,7 +614,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       PhaseTimer t(c, DD_PHASE_UPDATE);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
                          op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, c->red, c->st, o.precond,
-                         nact_dst, 0);
+                         nact_dst, 0, (const int *)nullptr, c->gamma_parts);
     }
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
@@ -894,10 +897,18 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
       return bail(DD_EHIP);
     }
   }
-  c->max_chunks = std::max((size_t)(c->n_gamma + kGRows - 1) / kGRows,
+  c->max_chunks = std::max((size_t)(c->n_gamma + kGChunk - 1) / kGChunk,
                            (size_t)(std::max(c->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
   if ((s = dalloc(c, &c->red.part0, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->red.part1, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->red.part2, c->max_chunks * kMaxLd)) != DD_OK) return bail(s);
+  const size_t ngroups = c->max_chunks / kPGroup + 1;
+  if ((s = dalloc(c, &c->red.part3, ngroups * kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->red.gcount, ngroups * kCounterStride)) != DD_OK) return bail(s);
+  if (hipMemset(c->red.gcount, 0, ngroups * kCounterStride * sizeof(unsigned)) != hipSuccess) {
+    c->err = "hipMemset failed";
+    return bail(DD_EHIP);
+  }
   if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
@@ -1206,7 +1217,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
       gamma_apply(c, prec, P, w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, pB);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, L, kMaxLd,
                          op.dinv, w.dG, w.rG, w.zG, pB, w.qG, c->red, c->st, B.o.precond,
-                         (int *)nullptr, 0, (const int *)nullptr);
+                         (int *)nullptr, 0, (const int *)nullptr, c->gamma_parts);
       std::swap(pA, pB);
     }
     // keep the current direction in pG (the buffer the next step reads)

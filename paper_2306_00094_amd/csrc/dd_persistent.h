@@ -25,7 +25,7 @@
 
 namespace dd {
 
-constexpr int kPBlock = kGRows * kWave;   // 16 waves per workgroup
+constexpr int kPBlock = 16 * kWave;   // 16 waves per workgroup
 // Narrower unroll than the per-phase kernels: the fused kernel holds the
 // registers of all phases and must fit 16 waves per workgroup.
 template <int C> struct PUnroll { static constexpr int U = C == 1 ? 4 : (C <= 4 ? 2 : 1); };
@@ -131,7 +131,7 @@ k_pcg_persistent(PArgs<VT, MT> a) {
   const int wv = wave_id(), lane = lane_id();
   const int gw = blockIdx.x * WPB + wv, nw = gridDim.x * WPB;
   const int ld = a.ld;
-  const int PC = (a.nG + kGRows - 1) / kGRows;     // interface chunks of phase C
+  const int PC = (a.nG + kGChunk - 1) / kGChunk;   // interface chunks of phase C
   const int PD = (a.nG + kRowsE - 1) / kRowsE;     // interface chunks of phase D
   double *pA = a.pA, *pB = a.pB;
   int it = 0;
@@ -194,23 +194,32 @@ k_pcg_persistent(PArgs<VT, MT> a) {
     }
     if (!grid_barrier(a.bar, &s_role, [] {})) return;
     // ---- C: q = K_GG p - K_GI w, store this row's direction, chunk partials of p.q
+    //      (same row arithmetic, chunks and reduction tree as k_gamma_rows; a
+    //      workgroup handles CPB chunks of kGChunk rows at a time)
     const Src ws{a.w, nullptr, nullptr, nullptr};
-    for (int ch = blockIdx.x; ch < PC; ch += gridDim.x) {
-      const int j = ch * kGRows + wv;
+    constexpr int CPB = WPB / kGRows;
+    const int NSC = (PC + CPB - 1) / CPB;
+    for (int sc = blockIdx.x; sc < NSC; sc += gridDim.x) {
+      const int sub = wv / kGRows;
+      const int ch = sc * CPB + sub;
+      const int jl = (wv % kGRows) * kGRowsPerWave + lane / kGLanes;
+      const bool head = (lane & (kGLanes - 1)) == 0;
+      const int j = ch * kGChunk + jl;
       for (int cp = 0; cp < ld; cp += C) {
         double a1[C], a2[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) { a1[c] = 0.0; a2[c] = 0.0; }
         if (j < a.nG) {
           int b = a.g_ptr[j], s = a.g_split[j], e = a.g_ptr[j + 1];
-          csr_row_acc2<C, VT, true, PUnroll<C>::U>(b, s, e, a.g_col, a.g_val, P, ws, ld, cp, a1, a2);
+          csr_row_acc2<C, VT, true, PUnroll<C>::U, kGLanes>(b, s, e, a.g_col, a.g_val, P, ws, ld, cp,
+                                                            a1, a2);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          a1[c] = wave_sum(a1[c]);
-          a2[c] = wave_sum(a2[c]);
+          a1[c] = group_sum<kGLanes>(a1[c]);
+          a2[c] = group_sum<kGLanes>(a2[c]);
         }
-        if (lane == 0) {
+        if (head) {
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             double prod = 0.0;
@@ -222,22 +231,32 @@ k_pcg_persistent(PArgs<VT, MT> a) {
               store_coh(pB + o, pj);
               prod = qv * pj;
             }
-            lds[wv * ld + cp + c] = prod;
+            lds[(sub * kGChunk + jl) * ld + cp + c] = prod;
           }
         }
       }
       __syncthreads();
-      for (int c = wv; c < ld; c += WPB)
-        if (lane == 0) {
+      for (int t = wv; t < CPB * ld; t += WPB) {
+        const int sub2 = t / ld, c = t - sub2 * ld;
+        const int ch2 = sc * CPB + sub2;
+        if (lane == 0 && ch2 < PC) {
           double s = 0.0;
-          for (int rr = 0; rr < kGRows; ++rr) s += lds[rr * ld + c];
-          store_partial(a.red.part0 + (size_t)ch * ld + c, s);
+          for (int rr = 0; rr < kGChunk; ++rr) s += lds[(sub2 * kGChunk + rr) * ld + c];
+          store_partial(a.red.part2 + (size_t)ch2 * ld + c, s);
         }
+      }
       __syncthreads();
     }
+    const int G2 = (PC + kPGroup - 1) / kPGroup;
     bool ok = grid_barrier(a.bar, &s_role, [&] {
+      for (int t = wv; t < G2 * ld; t += WPB) {
+        const int g = t / ld, c = t - g * ld;
+        double v = chunk_group_sum(a.red.part2, PC, ld, c, g);
+        if (lane == 0) store_partial(a.red.part3 + (size_t)g * ld + c, v);
+      }
+      __syncthreads();
       for (int c = wv; c < ld; c += WPB) {
-        double pq = partials_sum(a.red.part0, PC, ld, c);
+        double pq = partials_sum(a.red.part3, G2, ld, c);
         if (lane == 0) {
           double al = 0.0;
           if (load_coh(a.st.active + c)) {
