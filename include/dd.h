@@ -100,7 +100,8 @@ typedef struct {
   int32_t max_it;        /* CG iteration cap per CG solve */
   int32_t precond;       /* 0 none, 1 exact diag(S) Jacobi */
   int32_t max_refine;    /* DD_MIXED: outer refinement steps */
-  double inner_tol;      /* DD_MIXED: inner CG stops at ||r_in|| <= inner_tol ||r_outer|| */
+  double inner_tol;      /* DD_MIXED: inner CG stops at ||r_in|| <= max(inner_tol ||r_outer||,
+                            tol ||b|| / 2) */
   int32_t fp64_fallback; /* DD_MIXED: 1 = finish stalled columns with the FP64 path */
   int32_t apply;         /* dd_apply */
   int32_t launch;        /* dd_launch */

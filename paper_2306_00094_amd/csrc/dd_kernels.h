@@ -510,7 +510,10 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 
 
 // ----------------------------------------------------------- CG updates --
-// Chunk of kRowsE interface rows x ld columns per workgroup.
+// Chunks of kRowsE interface rows x ld columns; a workgroup handles cpw
+// consecutive chunks in one pass (cpw * ld <= 64; cpw is a launch choice:
+// every chunk writes the same partials whatever cpw is, so results do not
+// depend on it).
 // mode 0 (init):   x = 0, r given, z = D^{-1} r, p = 0 (so the first
 //                  direction z + 0 * p is z);                 dots: r.z, r.r
 // mode 1 (update): a = rz / p^T q from the npq group sums of the interface-row
@@ -518,21 +521,25 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 //                  all compute the same a; p^T q <= 0 is a breakdown and
 //                  stops the column), then
 //                  x += a p, r -= a q, z = D^{-1} r (active);  dots: r.z, r.r
+// mode 2 (masked init): columns with mask[c] != 0 restart from the residual
+//                  given in q (mode 0 for those columns), the others keep
+//                  their state.
 // The last workgroup then updates the column state:
 //   init:   rz = r.z, active = (r.r > stop2) for c < nrhs, iters = 0
 //   update: iters += 1; converged when r.r <= stop2; beta = r.z / rz_old
-// and, when host_nact is given, publishes (number of active columns + 1).
+// and, when host_nact is given, publishes (number of active columns + 1) to
+// host memory (a plain system-coherent store: the host reads only that value).
+constexpr int kUpdMaxE = kRowsE * kMaxLd / kBlock;   // elements per thread per chunk
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
             int use_precond, int *__restrict__ host_nact, int init_p_is_z,
-            const int *__restrict__ mask = nullptr, int npq = 0) {
+            const int *__restrict__ mask = nullptr, int npq = 0, int cpw = 1) {
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ double salpha[kMaxLd];
   __shared__ int sact[kMaxLd];
   __shared__ int lflag;
-  const int row0 = blockIdx.x * kRowsE;
   const int wv = wave_id(), lane = lane_id();
   if (mode == 1) {
     for (int c = wv; c < ld; c += kWavesPerBlock) {
@@ -550,84 +557,101 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     }
     __syncthreads();
   }
-  // pass 1: element-wise update; products r*z
-  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
-    int lr = e / ld, c = e - lr * ld;
-    int j = row0 + lr;
-    double rz = 0.0;
-    if (j < nrows) {
-      size_t o = (size_t)j * ld + c;
-      bool init = mode == 0 || (mode == 2 && mask[c]);
-      double rv = (mode == 2 && init) ? q[o] : r[o];     // mode 2: new residual in q
-      if (mode == 2 && init) r[o] = rv;
-      bool act = init ? true : (mode == 1 && sact[c] != 0);
-      if (mode == 1 && act) {
-        double a = salpha[c];
-        x[o] = fma(a, p[o], x[o]);
-        rv = fma(-a, q[o], rv);
-        r[o] = rv;
+  const int nchunks = (nrows + kRowsE - 1) / kRowsE;
+  const int chunk0 = blockIdx.x * cpw;
+  const int nck = min(cpw, nchunks - chunk0);         // chunks of this workgroup
+  const int nel = nck * kRowsE * ld;                  // <= kRowsE * kMaxLd (cpw * ld <= 64)
+  const int row0 = chunk0 * kRowsE;
+  // element-wise update; products r*z to LDS, r*r kept in registers
+  double rrv[kUpdMaxE];
+#pragma unroll
+  for (int k = 0; k < kUpdMaxE; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    rrv[k] = 0.0;
+    if (e < nel) {
+      const int lr = e / ld, c = e - lr * ld;
+      const int j = row0 + lr;
+      double rz = 0.0;
+      if (j < nrows) {
+        size_t o = (size_t)j * ld + c;
+        bool init = mode == 0 || (mode == 2 && mask[c]);
+        double rv = (mode == 2 && init) ? q[o] : r[o];     // mode 2: new residual in q
+        if (mode == 2 && init) r[o] = rv;
+        bool act = init ? true : (mode == 1 && sact[c] != 0);
+        if (mode == 1 && act) {
+          double a = salpha[c];
+          x[o] = fma(a, p[o], x[o]);
+          rv = fma(-a, q[o], rv);
+          r[o] = rv;
+        }
+        if (init) x[o] = 0.0;
+        double zv = use_precond ? dinv[j] * rv : rv;
+        if (act) z[o] = zv;
+        else zv = z[o];
+        if (init) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
+        rz = rv * zv;
+        rrv[k] = rv * rv;
       }
-      if (init) x[o] = 0.0;
-      double zv = use_precond ? dinv[j] * rv : rv;
-      if (act) z[o] = zv;
-      else zv = z[o];
-      if (init) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
-      rz = rv * zv;
+      lds[e] = rz;
     }
-    lds[lr * ld + c] = rz;
   }
   __syncthreads();
-  for (int c = wv; c < ld; c += kWavesPerBlock) {
-    double s = chunk64_sum(lds, ld, c);
-    if (lane == 0) store_partial(red.part0 + (size_t)blockIdx.x * ld + c, s);
+  for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
+    const int k = t / ld, c = t - k * ld;
+    double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
+    if (lane == 0) store_partial(red.part0 + (size_t)(chunk0 + k) * ld + c, sm);
   }
   __syncthreads();
-  // pass 2: products r*r of the same elements (each thread rereads its own writes)
-  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
-    int lr = e / ld, c = e - lr * ld;
-    int j = row0 + lr;
-    double rr = 0.0;
-    if (j < nrows) { double rv = r[(size_t)j * ld + c]; rr = rv * rv; }
-    lds[lr * ld + c] = rr;
+#pragma unroll
+  for (int k = 0; k < kUpdMaxE; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    if (e < nel) lds[e] = rrv[k];
   }
   __syncthreads();
-  for (int c = wv; c < ld; c += kWavesPerBlock) {
-    double s = chunk64_sum(lds, ld, c);
-    if (lane == 0) store_partial(red.part1 + (size_t)blockIdx.x * ld + c, s);
+  for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
+    const int k = t / ld, c = t - k * ld;
+    double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
+    if (lane == 0) store_partial(red.part1 + (size_t)(chunk0 + k) * ld + c, sm);
   }
   if (!last_block(&red.counter[1], &lflag)) return;
   for (int c = wv; c < ld; c += kWavesPerBlock) {
     double rz, rr;
-    partials_sum2(red.part0, red.part1, gridDim.x, ld, c, rz, rr);
+    partials_sum2(red.part0, red.part1, nchunks, ld, c, rz, rr);
     if (lane == 0) {
+      int active = st.active[c];
       if (mode == 0 || (mode == 2 && mask[c])) {
         st.rz[c] = rz;
         st.iters[c] = 0;
         st.beta[c] = 0.0;
-        st.active[c] = ((mode == 2 || c < nrhs) && rr > st.stop2[c]) ? 1 : 0;
+        active = ((mode == 2 || c < nrhs) && rr > st.stop2[c]) ? 1 : 0;
       } else if (mode == 1) {
         st.alpha[c] = salpha[c];
-        if (st.active[c] && !sact[c]) {     // breakdown: p^T q <= 0
-          st.active[c] = 0;
+        if (active && !sact[c]) {           // breakdown: p^T q <= 0
+          active = 0;
           st.flag[0] = 1;
         } else if (sact[c]) {
           st.iters[c] += 1;
           st.beta[c] = rz / st.rz[c];
           st.rz[c] = rz;
-          if (rr <= st.stop2[c]) st.active[c] = 0;
+          if (rr <= st.stop2[c]) active = 0;
         }
       }
+      st.active[c] = active;
+      sact[c] = active;
       if (mode != 2 || mask[c]) st.nrm2[c] = rr;
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0;
-    for (int c = 0; c < ld; ++c) na += st.active[c];
-    if (st.flag[0]) na = 0;            // breakdown ends the loop
-    st.flag[1] = na > 0 ? 1 : 0;       // loop decision for the persistent launch
-    if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    reset_counter(&red.counter[1]);
+  if (wv == 0) {
+    int na = lane < ld ? sact[lane] : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
+    if (lane == 0) {
+      if (st.flag[0]) na = 0;            // breakdown ends the loop
+      st.flag[1] = na > 0 ? 1 : 0;       // loop decision for the persistent launch
+      if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      reset_counter(&red.counter[1]);
+    }
   }
 }
 

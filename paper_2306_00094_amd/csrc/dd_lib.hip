@@ -81,6 +81,7 @@ struct dd_ctx {
   RedBuf red{};
   int *d_status = nullptr, *d_bad = nullptr;
   size_t max_chunks = 0;
+  int *d_solve_mask = nullptr;         // refinement column mask of dd_solve (kMaxLd)
   int gamma_parts = 0;                  // p^T q group sums written by the last interface-row launch
   // host polling
   int *h_nact = nullptr;          // pinned, mapped
@@ -313,6 +314,15 @@ void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
       hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
                          c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
   }
+}
+
+// Update-kernel launch shape: cpw chunks of kRowsE rows per workgroup (more
+// chunks per workgroup for narrow batches; the chunk partials do not change).
+inline int upd_cpw(int ld) { return ld >= 4 ? 1 : 4 / ld; }
+inline unsigned upd_grid(int n_gamma, int ld) {
+  unsigned ch = grid_for(n_gamma, kRowsE);
+  unsigned w = (unsigned)upd_cpw(ld);
+  return (ch + w - 1) / w;
 }
 
 template <typename VT>
@@ -563,11 +573,11 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
-  unsigned ge = c->n_gamma > 0 ? grid_for(c->n_gamma, kRowsE) : 0;
+  unsigned ge = c->n_gamma > 0 ? upd_grid(c->n_gamma, ld) : 0;
   if (c->n_gamma > 0)
     hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 0, c->n_gamma, ld, nrhs,
                        op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr,
-                       c->direction_kernel);
+                       c->direction_kernel, (const int *)nullptr, 0, upd_cpw(ld));
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
     dd_status ps = prec == DD_FP64
@@ -614,7 +624,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       PhaseTimer t(c, DD_PHASE_UPDATE);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
                          op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, c->red, c->st, o.precond,
-                         nact_dst, 0, (const int *)nullptr, c->gamma_parts);
+                         nact_dst, 0, (const int *)nullptr, c->gamma_parts, upd_cpw(ld));
     }
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
@@ -684,21 +694,38 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     c->last_launch = DD_LAUNCH_GRAPH;
   } else {
+    // The update kernel of iteration `it` stores (active columns + 1) into
+    // host memory h_nact[it % nslots]; the host waits for that value of
+    // iteration it - lag by reading it (no event per iteration: an event
+    // record adds a release of the caches and a gap between kernels).
+    volatile int *hn = (volatile int *)c->h_nact;
+    auto wait_slot = [&](int s2) -> dd_status {
+      for (long spins = 1; hn[s2] == 0; ++spins) {
+        if ((spins & 255) == 0) {
+          hipError_t q = hipStreamQuery(c->stream);
+          if (q == hipSuccess) {               // stream drained: the value must be there
+            if (hn[s2] == 0) return fail(c, DD_EHIP, "CG state not published by the update kernel");
+            break;
+          }
+          if (q != hipErrorNotReady)
+            return fail(c, DD_EHIP, std::string("hipStreamQuery: ") + hipGetErrorString(q));
+        }
+      }
+      return DD_OK;
+    };
     while (!stop && it < o.max_it) {
       ++it;
       int slot = it % c->nslots;
-      c->h_nact[slot] = 0;
+      hn[slot] = 0;
       TRY(iteration(pA, pB, c->h_nact_dev + slot));
-      HIPCHK(c, hipEventRecord(c->ev[slot], c->stream));
       ring_it[slot] = it;
-      // look at iteration it - lag (blocking), never more than nslots in flight
+      // look at iteration it - lag, never more than nslots in flight
       int target = it - lag;
       while (observed < target) {
         int s2 = (observed + 1) % c->nslots;
-        HIPCHK(c, hipEventSynchronize(c->ev[s2]));
+        TRY(wait_slot(s2));
         ++observed;
-        int v = ((volatile int *)c->h_nact)[s2];
-        if (v == 1) {
+        if (hn[s2] == 1) {
           stop = true;
           break;
         }
@@ -710,6 +737,15 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   interior_solve(c, prec, o.apply, w.yI, uI, ld);
   HIPCHK(c, hipGetLastError());
   return DD_OK;
+}
+
+// Squared stopping threshold of the inner (FP32-operator) CG of one
+// refinement step: the relative reduction inner_tol of the current FP64
+// residual, but never tighter than half the outer target tol * ||b||, so the
+// last step stops as soon as the outer tolerance can be met instead of
+// reducing the residual by inner_tol once more.
+inline double inner_stop2(double inner_tol, double tol, double rn2, double bn2) {
+  return std::max(inner_tol * inner_tol * rn2, 0.25 * tol * tol * bn2);
 }
 
 dd_status fetch_state(dd_ctx *c, StateBlock *h) {
@@ -913,6 +949,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->batch.d_mask, kMaxLd)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_solve_mask, kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->batch.d_slots, kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bad, 1)) != DD_OK) return bail(s);
   if (hipMemset(c->red.counter, 0, 8 * sizeof(unsigned)) != hipSuccess) {
@@ -1117,9 +1154,9 @@ dd_status batch_start_cg(dd_ctx *c, const int *mask, const double *rI, const dou
   std::vector<double> st2(B.stop2, B.stop2 + kMaxLd);
   HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
   if (c->n_gamma > 0)
-    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(c->n_gamma, kRowsE)), dim3(kBlock), 0, c->stream, 2,
+    hipLaunchKernelGGL(k_cg_update, dim3(upd_grid(c->n_gamma, ld)), dim3(kBlock), 0, c->stream, 2,
                        c->n_gamma, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, c->red, c->st,
-                       B.o.precond, (int *)nullptr, 0, (const int *)B.d_mask);
+                       B.o.precond, (int *)nullptr, 0, (const int *)B.d_mask, 0, upd_cpw(ld));
   HIPCHK(c, hipGetLastError());
   return DD_OK;
 }
@@ -1191,8 +1228,8 @@ dd_status dd_batch_admit(dd_ctx *c, const int32_t *slots, int32_t ncol, const do
       B.rn2[j] = bn[j];
       B.its[j] = B.steps[j] = B.conv[j] = B.stall[j] = 0;
       B.prev[j] = -1.0;
-      double t = B.prec == DD_FP64 ? B.o.tol : B.o.inner_tol;
-      B.stop2[j] = t * t * bn[j];
+      B.stop2[j] = B.prec == DD_FP64 ? B.o.tol * B.o.tol * bn[j]
+                                     : inner_stop2(B.o.inner_tol, B.o.tol, bn[j], bn[j]);
     }
   return batch_start_cg(c, mask.data(), w.bI, w.bG);
 }
@@ -1208,7 +1245,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
   bool any = false;
   for (int j = 0; j < kMaxLd; ++j) any |= B.state[j] == DD_SLOT_RUNNING;
   if (any && iters > 0 && c->n_gamma > 0) {
-    unsigned ge = grid_for(c->n_gamma, kRowsE);
+    unsigned ge = upd_grid(c->n_gamma, L);
     double *pA = w.pG, *pB = w.xG;
     for (int it = 0; it < iters; ++it) {
       Src P{nullptr, w.zG, pA, c->st.beta};
@@ -1217,7 +1254,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
       gamma_apply(c, prec, P, w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, pB);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, L, kMaxLd,
                          op.dinv, w.dG, w.rG, w.zG, pB, w.qG, c->red, c->st, B.o.precond,
-                         (int *)nullptr, 0, (const int *)nullptr, c->gamma_parts);
+                         (int *)nullptr, 0, (const int *)nullptr, c->gamma_parts, upd_cpw(L));
       std::swap(pA, pB);
     }
     // keep the current direction in pG (the buffer the next step reads)
@@ -1282,7 +1319,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
           continue;
         }
         B.prev[j] = rn[j];
-        B.stop2[j] = B.o.inner_tol * B.o.inner_tol * rn[j];
+        B.stop2[j] = inner_stop2(B.o.inner_tol, B.o.tol, rn[j], B.bn2[j]);
         again[j] = 1;
         anyagain = true;
       }
@@ -1442,9 +1479,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0);
     for (int j = nrhs; j < kMaxLd; ++j) done[j] = 1;
     std::vector<int> mask(kMaxLd, 0);
-    int *dmask = nullptr;
-    HIPCHK(c, hipMalloc(&dmask, kMaxLd * sizeof(int)));
-    struct Free { int *p; ~Free() { if (p) (void)hipFree(p); } } fr{dmask};
+    int *dmask = c->d_solve_mask;
     for (int step = 0;; ++step) {
       // FP64 residual (step 0: r = b)
       if (step == 0) {
@@ -1471,7 +1506,8 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
       for (int j = 0; j < kMaxLd; ++j) mask[j] = done[j] ? 0 : 1;
       HIPCHK(c, hipMemcpyAsync(dmask, mask.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
       std::vector<double> st2(kMaxLd, 0.0);
-      for (int j = 0; j < kMaxLd; ++j) st2[j] = mask[j] ? o.inner_tol * o.inner_tol * rn2[j] : 0.0;
+      for (int j = 0; j < kMaxLd; ++j)
+        st2[j] = mask[j] ? inner_stop2(o.inner_tol, o.tol, rn2[j], bn2[j]) : 0.0;
       HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
       for (int j = 0; j < nrhs; ++j)
         if (!mask[j]) {
