@@ -647,6 +647,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
     if (lane == 0) {
+      if (mode == 0) st.flag[0] = 0;     // a new solve starts without breakdown
       if (st.flag[0]) na = 0;            // breakdown ends the loop
       st.flag[1] = na > 0 ? 1 : 0;       // loop decision for the persistent launch
       if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -733,6 +734,90 @@ k_colnorm2(int nrows, int ld, const double *__restrict__ v, RedBuf red, double *
   }
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(&red.counter[2]);
+}
+
+// out[c] = squared 2-norm of column c of the stacked vector [vI; vG]
+// (nI + nG rows in the DD layout): 64-row chunk partials by the wave
+// butterfly, summed in order by the last workgroup.  With stop2 != nullptr
+// also stop2[c] = f2 * out[c] (CG stopping thresholds).
+__global__ void __launch_bounds__(kBlock)
+k_norm2(int nI, int nG, int ld, const double *__restrict__ vI, const double *__restrict__ vG,
+        RedBuf red, double *__restrict__ out, double f2, double *__restrict__ stop2) {
+  __shared__ double lds[kRowsE * kMaxLd];
+  __shared__ int lflag;
+  const int n = nI + nG;
+  const int row0 = blockIdx.x * kRowsE;
+  const int wv = wave_id(), lane = lane_id();
+  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
+    int lr = e / ld, c = e - lr * ld;
+    int j = row0 + lr;
+    double t = 0.0;
+    if (j < n) {
+      double a = j < nI ? vI[(size_t)j * ld + c] : vG[(size_t)(j - nI) * ld + c];
+      t = a * a;
+    }
+    lds[lr * ld + c] = t;
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double sm = chunk64_sum(lds, ld, c);
+    if (lane == 0) store_partial(red.part0 + (size_t)blockIdx.x * ld + c, sm);
+  }
+  if (!last_block(&red.counter[2], &lflag)) return;
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    double sm = partials_sum(red.part0, gridDim.x, ld, c);
+    if (lane == 0) {
+      out[c] = sm;
+      if (stop2) stop2[c] = f2 * sm;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) reset_counter(&red.counter[2]);
+}
+
+// Right-hand sides into the DD layout, both parts in one launch: row i < nI
+// of the stacked output is b[imap[i]], row nI + k is b[gmap[k]]; columns
+// c >= nrhs of the ld-wide layout are zero.
+__global__ void k_gather2(int nI, int nG, const int *__restrict__ imap, const int *__restrict__ gmap,
+                          const double *__restrict__ b, int ldb, int nrhs, int ld,
+                          double *__restrict__ outI, double *__restrict__ outG) {
+  size_t total = (size_t)(nI + nG) * ld;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int i = (int)(e / ld), c = (int)(e % ld);
+    bool in = i < nI;
+    int g = in ? imap[i] : gmap[i - nI];
+    double v = c < nrhs ? b[(size_t)c * ldb + g] : 0.0;
+    if (in) outI[e] = v;
+    else outG[e - (size_t)nI * ld] = v;
+  }
+}
+
+// Solution out of the DD layout, both parts in one launch.
+__global__ void k_scatter2(int nI, int nG, const int *__restrict__ imap, const int *__restrict__ gmap,
+                           const double *__restrict__ inI, const double *__restrict__ inG, int ld,
+                           int nrhs, double *__restrict__ u, int ldu) {
+  const int n = nI + nG;
+  size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e / n), i = (int)(e % n);
+    if (i < nI) u[(size_t)c * ldu + imap[i]] = inI[(size_t)i * ld + c];
+    else u[(size_t)c * ldu + gmap[i - nI]] = inG[(size_t)(i - nI) * ld + c];
+  }
+}
+
+// y += x on the columns with mask[c] != 0, both parts in one launch.
+__global__ void k_axpy2_masked(size_t nIe, size_t nGe, int ld, const double *__restrict__ xI,
+                               const double *__restrict__ xG, double *__restrict__ yI,
+                               double *__restrict__ yG, const int *__restrict__ mask) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nIe + nGe;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e % ld);
+    if (!mask[c]) continue;
+    if (e < nIe) yI[e] += xI[e];
+    else yG[e - nIe] += xG[e - nIe];
+  }
 }
 
 // Deterministic synthetic right-hand sides for the autotuner: entry (i, c) of

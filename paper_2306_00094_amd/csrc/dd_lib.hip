@@ -85,6 +85,9 @@ struct dd_ctx {
   int gamma_parts = 0;                  // p^T q group sums written by the last interface-row launch
   // host polling
   int *h_nact = nullptr;          // pinned, mapped
+  StateBlock *h_state = nullptr;   // pinned copy target of the device state block
+  int *h_mask = nullptr;           // pinned staging of per-column masks (kMaxLd)
+  double *h_stop2 = nullptr;       // pinned staging of stopping thresholds (kMaxLd)
   int *h_nact_dev = nullptr;
   int nslots = 0;
   std::vector<hipEvent_t> ev;
@@ -567,13 +570,14 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
                      double *uG, int ld, int nrhs, const CoreOpts &o) {
   Work &w = c->w;
   const Ops &op = c->op[prec];
-  HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
   // condensation (eq. subForcing summed over subdomains): r = bG - K_GI K_II^{-1} bI
   interior_solve(c, prec, o.apply, bI, w.wI, ld);
   gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
   unsigned ge = c->n_gamma > 0 ? upd_grid(c->n_gamma, ld) : 0;
+  if (c->n_gamma == 0)            // no init kernel to clear the breakdown flag
+    HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
   if (c->n_gamma > 0)
     hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 0, c->n_gamma, ld, nrhs,
                        op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr,
@@ -805,6 +809,9 @@ void dd_destroy(dd_ctx *c) {
   for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->h_nact) (void)hipHostFree(c->h_nact);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  if (c->h_mask) (void)hipHostFree(c->h_mask);
+  if (c->h_stop2) (void)hipHostFree(c->h_stop2);
   delete c;
 }
 
@@ -958,7 +965,10 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   }
   c->nslots = 16;
   if (hipHostMalloc((void **)&c->h_nact, c->nslots * sizeof(int), hipHostMallocMapped) != hipSuccess ||
-      hipHostGetDevicePointer((void **)&c->h_nact_dev, c->h_nact, 0) != hipSuccess) {
+      hipHostGetDevicePointer((void **)&c->h_nact_dev, c->h_nact, 0) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_state, sizeof(StateBlock), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_mask, kMaxLd * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_stop2, kMaxLd * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     c->err = "pinned host allocation failed";
     return bail(DD_ENOMEM);
   }
@@ -1261,7 +1271,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
     if (pA != w.pG) std::swap(w.pG, w.xG);
     HIPCHK(c, hipGetLastError());
   }
-  StateBlock h;
+  StateBlock &h = *c->h_state;
   TRY(fetch_state(c, &h));
   // slots whose CG finished: back substitution of the correction and update of u
   std::vector<int> fin(kMaxLd, 0);
@@ -1434,35 +1444,51 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
               o.check_every,
               (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS};
   Work &w = c->w;
-  // gather b into the DD layout
-  hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->NI * L, 256))), dim3(256), 0,
-                     c->stream, c->NI, c->d_imap, b_dev, ld, nrhs, L, w.bI);
-  if (c->n_gamma > 0)
-    hipLaunchKernelGGL(k_gather, dim3(std::min(4096u, grid_for((size_t)c->n_gamma * L, 256))), dim3(256),
-                       0, c->stream, c->n_gamma, c->d_gmap, b_dev, ld, nrhs, L, w.bG);
+  // gather b into the DD layout (both parts in one launch)
+  const int n_all = c->NI + c->n_gamma;
+  hipLaunchKernelGGL(k_gather2, dim3(std::min(4096u, grid_for((size_t)n_all * L, 256))), dim3(256), 0,
+                     c->stream, c->NI, c->n_gamma, c->d_imap, c->d_gmap, b_dev, ld, nrhs, L, w.bI, w.bG);
   HIPCHK(c, hipGetLastError());
-  TRY(dd_norm2(c, L, w.bI, w.bG, w.bnrm2));
-  std::vector<double> bn2(kMaxLd, 0.0), rn2(kMaxLd, 0.0);
-  std::vector<int> its(kMaxLd, 0), conv(kMaxLd, 0), steps(kMaxLd, 0), fb(kMaxLd, 0);
-  dd_status result = DD_OK;
-
-  auto read_iters = [&](std::vector<int> &dst, bool add) -> dd_status {
-    StateBlock h;
-    TRY(fetch_state(c, &h));
-    for (int j = 0; j < nrhs; ++j) dst[j] = add ? dst[j] + h.iters[j] : h.iters[j];
+  // squared column norms of a stacked [vI; vG] (optionally stop2 = f2 * norm)
+  auto norm2 = [&](const double *vI, const double *vG, double *out, double f2, double *stop2) {
+    hipLaunchKernelGGL(k_norm2, dim3(grid_for((size_t)n_all, kRowsE)), dim3(kBlock), 0, c->stream,
+                       c->NI, c->n_gamma, L, vI, vG, c->red, out, f2, stop2);
+  };
+  auto scatter = [&]() {
+    hipLaunchKernelGGL(k_scatter2, dim3(std::min(4096u, grid_for((size_t)n_all * nrhs, 256))), dim3(256),
+                       0, c->stream, c->NI, c->n_gamma, c->d_imap, c->d_gmap, w.uI, w.uG, L, nrhs,
+                       u_dev, ld);
+  };
+  auto axpy = [&](const int *dmask) {
+    size_t nIe = (size_t)c->NI * L, nGe = (size_t)c->n_gamma * L;
+    hipLaunchKernelGGL(k_axpy2_masked, dim3(std::min(4096u, grid_for(nIe + nGe, 256))), dim3(256), 0,
+                       c->stream, nIe, nGe, L, w.dI, w.dG, w.uI, w.uG, dmask);
+  };
+  // zero the right-hand side columns of t that take no part in an inner solve
+  auto zero_unmasked = [&](const int *mask) -> dd_status {
+    for (int j = 0; j < nrhs; ++j)
+      if (!mask[j]) {
+        HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
+        if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
+      }
     return DD_OK;
   };
+  std::vector<double> bn2(kMaxLd, 0.0), rn2(kMaxLd, 0.0);
+  std::vector<int> its(kMaxLd, 0), conv(kMaxLd, 0), steps(kMaxLd, 0), fb(kMaxLd, 0);
+  StateBlock &h = *c->h_state;
+  dd_status result = DD_OK;
 
   if (prec == DD_FP64) {
-    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(kMaxLd), 0, c->stream, L, o.tol * o.tol, w.bnrm2, c->st);
+    norm2(w.bI, w.bG, w.bnrm2, o.tol * o.tol, c->st.stop2);
     dd_status s = core_solve(c, DD_FP64, w.bI, w.bG, w.uI, w.uG, L, nrhs, co);
     if (s != DD_OK) return s;
     if (o.verify) {
       full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
-      TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
+      norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
     }
-    StateBlock h;
-    TRY(fetch_state(c, &h));
+    scatter();
+    HIPCHK(c, hipGetLastError());
+    TRY(fetch_state(c, &h));              // one wait for the whole solve
     for (int j = 0; j < nrhs; ++j) {
       its[j] = h.iters[j];
       conv[j] = !h.active[j];
@@ -1471,55 +1497,55 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     }
   } else {
     // Mixed precision iterative refinement on the full system (FP64 residual):
-    //   r = b - A u;  inner DD solve with FP32 operators to inner_tol;  u += d.
-    HIPCHK(c, hipMemsetAsync(w.uI, 0, (size_t)c->NI * L * 8, c->stream));
-    HIPCHK(c, hipMemsetAsync(w.uG, 0, (size_t)c->n_gamma * L * 8, c->stream));
-    HIPCHK(c, hipMemcpy(bn2.data(), w.bnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
+    //   r = b - A u;  inner DD solve with FP32 operators;  u += d.
+    // Step 0 solves with r = b straight into u; its stopping thresholds come
+    // from ||b|| on the device, so no host round trip precedes it.
+    int *mask = c->h_mask;
+    double *st2 = c->h_stop2;
+    {
+      const double f20 = std::max(o.inner_tol * o.inner_tol, 0.25 * o.tol * o.tol);
+      norm2(w.bI, w.bG, w.bnrm2, f20, c->st.stop2);
+      dd_status s = core_solve(c, DD_MIXED, w.bI, w.bG, w.uI, w.uG, L, nrhs, co);
+      if (s != DD_OK) return s;
+    }
+    for (int j = 0; j < kMaxLd; ++j) mask[j] = j < nrhs ? 1 : 0;     // columns of the last inner solve
     std::vector<double> prev(kMaxLd, -1.0);
     std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0);
     for (int j = nrhs; j < kMaxLd; ++j) done[j] = 1;
-    std::vector<int> mask(kMaxLd, 0);
-    int *dmask = c->d_solve_mask;
-    for (int step = 0;; ++step) {
-      // FP64 residual (step 0: r = b)
-      if (step == 0) {
-        HIPCHK(c, hipMemcpyAsync(w.tI, w.bI, (size_t)c->NI * L * 8, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(w.tG, w.bG, (size_t)c->n_gamma * L * 8, hipMemcpyDeviceToDevice, c->stream));
-      } else {
-        full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
-      }
-      TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
-      HIPCHK(c, hipMemcpy(rn2.data(), w.rnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
+    for (int step = 1;; ++step) {
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
+      TRY(fetch_state(c, &h));            // inner iterations, ||b||, ||r||: one wait per step
       bool any = false;
       for (int j = 0; j < nrhs; ++j) {
+        if (mask[j]) {
+          its[j] += h.iters[j];
+          steps[j] += 1;
+        }
+        bn2[j] = h.bnrm2[j];
+        rn2[j] = h.rnrm2[j];
+        if (step == 1) prev[j] = bn2[j];  // the residual before the first step is b
+        mask[j] = 0;
         if (done[j]) continue;
         if (rn2[j] <= o.tol * o.tol * bn2[j]) { done[j] = 1; conv[j] = 1; continue; }
-        if (prev[j] >= 0.0 && rn2[j] > 0.25 * prev[j]) {   // reduction worse than 0.5 in norm
+        if (rn2[j] > 0.25 * prev[j]) {    // reduction worse than 0.5 in norm
           if (++stall[j] >= 2) { done[j] = 1; need_fb[j] = 1; continue; }
         }
         if (step >= o.max_refine) { done[j] = 1; need_fb[j] = 1; continue; }
         prev[j] = rn2[j];
+        mask[j] = 1;
+        st2[j] = inner_stop2(o.inner_tol, o.tol, rn2[j], bn2[j]);
         any = true;
       }
       if (!any) break;
-      // inner solve on the residual; finished columns get a zero right-hand side
-      for (int j = 0; j < kMaxLd; ++j) mask[j] = done[j] ? 0 : 1;
-      HIPCHK(c, hipMemcpyAsync(dmask, mask.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
-      std::vector<double> st2(kMaxLd, 0.0);
-      for (int j = 0; j < kMaxLd; ++j)
-        st2[j] = mask[j] ? inner_stop2(o.inner_tol, o.tol, rn2[j], bn2[j]) : 0.0;
-      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
-      for (int j = 0; j < nrhs; ++j)
-        if (!mask[j]) {
-          HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
-          if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
-        }
+      for (int j = nrhs; j < kMaxLd; ++j) { mask[j] = 0; st2[j] = 0.0; }
+      for (int j = 0; j < nrhs; ++j) if (!mask[j]) st2[j] = 0.0;
+      HIPCHK(c, hipMemcpyAsync(c->d_solve_mask, mask, kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2, kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+      TRY(zero_unmasked(mask));
       dd_status s = core_solve(c, DD_MIXED, w.tI, w.tG, w.dI, w.dG, L, nrhs, co);
       if (s != DD_OK) return s;
-      TRY(read_iters(its, true));
-      for (int j = 0; j < nrhs; ++j) if (mask[j]) steps[j] += 1;
-      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->NI * L, L, w.dI, w.uI, dmask);
-      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->n_gamma * L, L, w.dG, w.uG, dmask);
+      axpy(c->d_solve_mask);
       HIPCHK(c, hipGetLastError());
     }
     // FP64 fallback for columns whose refinement stalled
@@ -1530,38 +1556,32 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
         dd_status s = dd_factor(c, DD_FP64);
         if (s != DD_OK) return s;
       }
-      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
-      for (int j = 0; j < kMaxLd; ++j) mask[j] = (j < nrhs && need_fb[j]) ? 1 : 0;
-      HIPCHK(c, hipMemcpyAsync(dmask, mask.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
-      std::vector<double> st2(kMaxLd, 0.0);
-      for (int j = 0; j < kMaxLd; ++j) st2[j] = mask[j] ? o.tol * o.tol * bn2[j] : 0.0;
-      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
-      for (int j = 0; j < nrhs; ++j)
-        if (!mask[j]) {
-          HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
-          if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
-        }
+      for (int j = 0; j < kMaxLd; ++j) {
+        mask[j] = (j < nrhs && need_fb[j]) ? 1 : 0;
+        st2[j] = mask[j] ? o.tol * o.tol * bn2[j] : 0.0;
+      }
+      HIPCHK(c, hipMemcpyAsync(c->d_solve_mask, mask, kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2, kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+      TRY(zero_unmasked(mask));           // t still holds the last residual
       dd_status s = core_solve(c, DD_FP64, w.tI, w.tG, w.dI, w.dG, L, nrhs, co);
       if (s != DD_OK) return s;
-      TRY(read_iters(its, true));
-      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->NI * L, L, w.dI, w.uI, dmask);
-      hipLaunchKernelGGL(k_axpy_masked, dim3(1024), dim3(256), 0, c->stream, (size_t)c->n_gamma * L, L, w.dG, w.uG, dmask);
-      for (int j = 0; j < nrhs; ++j) if (mask[j]) fb[j] = 1;
+      axpy(c->d_solve_mask);
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
+      TRY(fetch_state(c, &h));
+      for (int j = 0; j < nrhs; ++j) {
+        if (mask[j]) {
+          its[j] += h.iters[j];
+          fb[j] = 1;
+        }
+        rn2[j] = h.rnrm2[j];
+      }
     }
-    // final FP64 residual
-    full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
-    TRY(dd_norm2(c, L, w.tI, w.tG, w.rnrm2));
-    HIPCHK(c, hipMemcpy(rn2.data(), w.rnrm2, kMaxLd * 8, hipMemcpyDeviceToHost));
     for (int j = 0; j < nrhs; ++j) conv[j] = rn2[j] <= o.tol * o.tol * bn2[j] * (1.0 + 1e-12);
+    scatter();
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
-  // scatter the DD-layout solution into u
-  hipLaunchKernelGGL(k_scatter, dim3(std::min(4096u, grid_for((size_t)c->NI * nrhs, 256))), dim3(256), 0,
-                     c->stream, c->NI, c->d_imap, w.uI, L, nrhs, u_dev, ld);
-  if (c->n_gamma > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(std::min(4096u, grid_for((size_t)c->n_gamma * nrhs, 256))), dim3(256),
-                       0, c->stream, c->n_gamma, c->d_gmap, w.uG, L, nrhs, u_dev, ld);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int j = 0; j < nrhs; ++j) {
     if (!conv[j]) result = DD_ENOCONV;
     if (info) {
