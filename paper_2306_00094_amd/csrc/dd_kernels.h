@@ -1,11 +1,13 @@
 // Device code of the substructuring Schur-complement solver (gfx950).
 //
-// Every per-row product is computed by one 64-lane wavefront: lane l takes
-// the row entries l, l+64, l+128, ... in order and the 64 partial sums are
-// combined by an xor butterfly.  A row's result therefore depends only on the
-// row and on the column of right-hand sides it belongs to -- never on how
-// many right-hand sides share the launch, or on the launch shape -- which is
-// what makes a request's result identical alone and inside a batch.
+// Every per-row product is computed by one aligned group of G lanes (the
+// whole 64-lane wavefront, or half of it for the interface rows): lane l of
+// the group takes the row entries l, l+G, l+2G, ... in order and the G
+// partial sums are combined by an xor butterfly.  A row's result therefore
+// depends only on the row and on the column of right-hand sides it belongs
+// to -- never on how many right-hand sides share the launch, or on the launch
+// shape -- which is what makes a request's result identical alone and inside
+// a batch.
 //
 // Dot products are reduced deterministically: fixed row chunks are reduced
 // in a fixed order (a wave butterfly over 64 rows, or rows in order), and the
