@@ -317,11 +317,25 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
 
 // out = base + sign * A x  for CSR rows (one wave per row).
 // Used for y = K_IG p and for the back-substitution right side b_I - K_IG u_G.
+// With OTF and dir != nullptr the kernel also stores the direction it forms
+// at its gathers, dir = z + beta pp, for the ndir interface rows (a slice per
+// workgroup), so later kernels of the iteration gather it as a plain vector.
 template <int C, typename VT, bool OTF>
 __global__ void __launch_bounds__(kBlock)
 k_csr_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
            const VT *__restrict__ val, Src x, int ld,
-           const double *__restrict__ base, double sign, double *__restrict__ out) {
+           const double *__restrict__ base, double sign, double *__restrict__ out,
+           int ndir = 0, double *__restrict__ dir = nullptr) {
+  if (OTF && dir) {
+    const int per = (ndir + gridDim.x - 1) / gridDim.x;
+    const int j0 = blockIdx.x * per;
+    const int n = max(0, min(per, ndir - j0)) * ld;
+    for (int e = threadIdx.x; e < n; e += kBlock) {
+      const size_t o = (size_t)j0 * ld + e;
+      const int c = e % ld;
+      dir[o] = fma(x.beta[c], x.pp[o], x.z[o]);
+    }
+  }
   int row = blockIdx.x * kWavesPerBlock + wave_id();
   if (row >= nrows) return;
   int b = ptr[row], e = ptr[row + 1];

@@ -258,25 +258,26 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
 // ------------------------------------------------------------ launchers --
 template <int C, typename VT>
 void launch_csr(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *val,
-                Src x, int ld, const double *base, double sign, double *out) {
+                Src x, int ld, const double *base, double sign, double *out, double *dir) {
   if (nrows <= 0) return;
   if (x.z)
     hipLaunchKernelGGL((k_csr_rows<C, VT, true>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
-                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
+                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out,
+                       dir ? c->n_gamma : 0, dir);
   else
     hipLaunchKernelGGL((k_csr_rows<C, VT, false>), dim3(grid_for(nrows, kWavesPerBlock)), dim3(kBlock), 0,
-                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out);
+                       c->stream, nrows, ptr, col, val, x, ld, base, sign, out, 0, (double *)nullptr);
 }
 
 template <typename VT>
 void csr_rows(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *val,
-              Src x, int ld, const double *base, double sign, double *out) {
+              Src x, int ld, const double *base, double sign, double *out, double *dir = nullptr) {
   switch (std::min(ld, 16)) {
-    case 1: launch_csr<1, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
-    case 2: launch_csr<2, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
-    case 4: launch_csr<4, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
-    case 8: launch_csr<8, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
-    default: launch_csr<16, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out); break;
+    case 1: launch_csr<1, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out, dir); break;
+    case 2: launch_csr<2, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out, dir); break;
+    case 4: launch_csr<4, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out, dir); break;
+    case 8: launch_csr<8, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out, dir); break;
+    default: launch_csr<16, VT>(c, nrows, ptr, col, val, x, ld, base, sign, out, dir); break;
   }
 }
 
@@ -375,14 +376,16 @@ void interior_solve(dd_ctx *c, int prec, int apply, const double *y, double *z, 
 }
 
 // y = K_IG x (+ base, sign) with the coupling values of `prec`.
+// y = base + sign * K_IG x; with an on-the-fly direction x and dir != nullptr
+// the launch also stores that direction (all interface rows) into dir.
 void kig_apply(dd_ctx *c, int prec, Src x, int ld, const double *base, double sign,
-               double *out) {
+               double *out, double *dir = nullptr) {
   if (prec == DD_FP64)
     csr_rows<double>(c, c->NI, c->d_ig_ptr, c->d_ig_col, (const double *)c->op[0].ig_val, x, ld,
-                     base, sign, out);
+                     base, sign, out, dir);
   else
     csr_rows<float>(c, c->NI, c->d_ig_ptr, c->d_ig_col, (const float *)c->op[1].ig_val, x, ld,
-                    base, sign, out);
+                    base, sign, out, dir);
 }
 
 void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const double *base,
@@ -612,9 +615,11 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     const bool dk = c->direction_kernel != 0;
     Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
+    // (formed at the K_IG gathers, which also store it into pB for the rest of
+    // the iteration)
     {
       PhaseTimer t(c, DD_PHASE_KIG);
-      kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI);
+      kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI, dk ? nullptr : pB_);
     }
     {
       PhaseTimer t(c, DD_PHASE_INTERIOR);
@@ -622,7 +627,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     {
       PhaseTimer t(c, DD_PHASE_GAMMA);
-      gamma_apply(c, prec, P, w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, dk ? nullptr : pB_);
+      gamma_apply(c, prec, dk ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
     }
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
@@ -1259,9 +1264,9 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
     double *pA = w.pG, *pB = w.xG;
     for (int it = 0; it < iters; ++it) {
       Src P{nullptr, w.zG, pA, c->st.beta};
-      kig_apply(c, prec, P, L, nullptr, 1.0, w.yI);
+      kig_apply(c, prec, P, L, nullptr, 1.0, w.yI, pB);
       interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);
-      gamma_apply(c, prec, P, w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, pB);
+      gamma_apply(c, prec, plain(pB), w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
       hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, L, kMaxLd,
                          op.dinv, w.dG, w.rG, w.zG, pB, w.qG, c->red, c->st, B.o.precond,
                          (int *)nullptr, 0, (const int *)nullptr, c->gamma_parts, upd_cpw(L));
