@@ -545,27 +545,57 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 //   update: iters += 1; converged when r.r <= stop2; beta = r.z / rz_old
 // and, when host_nact is given, publishes (number of active columns + 1) to
 // host memory (a plain system-coherent store: the host reads only that value).
-constexpr int kUpdMaxE = kRowsE * kMaxLd / kBlock;   // elements per thread per chunk
+// E = elements per thread (cpw * kRowsE * ld / kBlock, at least 1).
+template <int E>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
             int use_precond, int *__restrict__ host_nact, int init_p_is_z,
-            const int *__restrict__ mask = nullptr, int npq = 0, int cpw = 1) {
+            const int *__restrict__ mask, int npq, int cpw) {
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ double salpha[kMaxLd];
   __shared__ int sact[kMaxLd];
   __shared__ int lflag;
   const int wv = wave_id(), lane = lane_id();
+  const int nchunks = (nrows + kRowsE - 1) / kRowsE;
+  const int chunk0 = blockIdx.x * cpw;
+  const int nck = min(cpw, nchunks - chunk0);         // chunks of this workgroup
+  const int nel = nck * kRowsE * ld;                  // <= E * kBlock
+  const int row0 = chunk0 * kRowsE;
+  // this thread's elements, loaded before the step length is known (their
+  // loads overlap the reduction below)
+  double rv[E], qv[E], xv[E], pv[E], dv[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    rv[k] = qv[k] = xv[k] = pv[k] = 0.0;
+    dv[k] = 1.0;
+    if (e < nel) {
+      const int lr = e / ld, c = e - lr * ld, j = row0 + lr;
+      if (j < nrows) {
+        const size_t o = (size_t)j * ld + c;
+        rv[k] = r[o];
+        if (mode != 0) qv[k] = q[o];                   // mode 2: new residual in q
+        if (mode == 1) {
+          xv[k] = x[o];
+          pv[k] = p[o];
+        }
+        if (use_precond) dv[k] = dinv[j];
+      }
+    }
+  }
   if (mode == 1) {
     for (int c = wv; c < ld; c += kWavesPerBlock) {
+      const int act0 = st.active[c];
+      const double rz0 = st.rz[c];
       double pq = partials_sum(red.part3, npq, ld, c);
       if (lane == 0) {
-        int act = st.active[c];
+        int act = act0;
         double a = 0.0;
         if (act) {
           if (!(pq > 0.0)) act = 0;
-          else a = st.rz[c] / pq;
+          else a = rz0 / pq;
         }
         salpha[c] = a;
         sact[c] = act;
@@ -573,15 +603,10 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     }
     __syncthreads();
   }
-  const int nchunks = (nrows + kRowsE - 1) / kRowsE;
-  const int chunk0 = blockIdx.x * cpw;
-  const int nck = min(cpw, nchunks - chunk0);         // chunks of this workgroup
-  const int nel = nck * kRowsE * ld;                  // <= kRowsE * kMaxLd (cpw * ld <= 64)
-  const int row0 = chunk0 * kRowsE;
   // element-wise update; products r*z to LDS, r*r kept in registers
-  double rrv[kUpdMaxE];
+  double rrv[E];
 #pragma unroll
-  for (int k = 0; k < kUpdMaxE; ++k) {
+  for (int k = 0; k < E; ++k) {
     const int e = threadIdx.x + k * kBlock;
     rrv[k] = 0.0;
     if (e < nel) {
@@ -589,24 +614,24 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       const int j = row0 + lr;
       double rz = 0.0;
       if (j < nrows) {
-        size_t o = (size_t)j * ld + c;
-        bool init = mode == 0 || (mode == 2 && mask[c]);
-        double rv = (mode == 2 && init) ? q[o] : r[o];     // mode 2: new residual in q
-        if (mode == 2 && init) r[o] = rv;
-        bool act = init ? true : (mode == 1 && sact[c] != 0);
+        const size_t o = (size_t)j * ld + c;
+        const bool init = mode == 0 || (mode == 2 && mask[c]);
+        double rr_ = (mode == 2 && init) ? qv[k] : rv[k];
+        if (mode == 2 && init) r[o] = rr_;
+        const bool act = init ? true : (mode == 1 && sact[c] != 0);
         if (mode == 1 && act) {
-          double a = salpha[c];
-          x[o] = fma(a, p[o], x[o]);
-          rv = fma(-a, q[o], rv);
-          r[o] = rv;
+          const double a = salpha[c];
+          x[o] = fma(a, pv[k], xv[k]);
+          rr_ = fma(-a, qv[k], rr_);
+          r[o] = rr_;
         }
         if (init) x[o] = 0.0;
-        double zv = use_precond ? dinv[j] * rv : rv;
+        double zv = use_precond ? dv[k] * rr_ : rr_;
         if (act) z[o] = zv;
         else zv = z[o];
         if (init) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
-        rz = rv * zv;
-        rrv[k] = rv * rv;
+        rz = rr_ * zv;
+        rrv[k] = rr_ * rr_;
       }
       lds[e] = rz;
     }
@@ -615,11 +640,12 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
   for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
     const int k = t / ld, c = t - k * ld;
     double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
-    if (lane == 0) store_partial(red.part0 + (size_t)(chunk0 + k) * ld + c, sm);
+    if (lane == 0) __hip_atomic_store(red.part0 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kUpdMaxE; ++k) {
+  for (int k = 0; k < E; ++k) {
     const int e = threadIdx.x + k * kBlock;
     if (e < nel) lds[e] = rrv[k];
   }
@@ -627,34 +653,41 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
   for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
     const int k = t / ld, c = t - k * ld;
     double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
-    if (lane == 0) store_partial(red.part1 + (size_t)(chunk0 + k) * ld + c, sm);
+    if (lane == 0) __hip_atomic_store(red.part1 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
   }
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // both partial stores complete before the count
   if (!last_block(&red.counter[1], &lflag)) return;
   for (int c = wv; c < ld; c += kWavesPerBlock) {
+    // the column's state, loaded together with the partials
+    int active = st.active[c];
+    const double rzo = st.rz[c];
+    const int mk = mode == 2 ? mask[c] : 0;
+    const double s2 = st.stop2[c];
+    const int it0 = st.iters[c];
     double rz, rr;
     partials_sum2(red.part0, red.part1, nchunks, ld, c, rz, rr);
     if (lane == 0) {
-      int active = st.active[c];
-      if (mode == 0 || (mode == 2 && mask[c])) {
+      if (mode == 0 || (mode == 2 && mk)) {
         st.rz[c] = rz;
         st.iters[c] = 0;
         st.beta[c] = 0.0;
-        active = ((mode == 2 || c < nrhs) && rr > st.stop2[c]) ? 1 : 0;
+        active = ((mode == 2 || c < nrhs) && rr > s2) ? 1 : 0;
       } else if (mode == 1) {
         st.alpha[c] = salpha[c];
         if (active && !sact[c]) {           // breakdown: p^T q <= 0
           active = 0;
           st.flag[0] = 1;
         } else if (sact[c]) {
-          st.iters[c] += 1;
-          st.beta[c] = rz / st.rz[c];
+          st.iters[c] = it0 + 1;
+          st.beta[c] = rz / rzo;
           st.rz[c] = rz;
-          if (rr <= st.stop2[c]) active = 0;
+          if (rr <= s2) active = 0;
         }
       }
       st.active[c] = active;
       sact[c] = active;
-      if (mode != 2 || mask[c]) st.nrm2[c] = rr;
+      if (mode != 2 || mk) st.nrm2[c] = rr;
     }
   }
   __syncthreads();

@@ -329,6 +329,27 @@ inline unsigned upd_grid(int n_gamma, int ld) {
   return (ch + w - 1) / w;
 }
 
+// CG update launch; the elements per thread follow from the batch width.
+void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, double *x, double *r,
+                   double *z, double *p, const double *q, int precond, int *host_nact,
+                   int init_p_is_z, const int *mask, int npq) {
+  if (c->n_gamma <= 0) return;
+  const int cpw = upd_cpw(ld);
+  const dim3 g(upd_grid(c->n_gamma, ld)), b(kBlock);
+  const int E = std::max(1, cpw * kRowsE * ld / kBlock);
+#define DD_UPD(EE)                                                                              \
+  hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x, \
+                     r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw)
+  switch (E) {
+    case 1: DD_UPD(1); break;
+    case 2: DD_UPD(2); break;
+    case 4: DD_UPD(4); break;
+    case 8: DD_UPD(8); break;
+    default: DD_UPD(16); break;
+  }
+#undef DD_UPD
+}
+
 template <typename VT>
 void gamma_rows(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                 const double *base, double c1, double c2, double *out, int dot, double *pout) {
@@ -578,13 +599,11 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
-  unsigned ge = c->n_gamma > 0 ? upd_grid(c->n_gamma, ld) : 0;
   if (c->n_gamma == 0)            // no init kernel to clear the breakdown flag
     HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
   if (c->n_gamma > 0)
-    hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 0, c->n_gamma, ld, nrhs,
-                       op.dinv, uG, w.rG, w.zG, pA, w.qG, c->red, c->st, o.precond, (int *)nullptr,
-                       c->direction_kernel, (const int *)nullptr, 0, upd_cpw(ld));
+    launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
+                  c->direction_kernel, nullptr, 0);
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
     dd_status ps = prec == DD_FP64
@@ -631,9 +650,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
-      hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, ld, nrhs,
-                         op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, c->red, c->st, o.precond,
-                         nact_dst, 0, (const int *)nullptr, c->gamma_parts, upd_cpw(ld));
+      launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
+                    0, nullptr, c->gamma_parts);
     }
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
@@ -1169,9 +1187,8 @@ dd_status batch_start_cg(dd_ctx *c, const int *mask, const double *rI, const dou
   std::vector<double> st2(B.stop2, B.stop2 + kMaxLd);
   HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
   if (c->n_gamma > 0)
-    hipLaunchKernelGGL(k_cg_update, dim3(upd_grid(c->n_gamma, ld)), dim3(kBlock), 0, c->stream, 2,
-                       c->n_gamma, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, c->red, c->st,
-                       B.o.precond, (int *)nullptr, 0, (const int *)B.d_mask, 0, upd_cpw(ld));
+    launch_update(c, 2, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, B.o.precond, nullptr, 0,
+                  (const int *)B.d_mask, 0);
   HIPCHK(c, hipGetLastError());
   return DD_OK;
 }
@@ -1260,16 +1277,14 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
   bool any = false;
   for (int j = 0; j < kMaxLd; ++j) any |= B.state[j] == DD_SLOT_RUNNING;
   if (any && iters > 0 && c->n_gamma > 0) {
-    unsigned ge = upd_grid(c->n_gamma, L);
     double *pA = w.pG, *pB = w.xG;
     for (int it = 0; it < iters; ++it) {
       Src P{nullptr, w.zG, pA, c->st.beta};
       kig_apply(c, prec, P, L, nullptr, 1.0, w.yI, pB);
       interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);
       gamma_apply(c, prec, plain(pB), w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
-      hipLaunchKernelGGL(k_cg_update, dim3(ge), dim3(kBlock), 0, c->stream, 1, c->n_gamma, L, kMaxLd,
-                         op.dinv, w.dG, w.rG, w.zG, pB, w.qG, c->red, c->st, B.o.precond,
-                         (int *)nullptr, 0, (const int *)nullptr, c->gamma_parts, upd_cpw(L));
+      launch_update(c, 1, L, kMaxLd, op.dinv, w.dG, w.rG, w.zG, pB, w.qG, B.o.precond, nullptr, 0,
+                    nullptr, c->gamma_parts);
       std::swap(pA, pB);
     }
     // keep the current direction in pG (the buffer the next step reads)
