@@ -420,6 +420,59 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
   }
 }
 
+// Interior solve w = blockdiag(K_II^-1) y for wide batches: one wave takes
+// kRB consecutive rows of one subdomain (rb_first[b] = first row of block b;
+// blocks never cross subdomains) and shares every y load among them.  Each
+// lane visits the same entries in the same order as k_dense_rows and the
+// partial sums go through the same butterfly, so every entry is bit-identical
+// to the one-row-per-wave kernel.
+constexpr int kRB = 4;
+template <int C, typename MT, typename AT>
+__global__ void __launch_bounds__(kBlock)
+k_dense_rows_rb(int nblk, const int *__restrict__ rb_first, const MT *__restrict__ blocks,
+                const long long *__restrict__ koff, const int *__restrict__ ioff,
+                const int *__restrict__ ni, const int *__restrict__ rowsub,
+                const double *__restrict__ y, int ld, double *__restrict__ out) {
+  const int bk = blockIdx.x * kWavesPerBlock + wave_id();
+  if (bk >= nblk) return;
+  const int r0 = rb_first[bk];
+  const int k = rowsub[r0];
+  const int i0 = ioff[k], n = ni[k];
+  const int nr = min(kRB, i0 + n - r0);
+  const MT *rows = blocks + koff[k] + (size_t)(r0 - i0) * n;
+  const double *yb = y + (size_t)i0 * ld;
+  for (int cp = 0; cp < ld; cp += C) {
+    AT acc[kRB][C];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[r][c] = (AT)0;
+#pragma unroll 2
+    for (int j = lane_id(); j < n; j += kWave) {
+      AT a[kRB];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) a[r] = r < nr ? (AT)rows[(size_t)r * n + j] : (AT)0;
+      const double *yr = yb + (size_t)j * ld + cp;
+      AT yv[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) yv[c] = (AT)yr[c];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[r][c] = tfma(a[r], yv[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        AT v = wave_sum(acc[r][c]);
+        if (lane_id() == 0 && r < nr)
+          out[(size_t)(r0 + r) * ld + cp + c] = 0.0 + 1.0 * ((double)v + 0.0);
+      }
+    }
+  }
+}
+
 // Interface rows of [K_GG | K_GI]: per row, entries [ptr, split) are K_GG
 // (columns index p), entries [split, ptr+1) are K_GI (columns index z_I).
 //   out = base + c1 * K_GG p + c2 * K_GI z

@@ -68,6 +68,7 @@ struct dd_ctx {
   long long ktot = 0;
   size_t nnz_ig = 0, nnz_g = 0;
   // structure
+  int n_rb = 0, *d_rb_first = nullptr;   // row blocks of kRB rows (never crossing subdomains)
   int *d_ni = nullptr, *d_ioff = nullptr, *d_rowsub = nullptr, *d_imap = nullptr,
       *d_gmap = nullptr;
   long long *d_koff = nullptr;
@@ -388,6 +389,16 @@ void interior_solve(dd_ctx *c, int prec, int apply, const double *y, double *z, 
     else
       hipLaunchKernelGGL((k_trsm_apply<float, float>), grid, dim3(kBlock), 0, c->stream,
                          (const float *)c->op[1].L, c->d_koff, c->d_ioff, c->d_ni, y, z, ld, ncolw);
+    return;
+  }
+  if (ld >= 8 && c->n_rb > 0) {      // wide batches: kRB rows per wave share the y loads
+    const dim3 g(grid_for(c->n_rb, kWavesPerBlock)), b(kBlock);
+    if (prec == DD_FP64)
+      hipLaunchKernelGGL((k_dense_rows_rb<8, double, double>), g, b, 0, c->stream, c->n_rb, c->d_rb_first,
+                         (const double *)c->op[0].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z);
+    else
+      hipLaunchKernelGGL((k_dense_rows_rb<8, float, float>), g, b, 0, c->stream, c->n_rb, c->d_rb_first,
+                         (const float *)c->op[1].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z);
     return;
   }
   if (prec == DD_FP64)
@@ -926,6 +937,13 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if ((s = upload(c, &c->d_ioff, c->ioff.data(), c->n_sub)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_koff, c->koff.data(), c->n_sub)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_rowsub, rowsub.data(), NI)) != DD_OK) return bail(s);
+  {
+    std::vector<int> rbf;
+    for (int k = 0; k < c->n_sub; ++k)
+      for (int t = 0; t < p->sub[k].n_i; t += kRB) rbf.push_back(c->ioff[k] + t);
+    c->n_rb = (int)rbf.size();
+    if ((s = upload(c, &c->d_rb_first, rbf.data(), rbf.size())) != DD_OK) return bail(s);
+  }
   if ((s = upload(c, &c->d_imap, imap.data(), NI)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_gmap, p->gamma_map, c->n_gamma)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_kii64, kii.data(), kt)) != DD_OK) return bail(s);
