@@ -1188,6 +1188,117 @@ __device__ void trsm_llt(const LT *__restrict__ L, int n, BT *B, int rs, int cs,
   }
 }
 
+// ------------------------------------------------ explicit inverse on MFMA --
+// K_II^{-1} = L^{-T} L^{-1} in two steps, both on the matrix cores:
+//   1. X = L^{-1} (lower triangular, stored row-major: X[r][c] at r*n + c),
+//      one wave per (subdomain, 16-column tile C), block forward substitution
+//        X_RC = L_RR^{-1} (delta_RC I - sum_{C <= Q < R} L_RQ X_QC),
+//      the sum on MFMA 16x16x4 (q in steps of 4, increasing), the 16x16
+//      triangular solve with L_RR in LDS;
+//   2. K_II^{-1} = X^T X, one wave per 16x16 output tile (I >= J):
+//        (X^T X)_ij = sum_{r >= 16 I} X[r][i] X[r][j]   (r in steps of 4),
+//      written to both halves of the symmetric block (row i = column i).
+// Operand layout of v_mfma_{f64,f32}_16x16x4: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register r of lane l is row acc_row(g, r) of
+// column l%16, g = l/16.
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_trtri(const T *__restrict__ L, T *__restrict__ X, const long long *__restrict__ koff,
+        const int *__restrict__ ni) {
+  const int k = blockIdx.x, C = blockIdx.y;
+  const int n = ni[k];
+  const int nt = (n + 15) / 16;
+  if (C >= nt) return;
+  const T *Lk = L + koff[k];          // column-major: L[i][j] at j*n + i
+  T *Xk = X + koff[k];                // row-major
+  __shared__ T S[16][17];             // right-hand side, then solution, of one block row
+  __shared__ T D[16][17];             // diagonal block L_RR
+  const int lane = threadIdx.x, ci = lane % 16, g = lane / 16;
+  const int c0 = 16 * C;
+  const int jc = c0 + ci;             // this lane's column of the tile
+  // rows above the tile's diagonal block are zero
+  for (int e = lane; e < c0 * 16; e += kWave) {
+    const int r = e / 16, j = c0 + e % 16;
+    if (j < n) Xk[(size_t)r * n + j] = T(0);
+  }
+  for (int R = C; R < nt; ++R) {
+    const int r0 = 16 * R;
+    // diagonal block of L into LDS (zero outside the matrix)
+    for (int e = lane; e < 256; e += kWave) {
+      const int i = e % 16, j = e / 16;
+      D[i][j] = (r0 + i < n && r0 + j < n) ? Lk[(size_t)(r0 + j) * n + r0 + i] : T(0);
+    }
+    typename Vec4<T>::type acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = T(0);
+    // acc = - sum_{c0 <= q < r0} L[r0+i][q] X[q][c0+j]
+    const int ia = r0 + ci;
+    for (int q0 = c0; q0 < r0; q0 += 4) {
+      const int q = q0 + g;
+      const T a = ia < n ? -Lk[(size_t)q * n + ia] : T(0);
+      const T b = jc < n ? Xk[(size_t)q * n + jc] : T(0);
+      acc = mfma16x16x4(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = acc_row(T(0), g, r);
+      T v = acc[r];
+      if (R == C && i == ci) v += T(1);
+      S[i][ci] = v;
+    }
+    __syncthreads();
+    // forward substitution L_RR Y = S, the 16 columns in parallel
+    if (lane < 16) {
+      for (int i = 0; i < 16 && r0 + i < n; ++i) {
+        T sv = S[i][lane];
+        for (int q = 0; q < i; ++q) sv -= D[i][q] * S[q][lane];
+        S[i][lane] = sv / D[i][i];
+      }
+    }
+    __syncthreads();
+    for (int e = lane; e < 256; e += kWave) {
+      const int i = e / 16, j = e % 16;
+      const int r = r0 + i, cc = c0 + j;
+      if (r < n && cc < n) Xk[(size_t)r * n + cc] = r >= cc ? S[i][j] : T(0);
+    }
+    __threadfence_block();      // the stored rows feed the next block rows of this wave
+    __syncthreads();
+  }
+}
+
+// tiles[t] = (subdomain, I << 16 | J) for the output tiles I >= J of every block.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_gram(const T *__restrict__ X, T *__restrict__ Kinv, const long long *__restrict__ koff,
+       const int *__restrict__ ni, const int2 *__restrict__ tiles, int ntiles) {
+  const int t = blockIdx.x * kWavesPerBlock + wave_id();
+  if (t >= ntiles) return;
+  const int k = tiles[t].x;
+  const int I = tiles[t].y >> 16, J = tiles[t].y & 0xffff;
+  const int n = ni[k];
+  const T *Xk = X + koff[k];
+  T *Kk = Kinv + koff[k];
+  const int lane = lane_id(), ci = lane % 16, g = lane / 16;
+  const int ia = 16 * I + ci, jb = 16 * J + ci;
+  typename Vec4<T>::type acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = T(0);
+  for (int r0 = 16 * I; r0 < n; r0 += 4) {
+    const int r = r0 + g;
+    const T a = (r < n && ia < n) ? Xk[(size_t)r * n + ia] : T(0);
+    const T b = (r < n && jb < n) ? Xk[(size_t)r * n + jb] : T(0);
+    acc = mfma16x16x4(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * I + acc_row(T(0), g, r), j = 16 * J + ci;
+    if (i < n && j < n && (I > J || i >= j)) {
+      Kk[(size_t)j * n + i] = acc[r];
+      Kk[(size_t)i * n + j] = acc[r];
+    }
+  }
+}
+
 // K_II^{-1} from the factor, 16 columns of the identity per workgroup:
 // grid (n_sub, column chunks).
 constexpr int kInvCols = 16;

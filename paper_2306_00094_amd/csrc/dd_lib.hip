@@ -69,6 +69,8 @@ struct dd_ctx {
   size_t nnz_ig = 0, nnz_g = 0;
   // structure
   int n_rb = 0, *d_rb_first = nullptr;   // row blocks of kRB rows (never crossing subdomains)
+  int n_gram = 0;                         // 16x16 lower output tiles of all K_II^{-1} blocks
+  int2 *d_gram_tiles = nullptr;
   int *d_ni = nullptr, *d_ioff = nullptr, *d_rowsub = nullptr, *d_imap = nullptr,
       *d_gmap = nullptr;
   long long *d_koff = nullptr;
@@ -450,13 +452,28 @@ dd_status factor_impl(dd_ctx *c, int pi) {
     if (status[k])
       return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
                                      std::to_string(status[k] - 1));
-  dim3 ginv(c->n_sub, (c->max_ni + kInvCols - 1) / kInvCols);
-  hipLaunchKernelGGL((k_inverse<T>), ginv, dim3(kBlock), 0, c->stream, (const T *)L, Kinv,
-                     c->d_koff, c->d_ni);
-  HIPCHK(c, hipGetLastError());
-  hipLaunchKernelGGL((k_symmetrize<T>), dim3(c->n_sub, 64), dim3(256), 0, c->stream, Kinv,
-                     c->d_koff, c->d_ni);
-  HIPCHK(c, hipGetLastError());
+  if (c->use_mfma) {
+    // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set)
+    T *X = nullptr;
+    HIPCHK(c, hipMalloc(&X, std::max<size_t>(n, 1) * sizeof(T)));
+    struct FreeX { T *p; ~FreeX() { (void)hipFree(p); } } fx{X};
+    dim3 gt(c->n_sub, (c->max_ni + 15) / 16);
+    hipLaunchKernelGGL((k_trtri<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
+    HIPCHK(c, hipGetLastError());
+    if (c->n_gram > 0)
+      hipLaunchKernelGGL((k_gram<T>), dim3(grid_for(c->n_gram, kWavesPerBlock)), dim3(kBlock), 0, c->stream,
+                         (const T *)X, Kinv, c->d_koff, c->d_ni, c->d_gram_tiles, c->n_gram);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));     // X is freed on return
+  } else {
+    dim3 ginv(c->n_sub, (c->max_ni + kInvCols - 1) / kInvCols);
+    hipLaunchKernelGGL((k_inverse<T>), ginv, dim3(kBlock), 0, c->stream, (const T *)L, Kinv,
+                       c->d_koff, c->d_ni);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL((k_symmetrize<T>), dim3(c->n_sub, 64), dim3(256), 0, c->stream, Kinv,
+                       c->d_koff, c->d_ni);
+    HIPCHK(c, hipGetLastError());
+  }
   if (pi == DD_MIXED) {
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_ig, c->d_ig_val64,
                        (float *)o.ig_val);
@@ -943,6 +960,14 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
       for (int t = 0; t < p->sub[k].n_i; t += kRB) rbf.push_back(c->ioff[k] + t);
     c->n_rb = (int)rbf.size();
     if ((s = upload(c, &c->d_rb_first, rbf.data(), rbf.size())) != DD_OK) return bail(s);
+    std::vector<int2> gt;
+    for (int k = 0; k < c->n_sub; ++k) {
+      const int nt = (p->sub[k].n_i + 15) / 16;
+      for (int I = 0; I < nt; ++I)
+        for (int J = 0; J <= I; ++J) gt.push_back(make_int2(k, (I << 16) | J));
+    }
+    c->n_gram = (int)gt.size();
+    if ((s = upload(c, &c->d_gram_tiles, gt.data(), gt.size())) != DD_OK) return bail(s);
   }
   if ((s = upload(c, &c->d_imap, imap.data(), NI)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_gmap, p->gamma_map, c->n_gamma)) != DD_OK) return bail(s);
