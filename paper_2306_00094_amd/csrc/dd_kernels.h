@@ -1188,6 +1188,130 @@ __device__ void trsm_llt(const LT *__restrict__ L, int n, BT *B, int rs, int cs,
   }
 }
 
+// The same factorisation split into two launches per 16-wide panel so the
+// trailing updates of all subdomains spread over the whole GPU (one
+// workgroup per subdomain leaves most CUs idle).  Same arithmetic as k_potrf
+// step for step, so the factor is bit-identical.
+// Panel k0 = 16 * J: factor the diagonal block and solve the rows below it.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
+              const int *__restrict__ ni, int *__restrict__ status, int J) {
+  __shared__ T D[kNB][kNB + 1];
+  const int k = blockIdx.x;
+  const int n = ni[k];
+  const int k0 = kNB * J;
+  if (k0 >= n) return;
+  T *A = blocks + koff[k];
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int kb = min(kNB, n - k0);
+  int fail = 0;
+  for (int e = tid; e < kNB * kNB; e += kBlock) {
+    int i = e % kNB, j = e / kNB;
+    D[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + j) * n + k0 + i] : T(0);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    for (int j = 0; j < kb; ++j) {
+      T d = D[j][j];
+      if (!(d > T(0))) {
+        if (lane == 0 && fail == 0) fail = k0 + j + 1;
+        d = T(1);
+      }
+      T piv = sqrt(d);
+      if (lane == 0) D[j][j] = piv;
+      if (lane > j && lane < kb) D[lane][j] = D[lane][j] / piv;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int e = lane; e < kNB * kNB; e += kWave) {
+        int i = e % kNB, l = e / kNB;
+        if (l > j && i >= l && i < kb) D[i][l] -= D[i][j] * D[l][j];
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane == 0 && fail && status[k] == 0) status[k] = fail;
+  }
+  __syncthreads();
+  for (int e = tid; e < kNB * kNB; e += kBlock) {
+    int i = e % kNB, j = e / kNB;
+    if (i < kb && j < kb && i >= j) A[(size_t)(k0 + j) * n + k0 + i] = D[i][j];
+  }
+  for (int i = k0 + kb + tid; i < n; i += kBlock) {
+    T xr[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+      if (j < kb) {
+        T a = A[(size_t)(k0 + j) * n + i];
+        for (int q = 0; q < j; ++q) a -= xr[q] * D[j][q];
+        xr[j] = a / D[j][j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kNB; ++j)
+      if (j < kb) A[(size_t)(k0 + j) * n + i] = xr[j];
+  }
+}
+
+// Trailing update of panel J: A22 -= L21 L21^T on the 16x16 lower tiles of
+// every subdomain; grid (tile chunks, subdomains), one wave per tile.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_potrf_update(T *__restrict__ blocks, const long long *__restrict__ koff,
+               const int *__restrict__ ni, int J, int use_mfma) {
+  const int k = blockIdx.y;
+  const int n = ni[k];
+  const int k0 = kNB * J;
+  const int kb = min(kNB, n - k0);
+  const int t0 = k0 + kb;
+  const int m = n - t0;
+  if (kb <= 0 || m <= 0) return;
+  const int T16 = (m + 15) / 16;
+  const int ntiles = T16 * (T16 + 1) / 2;
+  const int t = blockIdx.x * kWavesPerBlock + wave_id();
+  if (t >= ntiles) return;
+  T *A = blocks + koff[k];
+  const int lane = lane_id();
+  int ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+  while (ti * (ti + 1) / 2 > t) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  int tj = t - ti * (ti + 1) / 2;
+  int i0 = t0 + 16 * ti, j0 = t0 + 16 * tj;
+  int ci = lane % 16, rq = lane / 16;
+  typename Vec4<T>::type acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+    acc[r] = (i < n && j < n) ? A[(size_t)j * n + i] : T(0);
+  }
+  if (use_mfma) {
+#pragma unroll
+    for (int kk = 0; kk < kNB; kk += 4) {
+      int q = kk + rq;
+      int ia = i0 + ci, jb = j0 + ci;
+      T a = (q < kb && ia < n) ? -A[(size_t)(k0 + q) * n + ia] : T(0);
+      T b = (q < kb && jb < n) ? A[(size_t)(k0 + q) * n + jb] : T(0);
+      acc = mfma16x16x4(a, b, acc);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+      if (i < n && j < n) {
+        T sv = acc[r];
+        for (int q = 0; q < kb; ++q)
+          sv -= A[(size_t)(k0 + q) * n + i] * A[(size_t)(k0 + q) * n + j];
+        acc[r] = sv;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int i = i0 + acc_row(T(0), rq, r), j = j0 + ci;
+    if (i < n && j < n && i >= j) A[(size_t)j * n + i] = acc[r];
+  }
+}
+
 // ------------------------------------------------ explicit inverse on MFMA --
 // K_II^{-1} = L^{-T} L^{-1} in two steps, both on the matrix cores:
 //   1. X = L^{-1} (lower triangular, stored row-major: X[r][c] at r*n + c),

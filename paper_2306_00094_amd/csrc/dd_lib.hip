@@ -442,8 +442,21 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   else
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, n, c->d_kii64, (float *)L);
   HIPCHK(c, hipGetLastError());
-  hipLaunchKernelGGL((k_potrf<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
-                     c->d_ni, c->d_status, c->use_mfma);
+  // panel by panel: the diagonal block and the rows below it (one workgroup per
+  // subdomain), then the trailing update of all subdomains' tiles
+  HIPCHK(c, hipMemsetAsync(c->d_status, 0, c->n_sub * sizeof(int), c->stream));
+  const int npanels = (c->max_ni + kNB - 1) / kNB;
+  for (int J = 0; J < npanels; ++J) {
+    hipLaunchKernelGGL((k_potrf_panel<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
+                       c->d_ni, c->d_status, J);
+    const int m = c->max_ni - kNB * (J + 1);
+    if (m > 0) {
+      const int t16 = (m + 15) / 16;
+      const int nt = t16 * (t16 + 1) / 2;
+      hipLaunchKernelGGL((k_potrf_update<T>), dim3(grid_for(nt, kWavesPerBlock), c->n_sub), dim3(kBlock), 0,
+                         c->stream, L, c->d_koff, c->d_ni, J, c->use_mfma);
+    }
+  }
   HIPCHK(c, hipGetLastError());
   std::vector<int> status(c->n_sub);
   HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
