@@ -162,6 +162,56 @@ def cpu_baseline(wl, b, tol, budget_s):
                        f"{dt:.1f} s", threads_available=os.cpu_count())
 
 
+def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
+    """Continuous-batching serving run (paper_2306_00094_amd.serving) over
+    four resident systems: the 1D constant kernel, the benchmark system and
+    half-scale 2D constant and fractional systems.  Requests carry 1-16
+    seeded right-hand sides.  First all requests arrive at once (saturated
+    throughput), then Poisson arrivals at 0.8x that request rate (latency
+    under load)."""
+    import numpy as np
+    from paper_2306_00094_amd import serving
+    specs = {
+        "1d-const h=1/1024": workloads.spec_1d(),
+        "2d-const h=1/64": workloads.scaled(workloads.spec_2d_const, 0.5),
+        "2d-frac h=1/48": workloads.scaled(workloads.spec_2d_frac, 0.5),
+    }
+    systems = {k: workloads.build(sp).dd for k, sp in specs.items()}
+    systems["2d-const h=1/128"] = wl_main.dd
+    specs["2d-const h=1/128"] = wl_main.spec
+    rng = np.random.default_rng(seed)
+    keys = sorted(systems)
+    loads = {k: workloads.rhs(specs[k], nrhs=16, seed_base=seed + 100 * i) for i, k in enumerate(keys)}
+
+    def requests(arrivals):
+        out = []
+        for i, t in enumerate(arrivals):
+            k = keys[int(rng.integers(0, len(keys)))]
+            m = int(rng.integers(1, 17))
+            out.append(serving.Request(key=k, b=np.asfortranarray(loads[k][:, :m]), arrival=float(t), rid=i))
+        return out
+
+    opts = dd.dd_default_opts(tol=1e-9)
+    srv = serving.Server(systems, prec=dd.DD_MIXED, opts=opts, iters_per_step=4)
+    try:
+        # every system resident (factors formed) before anything is timed
+        srv.run(requests(np.zeros(len(keys) * 2)), timeout=300, keep_resident=True)
+        t0 = time.perf_counter()
+        done = srv.run(requests(np.zeros(nreq)), timeout=600, keep_resident=True)
+        burst = serving.summarize(done, wall=time.perf_counter() - t0)
+        rate = 0.8 * burst["requests"] / burst["seconds"]
+        done = srv.run(requests(serving.poisson_arrivals(nreq, rate=rate, seed=seed + 1)), timeout=600,
+                       keep_resident=True)
+        load = serving.summarize(done)
+    finally:
+        srv.shutdown()
+    return dict(systems=keys, requests=nreq, rhs_per_request="1-16", rel_resid=1e-9, precision="mixed",
+                saturated_solves_per_s=burst["solves_per_s"], saturated_p50_ms=burst["p50_ms"],
+                saturated_p99_ms=burst["p99_ms"], offered_requests_per_s=rate,
+                solves_per_s=load["solves_per_s"], p50_ms=load["p50_ms"], p99_ms=load["p99_ms"],
+                fallbacks=load["fallbacks"] + burst["fallbacks"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +220,8 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--launch", default="auto", choices=["auto", "kernels", "graph", "persistent"],
                     help="CG launch mode; auto = the schedule chosen by the library's autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -308,6 +360,11 @@ def main():
         "paper_context": "14.6x FETI vs Jacobi-CG solve time, fractional kernel, 48x48 subdomains, "
                          "16M dofs, 2304 Broadwell ranks (different method and machine)",
     }
+    if args.serving_requests > 0:
+        log(f"bench: serving leg ({args.serving_requests} requests) ...")
+        t = time.perf_counter()
+        line["serving"] = serving_leg(dd, workloads, wl, args.serving_requests)
+        log(f"bench: serving leg done in {time.perf_counter() - t:.1f} s: {line['serving']}")
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s) ...")
         line["cpu_baseline"] = cpu_baseline(wl, b, tol, args.cpu_seconds)

@@ -251,12 +251,16 @@ class Server:
             s.thread.start()
             return s
 
-    def run(self, requests, timeout: float = 600.0):
+    def run(self, requests, timeout: float = 600.0, keep_resident: bool = False):
         """Release the requests at their arrival times (seconds from start) and
-        wait for all completions.  Returns the completed requests."""
+        wait for all completions.  Returns the completed requests of this run.
+        With keep_resident the systems (factors, Krylov state) stay on the
+        device for the next run; otherwise they are released at the end."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         pending = collections.deque(reqs)
         waiting = collections.deque()
+        with self.done_cv:
+            self.done = []
         self.t0 = time.monotonic()
         deadline = self.t0 + timeout
         while pending or waiting or len(self.done) < len(reqs):
@@ -277,7 +281,8 @@ class Server:
             with self.done_cv:
                 nxt = pending[0].arrival - self.now() if pending else 0.005
                 self.done_cv.wait(timeout=max(0.0005, min(nxt, 0.005)))
-        self.shutdown()
+        if not keep_resident:
+            self.shutdown()
         return self.done
 
     def shutdown(self):
