@@ -101,7 +101,8 @@ typedef struct {
   int32_t precond;       /* 0 none, 1 exact diag(S) Jacobi */
   int32_t max_refine;    /* DD_MIXED: outer refinement steps */
   double inner_tol;      /* DD_MIXED: inner CG stops at ||r_in|| <= max(inner_tol ||r_outer||,
-                            tol ||b|| / 2) */
+                            tol ||b|| / 2); 0 = automatic (the autotuned value for this
+                            batch width, else 1e-5) */
   int32_t fp64_fallback; /* DD_MIXED: 1 = finish stalled columns with the FP64 path */
   int32_t apply;         /* dd_apply */
   int32_t launch;        /* dd_launch */
@@ -119,7 +120,7 @@ typedef struct {
 } dd_solve_info;
 
 /* Fill opts with defaults: tol 1e-10, max_it 1000, precond 1, max_refine 8,
- * inner_tol 1e-4, fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1. */
+ * inner_tol 0 (automatic), fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1. */
 void dd_default_opts(dd_solve_opts *opts);
 
 /* Device bytes a context for `prob` would hold (matrices, factors for
@@ -172,13 +173,16 @@ typedef struct {
   int32_t check_every;       /* polling lag (kernels) or iterations per graph (graph) */
   double ms_per_solve;       /* measured time of one solve of the batch with this schedule */
   int32_t candidates;        /* schedules timed */
+  double inner_tol;          /* DD_MIXED: inner tolerance chosen (0 for DD_FP64) */
 } dd_tune_result;
 
 /* Autotuner: time every candidate schedule of the CG loop on this context and
  * precision for a batch of nrhs synthetic right-hand sides (launch mode,
  * interior-solve variant, direction handling, polling lag), keep the fastest,
  * and use it for later dd_solve calls of that precision and batch width whose
- * opts leave apply and launch at AUTO.  base: tolerances used while timing
+ * opts leave apply and launch at AUTO.  For DD_MIXED with base->inner_tol == 0
+ * the inner tolerance (1e-4, 1e-5, 1e-6) is then timed with that schedule and
+ * kept for solves whose inner_tol is 0.  base: tolerances used while timing
  * (NULL = defaults).  The factors of `prec` must exist.  out may be NULL. */
 dd_status dd_autotune(dd_ctx *ctx, dd_precision prec, int32_t nrhs, const dd_solve_opts *base,
                       dd_tune_result *out);

@@ -68,7 +68,8 @@ class dd_solve_info(ctypes.Structure):
 class dd_tune_result(ctypes.Structure):
     _fields_ = [("apply", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("direction_kernel", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("ms_per_solve", ctypes.c_double), ("candidates", ctypes.c_int32)]
+                ("ms_per_solve", ctypes.c_double), ("candidates", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
 
 
 class DDError(RuntimeError):
@@ -248,7 +249,8 @@ def dd_autotune(ctx, prec: int, nrhs: int, opts: dd_solve_opts | None = None) ->
     _check(lib, lib.dd_autotune(ctx, prec, nrhs, ctypes.byref(opts) if opts is not None else None,
                                 ctypes.byref(r)), ctx)
     return dict(apply=r.apply, launch=r.launch, direction_kernel=r.direction_kernel,
-                check_every=r.check_every, ms_per_solve=r.ms_per_solve, candidates=r.candidates)
+                check_every=r.check_every, ms_per_solve=r.ms_per_solve, candidates=r.candidates,
+                inner_tol=r.inner_tol)
 
 
 def dd_batch_begin(ctx, prec: int, opts: dd_solve_opts | None = None) -> None:

@@ -110,7 +110,7 @@ struct dd_ctx {
   std::vector<GraphEntry> graphs;
   bool capturing = false;
   // autotuned schedules per precision and batch width (log2)
-  struct Tuned { bool set = false; int apply = 0, launch = 0, dk = 0, check_every = 0; double ms = 0; };
+  struct Tuned { bool set = false; int apply = 0, launch = 0, dk = 0, check_every = 0; double ms = 0, inner_tol = 0; };
   Tuned tuned[2][7];
   // continuous batching
   struct Batch {
@@ -812,6 +812,17 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
 // residual, but never tighter than half the outer target tol * ||b||, so the
 // last step stops as soon as the outer tolerance can be met instead of
 // reducing the residual by inner_tol once more.
+// Inner tolerance when neither the caller nor the autotuner chose one: the
+// FP32 operators limit what one step can gain to about 1e-5..1e-6, and a
+// step that stops there needs two steps for a 1e-9 target instead of three.
+constexpr double kInnerTol = 1e-5;
+inline double resolve_inner_tol(const dd_ctx *c, int prec, int ld, double requested) {
+  if (requested > 0.0) return requested;
+  int lg = 0;
+  while ((1 << lg) < ld) ++lg;
+  const auto &t = c->tuned[prec][lg];
+  return (t.set && t.inner_tol > 0.0) ? t.inner_tol : kInnerTol;
+}
 inline double inner_stop2(double inner_tol, double tol, double rn2, double bn2) {
   return std::max(inner_tol * inner_tol * rn2, 0.25 * tol * tol * bn2);
 }
@@ -844,7 +855,7 @@ void dd_default_opts(dd_solve_opts *o) {
   o->max_it = 1000;
   o->precond = 1;
   o->max_refine = 8;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 0.0;             // automatic: the tuned value, else kInnerTol
   o->fp64_fallback = 1;
   o->apply = DD_APPLY_AUTO;
   o->launch = DD_LAUNCH_AUTO;
@@ -1166,6 +1177,32 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
       bc = cd;
     }
   }
+  // mixed precision: the inner tolerance, with the schedule just chosen
+  double best_itol = o.inner_tol > 0.0 ? o.inner_tol : kInnerTol;
+  int ncand = (int)cands.size();
+  if (prec == DD_MIXED && !(o.inner_tol > 0.0)) {
+    for (double itol : {1e-4, 1e-5, 1e-6}) {
+      dd_solve_opts oc = o;
+      oc.apply = bc.apply;
+      oc.launch = bc.launch;
+      oc.check_every = bc.ce;
+      oc.inner_tol = itol;
+      c->direction_kernel = bc.dk;
+      dd_status s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);
+      if (s != DD_OK) continue;
+      const int reps = 3;
+      auto t0 = std::chrono::steady_clock::now();
+      for (int r = 0; r < reps && s == DD_OK; ++r) s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);
+      auto t1 = std::chrono::steady_clock::now();
+      if (s != DD_OK) continue;
+      ++ncand;
+      double ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / reps;
+      if (ms < best) {
+        best = ms;
+        best_itol = itol;
+      }
+    }
+  }
   c->direction_kernel = saved_dk;
   c->err.clear();
   auto &t = c->tuned[prec][lg];
@@ -1175,13 +1212,15 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   t.dk = bc.dk;
   t.check_every = bc.ce;
   t.ms = best;
+  t.inner_tol = prec == DD_MIXED ? best_itol : 0.0;
   if (out) {
     out->apply = bc.apply;
     out->launch = bc.launch;
     out->direction_kernel = bc.dk;
     out->check_every = bc.ce;
     out->ms_per_solve = best;
-    out->candidates = (int)cands.size();
+    out->candidates = ncand;
+    out->inner_tol = t.inner_tol;
   }
   return DD_OK;
 }
@@ -1263,6 +1302,8 @@ dd_status dd_batch_begin(dd_ctx *c, dd_precision prec, const dd_solve_opts *opts
   B.d_slots = ds;
   if (opts) B.o = *opts; else dd_default_opts(&B.o);
   if (!(B.o.tol > 0.0) || B.o.max_it < 1) return fail(c, DD_EINVAL, "tol <= 0 or max_it < 1");
+  if (B.o.inner_tol < 0.0 || B.o.inner_tol >= 1.0) return fail(c, DD_EINVAL, "inner_tol not in [0,1)");
+  if (B.o.inner_tol == 0.0) B.o.inner_tol = kInnerTol;
   B.prec = prec;
   B.ld = 1;
   B.on = true;
@@ -1495,9 +1536,10 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   if (opts) o = *opts; else dd_default_opts(&o);
   if (!(o.tol > 0.0) || o.max_it < 1) return fail(c, DD_EINVAL, "tol <= 0 or max_it < 1");
   if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
-  if (prec == DD_MIXED && (o.max_refine < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0))
-    return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in (0,1)");
+  if (prec == DD_MIXED && (o.max_refine < 1 || o.inner_tol < 0.0 || o.inner_tol >= 1.0))
+    return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in [0,1)");
   const int L = next_pow2(nrhs);
+  if (prec == DD_MIXED) o.inner_tol = resolve_inner_tol(c, prec, L, o.inner_tol);
   struct RestoreDk {
     dd_ctx *c;
     int v;

@@ -52,7 +52,7 @@ def test_default_opts(lib):
     dd, _ = lib
     o = dd.dd_default_opts()
     assert (o.tol, o.max_it, o.precond, o.max_refine, o.inner_tol, o.fp64_fallback,
-            o.apply, o.launch, o.check_every, o.verify) == (1e-10, 1000, 1, 8, 1e-4, 1, 0, 0, 0, 1)
+            o.apply, o.launch, o.check_every, o.verify) == (1e-10, 1000, 1, 8, 0.0, 1, 0, 0, 0, 1)
 
 
 @pytest.fixture(scope="module")
