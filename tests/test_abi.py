@@ -104,3 +104,32 @@ def test_setup_rejects_bad_batch_width(lib, small):
         with pytest.raises(dd.DDError) as ei:
             dd.dd_setup(small, stream=0, max_nrhs=m)
         assert ei.value.status == dd.DD_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_bench_traffic_needs_matching_kernel_source():
+    """The stored counter traffic is reported only for the kernel source it was
+    measured on."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    saved = dict(bench.MEASURED_TRAFFIC)
+    try:
+        bench.MEASURED_TRAFFIC["src_sha256"] = "0" * 16
+        assert bench.measured_traffic("k_gamma_rows<double>", saved["workload"]) is None
+    finally:
+        bench.MEASURED_TRAFFIC.clear()
+        bench.MEASURED_TRAFFIC.update(saved)
+    assert bench.measured_traffic("k_gamma_rows<double>", "another workload") is None

@@ -215,6 +215,10 @@ def test_autotune_then_auto_solve(prec):
     print("  tuned", res, flush=True)
     assert res["candidates"] >= 8 and res["ms_per_solve"] > 0
     assert res["launch"] in (1, 2, 3) and res["apply"] in (1, 2)
+    if prec == 1:        # the mixed path also tunes its inner tolerance
+        assert res["inner_tol"] in (1e-4, 1e-5, 1e-6)
+    else:
+        assert res["inner_tol"] == 0.0
     r = s.solve(to_dev(b), prec=prec, opts=dd.dd_default_opts(tol=1e-12))
     err = oracle.rel_err(r.u.cpu().numpy().T, uref)
     assert err.max() <= (1e-10 if prec == 0 else 1e-8)

@@ -128,3 +128,27 @@ def test_serving_mix_alone_equal_and_correct():
         alone = serving.Request(key=r.key, b=r.b, arrival=0.0, rid=0)
         d1 = srv1.run([alone], timeout=120)
         assert np.array_equal(d1[0].u, r.u), r.rid
+
+
+def test_serving_keeps_systems_resident_between_runs():
+    """With keep_resident the factors and contexts survive a run: a second run
+    reuses the same resident system (no refactorisation) and returns the same
+    result, bit for bit, for the same request."""
+    dd = _dd()
+    from paper_2306_00094_amd import serving
+    wl, b, uref = system("2d")
+    opts = dd.dd_default_opts(tol=1e-11)
+    srv = serving.Server({"2d": wl.dd}, prec=dd.DD_MIXED, opts=opts, iters_per_step=3)
+    print("case serving keep_resident", flush=True)
+    try:
+        r1 = srv.run([serving.Request(key="2d", b=np.asfortranarray(b[:, :2]), rid=0)],
+                     timeout=120, keep_resident=True)
+        first = srv.resident["2d"]
+        r2 = srv.run([serving.Request(key="2d", b=np.asfortranarray(b[:, :2]), rid=1)],
+                     timeout=120, keep_resident=True)
+        assert srv.resident["2d"] is first
+        assert len(r1) == 1 and len(r2) == 1
+        assert np.array_equal(r1[0].u, r2[0].u)
+        assert oracle.rel_err(r2[0].u, uref[:, :2]).max() <= 1e-8
+    finally:
+        srv.shutdown()
