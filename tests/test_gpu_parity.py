@@ -223,3 +223,33 @@ def test_autotune_then_auto_solve(prec):
     err = oracle.rel_err(r.u.cpu().numpy().T, uref)
     assert err.max() <= (1e-10 if prec == 0 else 1e-8)
     s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_factor_rejects_indefinite_block(prec):
+    """A subdomain block that is not positive definite is reported by
+    dd_factor as DD_ENOTSPD naming the subdomain and the failing column; the
+    context stays usable after the error (a valid problem factors and solves
+    on a fresh context)."""
+    import copy
+    dd = _dd()
+    wl, b, uref = problem("1d-4strips")
+    bad = copy.deepcopy(wl.dd)
+    K = np.array(bad.kii[2], order="F", copy=True)
+    K[7, 7] = -10.0 * abs(K[7, 7])
+    bad.kii[2] = K
+    print(f"case indefinite block prec={prec}", flush=True)
+    s = dd.Solver(bad, max_nrhs=1)
+    with pytest.raises(dd.DDError) as ei:
+        s.factor(prec)
+    assert ei.value.status == dd.DD_ENOTSPD
+    assert "subdomain 2" in str(ei.value) and "column 7" in str(ei.value)
+    with pytest.raises(dd.DDError) as ei:          # no factors: solve refuses
+        s.solve(to_dev(b[:, :1]), prec=prec)
+    assert ei.value.status == dd.DD_ESTATE
+    s.close()
+    s = dd.Solver(wl.dd, max_nrhs=1)
+    s.factor(prec)
+    r = s.solve(to_dev(b[:, :1]), prec=prec, opts=dd.dd_default_opts(tol=1e-12))
+    assert oracle.rel_err(r.u.cpu().numpy().T, uref[:, :1]).max() <= (1e-10 if prec == 0 else 1e-8)
+    s.close()
