@@ -227,15 +227,17 @@ dd_status dd_batch_end(dd_ctx *ctx);
 enum {
   DD_PHASE_KIG = 0,       /* y = K_IG p                        (all subdomains) */
   DD_PHASE_INTERIOR = 1,  /* w = K_II^{-1} y                   (all subdomains) */
-  DD_PHASE_GAMMA = 2,     /* q = K_GG p - K_GI w, p^T q, alpha  (interface rows) */
-  DD_PHASE_UPDATE = 3,    /* x, r, z updates, r^T z, r^T r, beta, convergence */
+  DD_PHASE_GAMMA = 2,     /* q = K_GG p - K_GI w, p^T q partials (interface rows) */
+  DD_PHASE_UPDATE = 3,    /* alpha, x, r, z updates, r^T z, r^T r, beta, convergence */
   DD_PHASE_LOOP = 4,      /* one graph replay or one persistent CG launch (whole iterations) */
   DD_NPHASES = 5
 };
 
 /* Enable HIP-event timing of the phases whose bit is set in phase_mask
  * (0 disables) and reset the accumulators.  An event pair is recorded on
- * the context's stream around every launch of a timed phase. */
+ * the context's stream around every launch of a timed phase; for
+ * DD_PHASE_GAMMA the launch itself records the pair at kernel start and end
+ * (the kernel's own duration). */
 dd_status dd_set_timing(dd_ctx *ctx, uint32_t phase_mask);
 
 /* Accumulated milliseconds and launch counts per phase since the last

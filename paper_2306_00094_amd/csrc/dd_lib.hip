@@ -4,6 +4,7 @@
 // complement, back substitution, mixed-precision refinement), exported
 // through the C ABI declared in include/dd.h.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -307,16 +308,45 @@ void dense_rows(dd_ctx *c, const MT *blocks, const double *y, int ld, const doub
   }
 }
 
+// Event pair recorded by the launch itself at the start and the end of one
+// kernel of a timed phase (hipExtLaunchKernelGGL): the kernel's own duration,
+// without the gap that events recorded between launches add.
+bool kernel_events(dd_ctx *c, int phase, hipEvent_t *e0, hipEvent_t *e1) {
+  if (!((c->timing_mask >> phase) & 1u) || c->capturing) return false;
+  if (c->tev_used + 2 > c->tev.size()) {
+    for (int i = 0; i < 256; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      c->tev.push_back(e);
+    }
+    c->tev_phase.resize(c->tev.size() / 2, 0);
+  }
+  *e0 = c->tev[c->tev_used];
+  *e1 = c->tev[c->tev_used + 1];
+  c->tev_phase[c->tev_used / 2] = phase;
+  c->tev_used += 2;
+  return true;
+}
+
 template <int C, typename VT>
 void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
                   const double *base, double c1, double c2, double *out, int dot, double *pout) {
   if (c->n_gamma <= 0) return;
   dim3 g(grid_for(c->n_gamma, kGChunk)), b(kGRows * kWave);
   if (dot) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums
-  {
-    if (p.z)
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = dot && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1);   // CG iterations only
+  if (p.z) {
+    if (timed)
+      hipExtLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+    else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
                          c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+  } else {
+    if (timed)
+      hipExtLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
                          c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
@@ -685,10 +715,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       PhaseTimer t(c, DD_PHASE_INTERIOR);
       interior_solve(c, prec, o.apply, w.yI, w.wI, ld);
     }
-    {
-      PhaseTimer t(c, DD_PHASE_GAMMA);
-      gamma_apply(c, prec, dk ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
-    }
+    // (timed, when asked, by events the launch itself records: kernel_events)
+    gamma_apply(c, prec, dk ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
