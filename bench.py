@@ -53,16 +53,18 @@ WORKLOADS = {
 # Bytes moved beyond L2 per dispatch of the interface-row kernel, from two
 # rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of this benchmark on the
 # default workload, each scaled by what the counter read for an elementwise
-# kernel of known traffic (FETCH x2.000, WRITE x1.000).  Valid only for the
+# kernel of known traffic (FETCH x2.000, WRITE x1.000): 256 MiB read and written
+# read as 131085.3 KiB fetched and 262148.0 KiB written.  Valid only for the
 # kernel source they were taken on (sha256 prefix of csrc/dd_kernels.h);
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    "src_sha256": "5a844ee9b9a19ffd",
+    "src_sha256": "fca7be61cd6bd97a",
     "workload": "cfg2",
-    "k_gamma_rows<float>": dict(fetch_kib=22558.8, write_kib=183.8),
-    "k_gamma_rows<double>": dict(fetch_kib=33380.6, write_kib=183.8),
-    "fetch_scale": 2.000,
-    "write_scale": 1.000,
+    # median over the launches of the CG iterations (full [K_GG | K_GI] sweep)
+    "k_gamma_rows<float>": dict(fetch_kib=23242.3, write_kib=148.2),
+    "k_gamma_rows<double>": dict(fetch_kib=34223.1, write_kib=148.3),
+    "fetch_scale": 262144.0 / 131085.3,
+    "write_scale": 262144.0 / 262148.0,
 }
 
 
