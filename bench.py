@@ -222,6 +222,62 @@ def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
                 fallbacks=load["fallbacks"] + burst["fallbacks"])
 
 
+def jacobi_cg_leg(dd, workloads, wl, bt, b, tol, steps, warmup, torch, cpu_seconds):
+    """The paper's baseline solver on the same system: CG on the whole matrix
+    with diag(A) as preconditioner (section "Considered solver strategies"),
+    run by the library as the undecomposed problem (no subdomains, S = A).
+    Same tolerance, right-hand side, launch autotuning and timing as the
+    substructuring solve; its dominant kernel is the CSR sweep of A."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    und = workloads.undecomposed(wl.asm.A)
+    nrhs = b.shape[1]
+    ld = 1
+    while ld < nrhs:
+        ld *= 2
+    s = dd.Solver(und, max_nrhs=nrhs)
+    out = {}
+    try:
+        for name, prec in (("fp64", dd.DD_FP64), ("mixed", dd.DD_MIXED)):
+            s.factor(prec)
+            opts = dd.dd_default_opts(tol=tol)
+            tuned = s.autotune(prec, nrhs, opts)
+            r = time_path(s, dd, bt, prec, opts, steps, warmup, torch)
+            vb = 8 if prec == dd.DD_FP64 else 4
+            roof = None
+            if r["gamma_launches"] > 0:
+                avg = r["gamma_ms"] / r["gamma_launches"] * 1e-3
+                algo = gamma_kernel_bytes(und, ld, vb)
+                ach = algo / avg / 1e9
+                roof = dict(bound="hbm", kernel="k_gamma_rows<%s> (q = A p)" % ("double" if vb == 8 else "float"),
+                            achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                            algo_bytes_per_launch=algo, avg_launch_us=1e6 * avg,
+                            launches=r["gamma_launches"])
+            out[name] = dict(value=steps * nrhs / r["seconds"], ms_per_step=1e3 * r["seconds"] / steps,
+                             p50_ms=1e3 * statistics.median(r["lat"]), p99_ms=1e3 * pct(r["lat"], 0.99),
+                             iters=[i["iters"] for i in r["info"]],
+                             rel_resid_max=max(i["rel_resid"] for i in r["info"]),
+                             schedule=tuned, roofline=roof)
+            log(f"bench: jacobi-cg prec={prec} {out[name]['ms_per_step']:.3f} ms/step its={out[name]['iters'][:4]}")
+    finally:
+        s.close()
+    import oracle
+    with threadpool_limits(limits=1):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.jacobi_pcg(wl.asm.A, b[:, :1], tol=tol)
+            n += 1
+            if time.perf_counter() - t0 >= cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+    out["cpu_oracle"] = dict(value=n / dt, unit="solves/s", cores=1, kind="oracle",
+                             sample=f"{n} oracle Jacobi-PCG solves (1 rhs, tol {tol:g}), {dt:.1f} s")
+    out["nnz"] = int(wl.asm.A.nnz)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +288,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--no-jacobi-cg", action="store_true",
+                    help="skip the baseline leg (Jacobi-preconditioned CG on the whole system)")
     ap.add_argument("--launch", default="auto", choices=["auto", "kernels", "graph", "persistent"],
                     help="CG launch mode; auto = the schedule chosen by the library's autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
@@ -381,6 +439,13 @@ def main():
         "paper_context": "14.6x FETI vs Jacobi-CG solve time, fractional kernel, 48x48 subdomains, "
                          "16M dofs, 2304 Broadwell ranks (different method and machine)",
     }
+    if not args.no_jacobi_cg:
+        log("bench: baseline leg (Jacobi-preconditioned CG on the whole system) ...")
+        jcg = jacobi_cg_leg(dd, workloads, wl, bt, b, tol, args.steps, args.warmup, torch,
+                            min(5.0, args.cpu_seconds))
+        jcg["dd_speedup"] = {k: res_v / jcg[k]["value"]
+                             for k, res_v in (("fp64", fp64["value"]), ("mixed", mixed["value"]))}
+        line["jacobi_cg"] = jcg
     if args.serving_requests > 0:
         log(f"bench: serving leg ({args.serving_requests} requests) ...")
         t = time.perf_counter()

@@ -69,12 +69,18 @@ typedef struct {
 
 /* The partitioned system.  Every global dof is either interior to exactly one
  * subdomain or an interface dof; interiors of different subdomains must not be
- * coupled (checked through the sparsity the caller passes). */
+ * coupled (checked through the sparsity the caller passes).
+ *
+ * n_sub = 0 is the undecomposed system: every dof is an interface dof
+ * (gamma_map a permutation of [0, n_dof)), K_GG is the whole matrix A, S = A
+ * and diag(S) = diag(A), so dd_solve runs the diagonally preconditioned CG on
+ * A that the paper compares against (section "Considered solver strategies";
+ * one CSR sweep of A per iteration, no factorisation). */
 typedef struct {
   int32_t n_dof;             /* size of the free-dof system A */
   int32_t n_gamma;           /* interface dofs */
-  int32_t n_sub;             /* number of subdomains K */
-  const dd_subdomain *sub;   /* n_sub entries */
+  int32_t n_sub;             /* number of subdomains K (>= 0) */
+  const dd_subdomain *sub;   /* n_sub entries (may be NULL when n_sub = 0) */
   const int32_t *gamma_map;  /* n_gamma: interface index -> global dof */
   const int32_t *kgg_rowptr; /* n_gamma+1: CSR of the global K_GG (n_gamma x n_gamma) */
   const int32_t *kgg_col;

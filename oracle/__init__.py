@@ -11,6 +11,9 @@ solver computes (arXiv:2306.00094):
   section "A discretized weak formulation" (A symmetric positive definite
   when the Dirichlet collar is non-empty), by a banded Cholesky factorisation
   in the natural node order (LAPACK routine used as one step).
+* ``jacobi_pcg`` -- the paper's baseline solver: CG on the whole system
+  with the diagonal of A as preconditioner (section "Considered solver
+  strategies"), x0 = 0, independent columns, the same stopping rule as below.
 * ``DDOracle`` -- the same substructuring method the GPU runs:
   - factor each interior block A^k_{Omega Omega} = L_k L_k^T
     (block Cholesky splitting, eq. splittingBlockCholesky);
@@ -36,7 +39,10 @@ tolerance and no multi-RHS scheme):
 
 Pins of this oracle (tests/test_oracle.py): brute-force dense inverses on
 tiny systems, explicit dense Schur complements, DD-vs-monolithic agreement,
-CG termination in at most n_G steps, symmetry of S.
+CG termination in at most n_G steps, symmetry of S; for jacobi_pcg: the
+first iterates of a 2x2 system worked by hand in exact fractions, one-step
+convergence on diagonal systems, termination in n steps, agreement with the
+banded Cholesky solution.
 """
 from .dd_oracle import (DDOracle, cholesky, monolithic_solve, rel_err,  # noqa: F401
-                        full_residual)
+                        full_residual, jacobi_pcg)

@@ -39,6 +39,46 @@ def monolithic_solve(A: sp.spmatrix, b: np.ndarray) -> np.ndarray:
     return x.reshape(np.asarray(b).shape)
 
 
+def jacobi_pcg(A: sp.spmatrix, b: np.ndarray, tol: float = 1e-10, max_it: int = 100000):
+    """Conjugate gradients on the whole system A u = b with the diagonal of A
+    as preconditioner: the baseline solver of the paper's experiments (section
+    "Considered solver strategies"; the rows are not split into subdomains).
+
+    x0 = 0; column c stops when ||b_c - A x_c||_2 (recurrence residual) <=
+    tol * ||b_c||_2, every column an independent CG.  Returns (x, iterations,
+    converged)."""
+    A = A.tocsr()
+    b2 = np.asarray(b, dtype=np.float64).reshape(A.shape[0], -1)
+    n, m = b2.shape
+    dinv = 1.0 / A.diagonal()
+    x = np.zeros((n, m))
+    its = np.zeros(m, dtype=np.int64)
+    conv = np.zeros(m, dtype=bool)
+    for c in range(m):
+        r = b2[:, c].copy()
+        stop = tol * np.linalg.norm(b2[:, c])
+        z = dinv * r
+        p = z.copy()
+        rz = r @ z
+        it = 0
+        while np.linalg.norm(r) > stop and it < max_it:
+            q = A @ p
+            pq = p @ q
+            if pq <= 0.0:
+                raise ArithmeticError("p^T A p <= 0: A not positive definite")
+            alpha = rz / pq
+            x[:, c] += alpha * p
+            r -= alpha * q
+            it += 1
+            z = dinv * r
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        its[c] = it
+        conv[c] = np.linalg.norm(r) <= stop
+    return x.reshape(np.asarray(b).shape), its, conv
+
+
 def cholesky(K: np.ndarray) -> np.ndarray:
     """Lower Cholesky factor L with K = L L^T (LAPACK potrf as one step)."""
     return np.linalg.cholesky(np.asarray(K, dtype=np.float64))

@@ -141,7 +141,7 @@ class _Problem:
             self.keep.append(a)
             return a.ctypes.data_as(_f64p)
 
-        subs = (dd_subdomain * dd.n_sub)()
+        subs = (dd_subdomain * max(1, dd.n_sub))()     # n_sub = 0: undecomposed system
         for k in range(dd.n_sub):
             kig = dd.kig[k].tocsr()
             s = subs[k]

@@ -184,7 +184,7 @@ dd_status validate(const dd_problem *p) {
   if (!p) return fail(nullptr, DD_EINVAL, "problem is NULL");
   if (p->n_dof < 1) return fail(nullptr, DD_EINVAL, "n_dof < 1");
   if (p->n_gamma < 0 || p->n_gamma > p->n_dof) return fail(nullptr, DD_EINVAL, "n_gamma out of range");
-  if (p->n_sub < 1 || !p->sub) return fail(nullptr, DD_EINVAL, "n_sub < 1 or sub is NULL");
+  if (p->n_sub < 0 || (p->n_sub > 0 && !p->sub)) return fail(nullptr, DD_EINVAL, "n_sub < 0 or sub is NULL");
   if (p->n_gamma > 0 && (!p->gamma_map || !p->kgg_rowptr))
     return fail(nullptr, DD_EINVAL, "gamma_map / kgg_rowptr is NULL");
   std::vector<int> seen(p->n_dof, 0);
@@ -412,6 +412,7 @@ dd_status dd_norm2(dd_ctx *c, int ld, const double *vI, const double *vG, double
 
 // z_I = (K_II)^{-1} y_I with the operators of precision `prec`.
 void interior_solve(dd_ctx *c, int prec, int apply, const double *y, double *z, int ld) {
+  if (c->NI <= 0) return;
   if (apply == DD_APPLY_TRSM) {
     int ncolw = std::min(ld, 16);
     dim3 grid(c->n_sub, ld / ncolw);
@@ -474,7 +475,7 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   HIPCHK(c, hipGetLastError());
   // panel by panel: the diagonal block and the rows below it (one workgroup per
   // subdomain), then the trailing update of all subdomains' tiles
-  HIPCHK(c, hipMemsetAsync(c->d_status, 0, c->n_sub * sizeof(int), c->stream));
+  if (c->n_sub > 0) HIPCHK(c, hipMemsetAsync(c->d_status, 0, c->n_sub * sizeof(int), c->stream));
   const int npanels = (c->max_ni + kNB - 1) / kNB;
   for (int J = 0; J < npanels; ++J) {
     hipLaunchKernelGGL((k_potrf_panel<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
@@ -489,13 +490,16 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   }
   HIPCHK(c, hipGetLastError());
   std::vector<int> status(c->n_sub);
-  HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (c->n_sub > 0)
+    HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < c->n_sub; ++k)
     if (status[k])
       return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
                                      std::to_string(status[k] - 1));
-  if (c->use_mfma) {
+  if (c->n_sub == 0) {
+    // no interiors: nothing to invert (S = K_GG)
+  } else if (c->use_mfma) {
     // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set)
     T *X = nullptr;
     HIPCHK(c, hipMalloc(&X, std::max<size_t>(n, 1) * sizeof(T)));
@@ -706,7 +710,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     // (formed at the K_IG gathers, which also store it into pB for the rest of
-    // the iteration)
+    // the iteration; without interiors the interface rows form and store it)
+    const bool p_at_gamma = !dk && c->NI == 0;
     {
       PhaseTimer t(c, DD_PHASE_KIG);
       kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI, dk ? nullptr : pB_);
@@ -716,7 +721,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       interior_solve(c, prec, o.apply, w.yI, w.wI, ld);
     }
     // (timed, when asked, by events the launch itself records: kernel_events)
-    gamma_apply(c, prec, dk ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
+    gamma_apply(c, prec, (dk || p_at_gamma) ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1,
+                p_at_gamma ? pB_ : nullptr);
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
@@ -896,7 +902,8 @@ const char *dd_last_error(const dd_ctx *ctx) {
 }
 
 dd_status dd_footprint(const dd_problem *prob, dd_precision prec, int32_t max_nrhs, size_t *bytes) {
-  if (!prob || !bytes || !prob->sub || prob->n_sub < 1) return fail(nullptr, DD_EINVAL, "bad arguments");
+  if (!prob || !bytes || prob->n_sub < 0 || (prob->n_sub > 0 && !prob->sub))
+    return fail(nullptr, DD_EINVAL, "bad arguments");
   if (max_nrhs < 1 || max_nrhs > kMaxLd) return fail(nullptr, DD_EINVAL, "max_nrhs out of [1, 64]");
   *bytes = footprint_bytes(prob, prec, max_nrhs);
   return DD_OK;
@@ -1405,9 +1412,11 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
     double *pA = w.pG, *pB = w.xG;
     for (int it = 0; it < iters; ++it) {
       Src P{nullptr, w.zG, pA, c->st.beta};
+      const bool p_at_gamma = c->NI == 0;     // no K_IG rows to store the direction
       kig_apply(c, prec, P, L, nullptr, 1.0, w.yI, pB);
       interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);
-      gamma_apply(c, prec, plain(pB), w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
+      gamma_apply(c, prec, p_at_gamma ? P : plain(pB), w.wI, L, nullptr, 1.0, -1.0, w.qG, 1,
+                  p_at_gamma ? pB : nullptr);
       launch_update(c, 1, L, kMaxLd, op.dinv, w.dG, w.rG, w.zG, pB, w.qG, B.o.precond, nullptr, 0,
                     nullptr, c->gamma_parts);
       std::swap(pA, pB);
@@ -1614,7 +1623,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   auto zero_unmasked = [&](const int *mask) -> dd_status {
     for (int j = 0; j < nrhs; ++j)
       if (!mask[j]) {
-        HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
+        if (c->NI) HIPCHK(c, hipMemset2DAsync(w.tI + j, L * 8, 0, 8, c->NI, c->stream));
         if (c->n_gamma) HIPCHK(c, hipMemset2DAsync(w.tG + j, L * 8, 0, 8, c->n_gamma, c->stream));
       }
     return DD_OK;

@@ -133,3 +133,22 @@ def test_bench_traffic_needs_matching_kernel_source():
         bench.MEASURED_TRAFFIC.clear()
         bench.MEASURED_TRAFFIC.update(saved)
     assert bench.measured_traffic("k_gamma_rows<double>", "another workload") is None
+
+
+def test_undecomposed_problem_passes_host_checks(lib):
+    """n_sub = 0 (every dof an interface dof, K_GG = A: the paper's baseline
+    Jacobi-preconditioned CG on the whole system) is valid input: it has a
+    footprint without factor storage, and a gamma_map that is not a
+    permutation is still rejected."""
+    dd, _ = lib
+    A = W.build(W.spec_1d(n=64, strips=2)).asm.A
+    und = W.undecomposed(A)
+    assert und.n_sub == 0
+    nbytes = dd.dd_footprint(und, dd.DD_FP64, 1)
+    assert A.nnz * 12 <= nbytes < A.nnz * 12 + 64 * A.shape[0] * 8 + (1 << 20)
+    bad = W.undecomposed(A)
+    bad.gamma_map = bad.gamma_map.copy()
+    bad.gamma_map[0] = 1
+    with pytest.raises(dd.DDError) as ei:
+        dd.dd_setup(bad, stream=0, max_nrhs=1)
+    assert ei.value.status == dd.DD_EINVAL and "not injective" in str(ei.value)

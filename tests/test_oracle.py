@@ -139,3 +139,61 @@ def test_multi_rhs_columns_independent():
         u, it, _ = orc.solve(b[:, j:j + 1], tol=1e-12)
         assert it[0] == its[j]
         assert np.abs(u[:, 0] - U[:, j]).max() <= 1e-14 * np.abs(U[:, j]).max()
+
+
+# ------------------------------------------------ baseline: Jacobi-PCG on A --
+def test_jacobi_pcg_first_iterates_worked_by_hand():
+    """A = [[4, 1], [1, 3]], b = [1, 2], D = diag(4, 3), x0 = 0, by hand:
+    z0 = p0 = [1/4, 2/3], r0.z0 = 19/12, A p0 = [5/3, 9/4], p0.A p0 = 23/12,
+    alpha0 = 19/23, x1 = [19/92, 38/69]; CG ends after n = 2 steps at
+    A^{-1} b = [1/11, 7/11]."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(np.array([[4.0, 1.0], [1.0, 3.0]]))
+    b = np.array([1.0, 2.0])
+    x1, its, _ = oracle.jacobi_pcg(A, b, tol=1e-300, max_it=1)
+    assert its[0] == 1
+    assert np.allclose(x1, [19 / 92, 38 / 69], rtol=1e-15, atol=0)
+    x2, its, _ = oracle.jacobi_pcg(A, b, tol=1e-300, max_it=2)
+    assert np.allclose(x2, [1 / 11, 7 / 11], rtol=4e-16, atol=0)
+    _, its, conv = oracle.jacobi_pcg(A, b, tol=1e-14)
+    assert conv[0] and its[0] == 2
+
+
+def test_jacobi_pcg_diagonal_system_one_step():
+    """With A diagonal the preconditioned residual is the exact solution:
+    one step, x = b / diag(A)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(7)
+    d = rng.uniform(0.5, 3.0, 50)
+    b = rng.uniform(-1, 1, (50, 2))
+    x, its, conv = oracle.jacobi_pcg(sp.diags(d).tocsr(), b, tol=1e-14)
+    assert conv.all() and np.all(its == 1)
+    assert np.abs(x - b / d[:, None]).max() <= 1e-15 * np.abs(b / d[:, None]).max()
+
+
+def test_jacobi_pcg_matches_monolithic(case):
+    """kappa(A) is a few hundred on these systems, so a 1e-13 relative
+    residual bounds the error by about 1e-10; CG ends within n steps."""
+    wl, b = case
+    A = wl.asm.A
+    x, its, conv = oracle.jacobi_pcg(A, b, tol=1e-13)
+    uref = oracle.monolithic_solve(A, b)
+    assert conv.all() and np.all(its <= A.shape[0])
+    assert oracle.rel_err(x, uref).max() <= 1e-9
+    assert oracle.full_residual(A, x, b).max() <= 1e-12
+
+
+def test_undecomposed_dd_is_jacobi_pcg(case):
+    """With no subdomains the interface Schur complement is A and its exact
+    diagonal is diag(A): the substructuring oracle and the plain Jacobi-PCG
+    (no shared code) take the same iterations to the same iterate."""
+    wl, b = case
+    A = wl.asm.A
+    und = W.undecomposed(A)
+    assert und.n_sub == 0 and und.n_gamma == A.shape[0]
+    orc = oracle.DDOracle(und)
+    assert np.array_equal(orc.schur_diag(), A.diagonal())
+    u0, it0, c0 = orc.solve(b, tol=1e-11)
+    x, its, conv = oracle.jacobi_pcg(A, b, tol=1e-11)
+    assert c0.all() and conv.all() and np.array_equal(it0, its)
+    assert oracle.rel_err(u0, x).max() <= 1e-12

@@ -530,6 +530,18 @@ def split(A: sp.csr_matrix, part: Partition, ncomp: int = 1) -> DDProblem:
     return prob
 
 
+def undecomposed(A: sp.csr_matrix) -> DDProblem:
+    """The system with no subdomains: every dof is an interface dof, so
+    K_GG = A and the interface Schur complement is A itself.  Solved by the
+    substructuring solver this is the diagonally preconditioned CG on the
+    whole system that the paper uses as its baseline (section "Considered
+    solver strategies")."""
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    return DDProblem(n_dof=n, n_gamma=n, gamma_map=np.arange(n, dtype=np.int32), kgg=A)
+
+
 @dataclass
 class Workload:
     spec: Spec
