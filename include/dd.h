@@ -240,14 +240,17 @@ enum {
 };
 
 /* Enable HIP-event timing of the phases whose bit is set in phase_mask
- * (0 disables) and reset the accumulators.  An event pair is recorded on
- * the context's stream around every launch of a timed phase; for
- * DD_PHASE_GAMMA the launch itself records the pair at kernel start and end
- * (the kernel's own duration). */
-dd_status dd_set_timing(dd_ctx *ctx, uint32_t phase_mask);
+ * (0 disables).  An event pair is recorded on the context's stream around
+ * every launch of a timed phase; for DD_PHASE_GAMMA the launch itself records
+ * the pair at kernel start and end (the kernel's own duration; each such pair
+ * adds a few microseconds of stream time).  reset != 0 clears the
+ * accumulators; reset = 0 keeps them (pairs recorded so far are accumulated
+ * first, which synchronises the stream), so timing can be switched on for a
+ * sample of the calls. */
+dd_status dd_set_timing(dd_ctx *ctx, uint32_t phase_mask, int32_t reset);
 
 /* Accumulated milliseconds and launch counts per phase since the last
- * dd_set_timing (ms, launches: H, DD_NPHASES entries each).  Synchronises
+ * the last reset (ms, launches: H, DD_NPHASES entries each).  Synchronises
  * the context's stream. */
 dd_status dd_get_timing(dd_ctx *ctx, double *ms, int64_t *launches);
 

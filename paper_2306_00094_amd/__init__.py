@@ -109,7 +109,7 @@ def load_library(path: str = LIB_PATH):
     lib.dd_batch_retire.argtypes = [vp, _i32p, ctypes.c_int32, vp, ctypes.c_int32,
                                     ctypes.POINTER(dd_solve_info)]
     lib.dd_batch_end.argtypes = [vp]
-    lib.dd_set_timing.argtypes = [vp, ctypes.c_uint32]
+    lib.dd_set_timing.argtypes = [vp, ctypes.c_uint32, ctypes.c_int32]
     lib.dd_get_timing.argtypes = [vp, _f64p, ctypes.POINTER(ctypes.c_int64)]
     lib.dd_last_error.argtypes = [vp]
     lib.dd_last_error.restype = ctypes.c_char_p
@@ -289,13 +289,13 @@ def dd_batch_end(ctx) -> None:
     _check(lib, lib.dd_batch_end(ctx), ctx)
 
 
-def dd_set_timing(ctx, phase_mask: int) -> None:
+def dd_set_timing(ctx, phase_mask: int, reset: bool = True) -> None:
     lib = load_library()
-    _check(lib, lib.dd_set_timing(ctx, phase_mask), ctx)
+    _check(lib, lib.dd_set_timing(ctx, phase_mask, 1 if reset else 0), ctx)
 
 
 def dd_get_timing(ctx):
-    """Returns (ms per phase, launches per phase) accumulated since dd_set_timing."""
+    """Returns (ms per phase, launches per phase) accumulated since the last reset."""
     lib = load_library()
     ms = (ctypes.c_double * DD_NPHASES)()
     n = (ctypes.c_int64 * DD_NPHASES)()

@@ -1529,14 +1529,19 @@ dd_status dd_batch_retire(dd_ctx *c, const int32_t *slots, int32_t ncol, double 
   return batch_relayout(c, batch_need_ld(c));
 }
 
-dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask) {
+dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask, int32_t reset) {
   if (!c) return fail(nullptr, DD_EINVAL, "ctx is NULL");
-  c->timing_mask = phase_mask & ((1u << DD_NPHASES) - 1u);
-  for (int i = 0; i < DD_NPHASES; ++i) {
-    c->t_ms[i] = 0.0;
-    c->t_count[i] = 0;
+  if (reset) {
+    c->tev_used = 0;
+    for (int i = 0; i < DD_NPHASES; ++i) {
+      c->t_ms[i] = 0.0;
+      c->t_count[i] = 0;
+    }
+  } else if (c->tev_used > 0) {       // keep what was recorded so far
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    collect_timing(c);
   }
-  c->tev_used = 0;
+  c->timing_mask = phase_mask & ((1u << DD_NPHASES) - 1u);
   return DD_OK;
 }
 
