@@ -66,6 +66,12 @@ struct ColState {
   int *active;      // 1 while the column iterates
   int *iters;       // iterations taken
   int *flag;        // [0]: breakdown (p^T S p <= 0) seen; [1]: iterate (persistent launch)
+  // three-launch iteration: values of iteration k in slot k & 1 (a launch
+  // reads the previous iteration's slot while its workgroup 0 writes the
+  // current one), and the per-column breakdown marks of the step length
+  double *rz2;      // 2 x kMaxLd
+  int *act2;        // 2 x kMaxLd
+  int *bd;          // kMaxLd
 };
 
 // Partial-sum buffers and completion counters of the reductions.
@@ -182,14 +188,21 @@ __device__ __forceinline__ double chunk_group_sum(const double *part, int P, int
 }
 
 // ----------------------------------------------------------- row products --
-// Source of gathered vector entries: a plain vector x, or the CG direction
-// formed on the fly, x = z + beta * p_prev (beta per column).  Which of the
-// two is fixed at compile time (OTF), so a plain source holds no beta.
+// Source of gathered vector entries, fixed at compile time (OTF):
+//   0  a plain vector x;
+//   1  the CG direction formed on the fly, z + beta * pp (beta per column);
+//   2  the preconditioned residual of the next CG iterate formed on the fly,
+//      dinv_j * (x - alpha q) for columns with upd != 0 and dinv_j * x for the
+//      others (x = the previous residual, alpha = beta[] per column; dinv
+//      nullptr: no preconditioner).
 struct Src {
-  const double *x;       // plain vector (when z == nullptr)
-  const double *z;       // on the fly: z + beta * pp
+  const double *x;       // plain vector (kind 0); previous residual (kind 2)
+  const double *z;       // kind 1: z + beta * pp
   const double *pp;
-  const double *beta;
+  const double *beta;    // kind 1: beta; kind 2: step lengths alpha
+  const double *q;       // kind 2: S p of the previous iteration
+  const double *dinv;    // kind 2: 1 / diagonal of the preconditioner (nullptr: none)
+  const int *upd;        // kind 2: 1 if column c takes the step
 };
 
 template <int C, bool OTF>
@@ -204,10 +217,27 @@ __device__ __forceinline__ void src_load(const Src &s, size_t off, const double 
   }
 }
 
-template <int C, bool OTF>
+template <int C, int OTF>
 __device__ __forceinline__ void src_beta(const Src &s, int cp, double (&bt)[C]) {
 #pragma unroll
   for (int c = 0; c < C; ++c) bt[c] = OTF ? s.beta[cp + c] : 0.0;
+}
+
+// Kind 2 entry of row j.  The residual update and the preconditioner are the
+// exact operations the iteration's own update of row j performs, so every
+// gathered value equals the stored one bit for bit.  q is loaded for every
+// column and ignored where the column takes no step (q may then be stale).
+template <int C>
+__device__ __forceinline__ void src_load_z(const Src &s, int j, int ld, int cp, const double (&a)[C],
+                                           const bool (&up)[C], double (&out)[C]) {
+  const size_t off = (size_t)j * ld + cp;
+  const double d = s.dinv ? s.dinv[j] : 1.0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const double r = s.x[off + c], qv = s.q[off + c];
+    const double rn = up[c] ? fma(-a[c], qv, r) : r;
+    out[c] = s.dinv ? d * rn : rn;
+  }
 }
 
 // acc[c] += sum_k val[k] * x[col[k]][cp + c] over the row, lane-strided.
@@ -234,12 +264,15 @@ __device__ __forceinline__ void load_slots(int k, int e, const int *__restrict__
   }
 }
 
-template <int C, typename VT, bool OTF, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
+template <int C, typename VT, int OTF, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
 __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict__ col,
                                             const VT *__restrict__ val, const Src &x, int ld,
                                             int cp, double (&acc)[C]) {
   double bt[C];
   src_beta<C, OTF>(x, cp, bt);
+  bool up[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) up[c] = OTF == 2 ? x.upd[cp + c] != 0 : false;
   int k = b + (lane_id() & (G - 1));
   double vn[U];
   int cn[U];
@@ -251,8 +284,10 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       v[u] = vn[u];
-      if (cn[u] >= 0) src_load<C, OTF>(x, (size_t)cn[u] * ld + cp, bt, xv[u]);
-      else {
+      if (cn[u] >= 0) {
+        if constexpr (OTF == 2) src_load_z<C>(x, cn[u], ld, cp, bt, up, xv[u]);
+        else src_load<C, OTF != 0>(x, (size_t)cn[u] * ld + cp, bt, xv[u]);
+      } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
       }
@@ -312,6 +347,47 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
         acc2[c] = tfma(v2, xv[u][c], acc2[c]);
       }
     }
+  }
+}
+
+// Two sums over one row at once (one wave per row, entries in the lane order
+// of csr_row_acc): au += val * xs[j] and av += val * qs[j].  SCALED: the
+// gathered entries are multiplied by the preconditioner entry d_j = xs.dinv[j]
+// (1 without one); WITHV = false: the second sum is skipped.
+template <int C, typename VT, bool SCALED, bool WITHV, int U = (Unroll<C>::U + 1) / 2>
+__device__ __forceinline__ void csr_row_acc_uv(int b, int e, const int *__restrict__ col,
+                                               const VT *__restrict__ val, const Src &rs,
+                                               const Src &qs, int ld, int cp, double (&au)[C],
+                                               double (&av)[C]) {
+  int k = b + lane_id();
+  while (k < e) {
+    double v[U];
+    int cc[U];
+    load_slots<U, kWave>(k, e, col, val, v, cc);
+    double xr[U][C], xq[U][C];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cc[u] >= 0) {
+        const size_t off = (size_t)cc[u] * ld + cp;
+        const double d = (SCALED && rs.dinv) ? rs.dinv[cc[u]] : 1.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          xr[u][c] = SCALED ? d * rs.x[off + c] : rs.x[off + c];
+          xq[u][c] = WITHV ? qs.x[off + c] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) { xr[u][c] = 0.0; xq[u][c] = 0.0; }
+      }
+    }
+    k += U * kWave;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        au[c] = tfma(v[u], xr[u][c], au[c]);
+        if (WITHV) av[c] = tfma(v[u], xq[u][c], av[c]);
+      }
   }
 }
 
@@ -497,7 +573,8 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
-             RedBuf red, ColState st) {
+             RedBuf red, ColState st, const double *__restrict__ dinv,
+             double *__restrict__ qd) {
   constexpr int RPW = kWave / G, CH = NW * RPW;
   __shared__ double prod[CH * kMaxLd];
   const int wv = wave_id(), lane = lane_id();
@@ -534,6 +611,7 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
           size_t o = (size_t)j * ld + cp + c;
           q = (base ? base[o] : 0.0) + c1 * a1[c] + c2 * a2[c];
           out[o] = q;
+          if (qd) qd[o] = dinv ? dinv[j] * q : q;   // D^{-1} q for the next K_IG launch
           if (dot) {
             if (pout) pout[o] = pj[c];      // this row of the direction, kept for the update
             q *= pj[c];
@@ -572,9 +650,9 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
-             RedBuf red, ColState st) {
+             RedBuf red, ColState st, const double *__restrict__ dinv, double *__restrict__ qd) {
   gamma_rows_body<C, VT, OTF, G, U, PIPE, NW>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2,
-                                              out, dot, pout, red, st);
+                                              out, dot, pout, red, st, dinv, qd);
 }
 
 
@@ -756,6 +834,536 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       reset_counter(&red.counter[1]);
     }
   }
+}
+
+// ------------------------------------------ three-launch CG iteration --
+// Preconditioned CG on S with one launch fewer per iteration and no
+// completion counters in the update.  With p_k = z_k + beta_{k-1} p_{k-1},
+//   K_IG p_k = K_IG z_k + beta_{k-1} K_IG p_{k-1},
+// so w_k = K_II^{-1} K_IG p_k = K_II^{-1} K_IG z_k + beta_{k-1} w_{k-1}, and with
+// z_k = z_{k-1} - alpha_{k-1} D^{-1} q_{k-1} (both stored; the interface-row kernel
+// writes D^{-1} q with q),
+//   K_IG z_k = K_IG z_{k-1} - alpha_{k-1} K_IG D^{-1} q_{k-1},
+// two row sums that need no step length until the row is complete.  (The
+// slices compute z_k = D^{-1} r_k from the residual; the two agree up to
+// rounding.)  z alternates between two buffers like r.  Modes 0 and 1 only.
+// Iteration k is then
+//   K1 k_cg_kig:   y = K_IG z_k (the two sums, combined with alpha_{k-1});
+//                  the update of 64-row interface slices: x_k = x_{k-1} +
+//                  alpha p_{k-1}, r_k = r_{k-1} - alpha q_{k-1}, z_k = D^{-1} r_k and
+//                  chunk partials of r_k.z_k and r_k.r_k;
+//   K2 k_cg_dense: w_k = K_II^{-1} y + beta_{k-1} w_{k-1}, p_k = z_k + beta_{k-1} p_{k-1}
+//                  for 64-row slices; one workgroup writes the column state of
+//                  iteration k (convergence r_k.r_k <= stop2, iteration count,
+//                  host flag);
+//   K3 k_gamma_rows: q_k = K_GG p_k - K_GI w_k and the p_k.q_k partials.
+// alpha_{k-1} = r_{k-1}.z_{k-1} / p_{k-1}.q_{k-1} (from the interface-row group sums)
+// and beta_{k-1} = r_k.z_k / r_{k-1}.z_{k-1} (from K1's chunk partials) are reduced
+// by a fifth wave of every workgroup while the other four do row work.
+// Workgroups are dispatched in index order, so the ones with the longest
+// chains come first: K2's workgroup 0 writes the column state, then one
+// workgroup per 64-row interface slice (nsl = ceil(nG / 64), plus 1 in K2),
+// then the row workgroups, four rows each (one per wave).  Iteration 0 starts the columns (mode 0: all, mode 2: those
+// with mask[c]): no step, x = 0, beta = 0, so p_0 = z_0 and w_0 = K_II^{-1} K_IG z_0.
+// The residual alternates between two buffers (K1 gathers r_{k-1} while it
+// writes r_k); the column state of iteration k lives in slot k & 1.  Per
+// column every reduction runs the same tree for every batch width.
+struct CgVec {
+  const double *dinv;   // 1 / diag(S), nullptr: no preconditioner
+  double *x;            // iterate
+  const double *r_old;  // r_{k-1} (iteration 0: the initial residual)
+  double *r_new;        // r_k
+  const double *z_old;  // z_{k-1}
+  double *z;            // z_k
+  double *p;            // p_{k-1} before K2, p_k after
+  const double *q;      // S p_{k-1}
+  const double *qd;     // D^{-1} S p_{k-1} (written with q by the interface-row kernel)
+};
+
+__device__ __forceinline__ bool cg_starts(int mode, const int *mask, int c) {
+  return mode == 0 || (mode == 2 && mask[c] != 0);
+}
+
+// Lane part of partials_sum (items lane, lane + 64, ... added in increasing
+// order, the same sum) for partials written by an earlier launch, with
+// ordinary cacheable loads and few registers.
+__device__ __forceinline__ double prev_partials_lane(const double *part, int P, int ld, int c) {
+  double s = 0.0;
+#pragma unroll 2
+  for (int i = lane_id(); i < P; i += kWave) s += part[i * ld + c];
+  return s;
+}
+
+// Step length of column c from loaded inputs (K1): writes salpha / supd.
+__device__ __forceinline__ void cg_k1_column(int mode, const int *mask, int c, int act0, double rz0,
+                                             double pq_lane, ColState st, double *salpha, int *supd) {
+  const double pq = wave_sum(pq_lane);
+  const int act = cg_starts(mode, mask, c) ? 0 : act0;
+  double a = 0.0;
+  int up = 0, brk = 0;
+  if (act) {
+    if (pq > 0.0) {
+      a = rz0 / pq;
+      up = 1;
+    } else {
+      brk = 1;              // p^T S p <= 0: the column stops (recorded by K2)
+    }
+  }
+  if (lane_id() == 0) {
+    salpha[c] = a;
+    supd[c] = up;
+    if (blockIdx.x == 0) st.bd[c] = brk;
+  }
+}
+
+// K1.  Workgroup g < nsl updates interface rows 64g .. 64g+63; the others
+// take four interior rows each.  Wave w reduces the step length of columns
+// w, w+4, ...; the loads of its first column are issued before its row work.
+// E = elements per thread of a slice (64 ld / 256).
+template <int C, int E, typename VT>
+__global__ void __launch_bounds__(kBlock)
+k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
+         const int *__restrict__ col, const VT *__restrict__ val, int nG, int ld, CgVec v,
+         double *__restrict__ y, RedBuf red, ColState st, const int *__restrict__ mask, int npq) {
+  __shared__ double salpha[kMaxLd];
+  __shared__ int supd[kMaxLd];
+  __shared__ double lds[kRowsE * 4 * E];
+  const int wv = wave_id(), lane = lane_id();
+  const bool rowblk = (int)blockIdx.x >= nsl;
+  const int prev = (par ^ 1) * kMaxLd;
+  // first column's inputs, loaded before the row work (at most 64 group
+  // sums: one value per lane, the lane part of prev_partials_lane)
+  int act0 = 0;
+  double rz0 = 0.0, pq1 = 0.0;
+  const bool few = npq <= kWave;
+  if (wv < ld) {
+    act0 = st.act2[prev + wv];
+    rz0 = st.rz2[prev + wv];
+    if (few) pq1 = 0.0 + (lane < npq ? red.part3[(size_t)lane * ld + wv] : 0.0);
+  }
+  auto pq_lane0 = [&]() { return few ? pq1 : prev_partials_lane(red.part3, npq, ld, wv); };
+  if (rowblk) {
+    // u = K_IG z_{k-1} and v = K_IG D^{-1} q_{k-1} for this wave's row,
+    // y = u - alpha v once alpha is known (iteration 0: u = K_IG D^{-1} r_0)
+    const int row = ((int)blockIdx.x - nsl) * kWavesPerBlock + wv;
+    const Src rs{v.r_old, nullptr, nullptr, nullptr, nullptr, v.dinv, nullptr};
+    const Src zs{v.z_old, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const Src qs{v.qd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double au[C], av[C];
+    int b = 0, e = 0;
+    if (row < nrows) {
+      b = ptr[row];
+      e = ptr[row + 1];
+    }
+    bool first = true;
+    for (int cp = 0; cp < ld; cp += C) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) { au[c] = 0.0; av[c] = 0.0; }
+      if (row < nrows) {
+        if (mode == 0) csr_row_acc_uv<C, VT, true, false>(b, e, col, val, rs, rs, ld, cp, au, av);
+        else csr_row_acc_uv<C, VT, false, true>(b, e, col, val, zs, qs, ld, cp, au, av);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        au[c] = wave_sum(au[c]);
+        av[c] = wave_sum(av[c]);
+      }
+      if (first) {
+        if (wv < ld) cg_k1_column(mode, mask, wv, act0, rz0, pq_lane0(), st, salpha, supd);
+        if constexpr (C > kWavesPerBlock)      // (below 16 columns ld == C)
+          for (int c = wv + kWavesPerBlock; c < ld; c += kWavesPerBlock)
+            cg_k1_column(mode, mask, c, st.act2[prev + c], st.rz2[prev + c],
+                         prev_partials_lane(red.part3, npq, ld, c), st, salpha, supd);
+        __syncthreads();
+        first = false;
+      }
+      if (row < nrows && lane == 0)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          y[(size_t)row * ld + cp + c] = supd[cp + c] ? fma(-salpha[cp + c], av[c], au[c]) : au[c];
+    }
+    return;
+  }
+  // slice workgroup: the update of interface rows 64 g .. 64 g + 63
+  const int g = blockIdx.x;
+  const int row0 = g * kRowsE;
+  const int nel = kRowsE * ld;
+  // operands loaded before the step length is known (narrow batches; wide
+  // ones load them where they are used)
+  constexpr int EP = E <= 2 ? E : 1;
+  double ro[EP], qv[EP], xv[EP], pv[EP], dv[EP];
+#pragma unroll
+  for (int k = 0; k < EP; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    const int lr = e / ld, c = e - lr * ld, j = row0 + lr;
+    ro[k] = qv[k] = xv[k] = pv[k] = 0.0;
+    dv[k] = 1.0;
+    if (E <= 2 && e < nel && j < nG) {
+      const size_t o = (size_t)j * ld + c;
+      ro[k] = v.r_old[o];
+      qv[k] = v.q[o];
+      xv[k] = v.x[o];
+      pv[k] = v.p[o];
+      if (v.dinv) dv[k] = v.dinv[j];
+    }
+  }
+  if (wv < ld) cg_k1_column(mode, mask, wv, act0, rz0, pq_lane0(), st, salpha, supd);
+  if constexpr (C > kWavesPerBlock)
+    for (int c = wv + kWavesPerBlock; c < ld; c += kWavesPerBlock)
+      cg_k1_column(mode, mask, c, st.act2[prev + c], st.rz2[prev + c],
+                   prev_partials_lane(red.part3, npq, ld, c), st, salpha, supd);
+  __syncthreads();
+  double rrv[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    rrv[k] = 0.0;
+    if (e < nel) {
+      const int lr = e / ld, c = e - lr * ld, j = row0 + lr;
+      double rz = 0.0;
+      if (j < nG) {
+        const size_t o = (size_t)j * ld + c;
+        const int kp = E <= 2 ? k : 0;
+        const double r0 = E <= 2 ? ro[kp] : v.r_old[o];
+        double rn = r0;
+        if (supd[c]) {
+          const double a = salpha[c];
+          v.x[o] = fma(a, E <= 2 ? pv[kp] : v.p[o], E <= 2 ? xv[kp] : v.x[o]);
+          rn = fma(-a, E <= 2 ? qv[kp] : v.q[o], r0);
+        } else if (cg_starts(mode, mask, c)) {
+          v.x[o] = 0.0;
+        }
+        const double d = E <= 2 ? dv[kp] : (v.dinv ? v.dinv[j] : 1.0);
+        const double zv = v.dinv ? d * rn : rn;
+        v.r_new[o] = rn;
+        v.z[o] = zv;
+        rz = rn * zv;
+        rrv[k] = rn * rn;
+      }
+      lds[e] = rz;
+    }
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    const double sm = chunk64_sum(lds, ld, c);
+    if (lane == 0) red.part0[(size_t)g * ld + c] = sm;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    if (e < nel) lds[e] = rrv[k];
+  }
+  __syncthreads();
+  for (int c = wv; c < ld; c += kWavesPerBlock) {
+    const double sm = chunk64_sum(lds, ld, c);
+    if (lane == 0) red.part1[(size_t)g * ld + c] = sm;
+  }
+}
+
+// Inputs of K2's column scalars for column c (loads only).
+// Inputs of K2's column scalars for column c (rzl, rrl: lane parts of the
+// partial sums, or NaN when not loaded yet).
+struct CgK2In {
+  int act0, bd0, it0;
+  double rz0, s2, rzl, rrl;
+};
+__device__ __forceinline__ CgK2In cg_k2_load(int par, int ld, RedBuf red, ColState st, int nch, bool leader,
+                                             int c) {
+  const int prev = (par ^ 1) * kMaxLd;
+  CgK2In in;
+  in.act0 = st.act2[prev + c];
+  in.bd0 = st.bd[c];
+  in.rz0 = st.rz2[prev + c];
+  in.rzl = prev_partials_lane(red.part0, nch, ld, c);
+  in.rrl = 0.0;
+  in.it0 = 0;
+  in.s2 = 0.0;
+  if (leader) {
+    in.rrl = prev_partials_lane(red.part1, nch, ld, c);
+    in.it0 = st.iters[c];
+    in.s2 = st.stop2[c];
+  }
+  return in;
+}
+
+// beta of column c into sbeta / sinit; in the state workgroup (leader) also
+// the column state of iteration k (scnt = new active flag).
+__device__ __forceinline__ void cg_k2_column(int mode, int par, int nrhs, const int *mask, int c,
+                                             const CgK2In &in, bool leader, ColState st, RedBuf red,
+                                             int nch, int ld, double *sbeta, int *sinit, int *scnt,
+                                             int *sbk) {
+  const double rz = wave_sum(in.rzl);
+  const double rr = leader ? wave_sum(in.rrl) : 0.0;
+  if (lane_id() != 0) return;
+  const int cur = par * kMaxLd;
+  const bool init = cg_starts(mode, mask, c);
+  const int act = init ? 0 : in.act0;
+  const bool brk = act && in.bd0 != 0;
+  sbeta[c] = (act && !brk) ? rz / in.rz0 : 0.0;
+  sinit[c] = init ? 1 : 0;
+  if (!leader) return;
+  int active;
+  sbk[c] = (act && brk) ? 1 : 0;
+  if (init) {
+    st.rz2[cur + c] = rz;
+    st.iters[c] = 0;
+    active = ((mode == 2 || c < nrhs) && rr > in.s2) ? 1 : 0;
+    st.nrm2[c] = rr;
+  } else {
+    active = act;
+    st.rz2[cur + c] = (act && !brk) ? rz : in.rz0;
+    if (act && brk) {
+      active = 0;
+      st.flag[0] = 1;
+    } else if (act) {
+      st.iters[c] = in.it0 + 1;
+      if (rr <= in.s2) active = 0;
+    }
+    if (mode != 2) st.nrm2[c] = rr;
+  }
+  st.act2[cur + c] = active;
+  st.active[c] = active;
+  scnt[c] = active;
+}
+
+// All column scalars of K2 (wave w: columns w, w+4, ...; the first one's
+// inputs passed in when have0), then a barrier; the state workgroup then
+// publishes the number of active columns (+1) to the host.
+__device__ __forceinline__ void cg_k2_scalars(int mode, int par, int ld, int nrhs, const int *mask, RedBuf red,
+                                              ColState st, int nch, bool leader, bool have0, const CgK2In &in0,
+                                              int flag0, int *__restrict__ host_nact, double *sbeta,
+                                              int *sinit, int *scnt, int *sbk) {
+  const int wv = wave_id();
+  if (wv < ld)
+    cg_k2_column(mode, par, nrhs, mask, wv, have0 ? in0 : cg_k2_load(par, ld, red, st, nch, leader, wv), leader,
+                 st, red, nch, ld, sbeta, sinit, scnt, sbk);
+  for (int c = wv + kWavesPerBlock; c < ld; c += kWavesPerBlock)
+    cg_k2_column(mode, par, nrhs, mask, c, cg_k2_load(par, ld, red, st, nch, leader, c), leader, st, red, nch,
+                 ld, sbeta, sinit, scnt, sbk);
+  __syncthreads();
+  if (leader && wv == 0) {
+    const int lane = lane_id();
+    int na = lane < ld ? scnt[lane] : 0;
+    int nb = lane < ld ? sbk[lane] : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      na += __shfl_xor(na, o, kWave);
+      nb += __shfl_xor(nb, o, kWave);
+    }
+    if (lane == 0) {
+      if (mode == 0) st.flag[0] = 0;                    // a new solve starts without breakdown
+      if ((mode != 0 && flag0) || nb) na = 0;           // breakdown ends the loop
+      st.flag[1] = na > 0 ? 1 : 0;
+      if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+// K2 direction slice of workgroup 1 + g: p = z + beta p (started columns
+// p = z) for interface rows 64g .. 64g+63; the first element per thread is
+// loaded before the scalars are known.
+__device__ __forceinline__ void cg_k2_slice_pre(int nG, int ld, const double *__restrict__ z,
+                                                const double *__restrict__ p, double &z0, double &p0) {
+  const int e = threadIdx.x, lr = e / ld, j = ((int)blockIdx.x - 1) * kRowsE + lr;
+  z0 = p0 = 0.0;
+  if (e < kRowsE * ld && j < nG) {
+    z0 = z[(size_t)j * ld + (e - lr * ld)];
+    p0 = p[(size_t)j * ld + (e - lr * ld)];
+  }
+}
+__device__ __forceinline__ void cg_k2_slice(int nG, int ld, const double *__restrict__ z,
+                                            double *__restrict__ p, const double *sbeta,
+                                            const int *sinit, double z0, double p0) {
+  const int row0 = ((int)blockIdx.x - 1) * kRowsE;
+  for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
+    const int lr = e / ld, c = e - lr * ld, j = row0 + lr;
+    if (j >= nG) break;
+    const size_t o = (size_t)j * ld + c;
+    const bool first = e == (int)threadIdx.x;
+    const double zv = first ? z0 : z[o];
+    const double pv = first ? p0 : p[o];
+    p[o] = sinit[c] ? zv : fma(sbeta[c], pv, zv);
+  }
+}
+
+// K2: workgroup 0 writes the column state, workgroups 1 .. nsl-1 update the
+// direction slices, the others take interior rows: one row per wave (row
+// arithmetic of k_dense_rows), w = result + beta w_prev.
+template <int C, typename MT, typename AT>
+__global__ void __launch_bounds__(kBlock)
+k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
+           const long long *__restrict__ koff, const int *__restrict__ ioff, const int *__restrict__ ni,
+           const int *__restrict__ rowsub, const double *__restrict__ y, int ld, double *__restrict__ w,
+           int nG, int nrhs, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
+           ColState st, const int *__restrict__ mask, int *__restrict__ host_nact) {
+  __shared__ double sbeta[kMaxLd];
+  __shared__ int sinit[kMaxLd];
+  __shared__ int scnt[kMaxLd];
+  __shared__ int sbk[kMaxLd];
+  __shared__ double sp[C][kWavesPerBlock][kWave];
+  const int wv = wave_id(), lane = lane_id();
+  const int nch = (nG + kRowsE - 1) / kRowsE;
+  const bool leader = blockIdx.x == 0;
+  const bool rowblk = (int)blockIdx.x >= nsl;
+  if (!rowblk) {
+    const int flag0 = leader ? st.flag[0] : 0;
+    double z0 = 0.0, p0 = 0.0;
+    if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
+    cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
+                  sinit, scnt, sbk);
+    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0);
+    return;
+  }
+  // (launched with C == ld <= 4: one pass covers every column)
+  // Column scalar inputs loaded before the row work: the scalars of column
+  // c < ld, and, with nch <= 256, wave w's part of the r.z partials (item
+  // 64 w + lane of every column; combined through LDS afterwards in the order
+  // of prev_partials_lane).
+  const bool early = nch <= kWavesPerBlock * kWave;
+  double pz[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i = wv * kWave + lane;
+    pz[c] = (early && i < nch) ? red.part0[(size_t)i * ld + c] : 0.0;
+  }
+  const int r = ((int)blockIdx.x - nsl) * kWavesPerBlock + wv;
+  double t = 0.0, wp = 0.0;
+  bool have = false;
+  if (r < nrows) {
+    if (lane < ld) wp = w[(size_t)r * ld + lane];     // w_prev, loaded early
+    const int k = rowsub[r];
+    const int i0 = ioff[k];
+    const int n = ni[k];
+    const MT *row = blocks + koff[k] + (size_t)(r - i0) * n;
+    const double *yb = y + (size_t)i0 * ld;
+    AT acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = (AT)0;
+    constexpr int U = Unroll<C>::U;
+    for (int j = lane; j < n; j += U * kWave) {
+      AT a[U];
+      double yv[U][C];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int jj = j + u * kWave;
+        bool ok = jj < n;
+        a[u] = ok ? (AT)row[jj] : (AT)0;
+        const double *yr = yb + (size_t)(ok ? jj : 0) * ld;
+#pragma unroll
+        for (int c = 0; c < C; ++c) yv[u][c] = ok ? yr[c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = tfma(a[u], (AT)yv[u][c], acc[c]);
+    }
+    // lane c keeps column c's result
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double sv = (double)wave_sum(acc[c]);
+      if (lane == c) t = sv;
+    }
+    have = true;
+  }
+  CgK2In in0{};
+  if (early) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) sp[c][wv][lane] = pz[c];
+    __syncthreads();
+    if (wv < ld) {
+      const int prev = (par ^ 1) * kMaxLd;
+      in0.act0 = st.act2[prev + wv];
+      in0.bd0 = st.bd[wv];
+      in0.rz0 = st.rz2[prev + wv];
+      in0.rzl = 0.0;
+#pragma unroll
+      for (int bw = 0; bw < kWavesPerBlock; ++bw) in0.rzl += sp[wv][bw][lane];
+      in0.rrl = 0.0;
+      in0.it0 = 0;
+      in0.s2 = 0.0;
+    }
+  }
+  cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, false, early, in0, 0, nullptr, sbeta, sinit, scnt, sbk);
+  if (have && lane < ld) {
+    const int c = lane;
+    w[(size_t)r * ld + c] = sinit[c] ? t : fma(sbeta[c], wp, t);
+  }
+}
+
+// K2 for wide batches (ld >= 8): kRB rows per wave (row arithmetic of
+// k_dense_rows_rb), results parked in LDS until beta is known.
+template <int C, typename MT, typename AT>
+__global__ void __launch_bounds__(kBlock)
+k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_first,
+              const MT *__restrict__ blocks, const long long *__restrict__ koff,
+              const int *__restrict__ ioff, const int *__restrict__ ni, const int *__restrict__ rowsub,
+              const double *__restrict__ y, int ld, double *__restrict__ w, int nG, int nrhs,
+              const double *__restrict__ z, double *__restrict__ p, RedBuf red, ColState st,
+              const int *__restrict__ mask, int *__restrict__ host_nact) {
+  __shared__ double sbeta[kMaxLd];
+  __shared__ int sinit[kMaxLd];
+  __shared__ int scnt[kMaxLd];
+  __shared__ int sbk[kMaxLd];
+  __shared__ double st_[kWavesPerBlock][kRB][kMaxLd];
+  const int wv = wave_id(), lane = lane_id();
+  const int nch = (nG + kRowsE - 1) / kRowsE;
+  const bool leader = blockIdx.x == 0;
+  const bool rowblk = (int)blockIdx.x >= nsl;
+  if (!rowblk) {
+    const int flag0 = leader ? st.flag[0] : 0;
+    double z0 = 0.0, p0 = 0.0;
+    if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
+    cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
+                  sinit, scnt, sbk);
+    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0);
+    return;
+  }
+  const int bk = ((int)blockIdx.x - nsl) * kWavesPerBlock + wv;
+  int r0 = 0, nr = 0;
+  if (bk < nblk) {
+    r0 = rb_first[bk];
+    const int k = rowsub[r0];
+    const int i0 = ioff[k], n = ni[k];
+    nr = min(kRB, i0 + n - r0);
+    const MT *rows = blocks + koff[k] + (size_t)(r0 - i0) * n;
+    const double *yb = y + (size_t)i0 * ld;
+    for (int cp = 0; cp < ld; cp += C) {
+      AT acc[kRB][C];
+#pragma unroll
+      for (int rr = 0; rr < kRB; ++rr)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[rr][c] = (AT)0;
+#pragma unroll 2
+      for (int j = lane; j < n; j += kWave) {
+        AT a[kRB];
+#pragma unroll
+        for (int rr = 0; rr < kRB; ++rr) a[rr] = rr < nr ? (AT)rows[(size_t)rr * n + j] : (AT)0;
+        const double *yr = yb + (size_t)j * ld + cp;
+        AT yv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) yv[c] = (AT)yr[c];
+#pragma unroll
+        for (int rr = 0; rr < kRB; ++rr)
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[rr][c] = tfma(a[rr], yv[c], acc[rr][c]);
+      }
+#pragma unroll
+      for (int rr = 0; rr < kRB; ++rr)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          AT sv = wave_sum(acc[rr][c]);
+          if (lane == 0) st_[wv][rr][cp + c] = (double)sv;
+        }
+    }
+  }
+  cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, false, false, CgK2In{}, 0, nullptr, sbeta, sinit, scnt,
+                sbk);
+  for (int rr = 0; rr < nr; ++rr)
+    for (int c = lane; c < ld; c += kWave) {
+      const size_t o = (size_t)(r0 + rr) * ld + c;
+      w[o] = sinit[c] ? st_[wv][rr][c] : fma(sbeta[c], w[o], st_[wv][rr][c]);
+    }
 }
 
 // stop2[c] = f^2 * v[c]  (v: squared norms)

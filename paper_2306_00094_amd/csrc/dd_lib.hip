@@ -47,12 +47,16 @@ struct Ops {
 struct StateBlock {
   double rz[kMaxLd], alpha[kMaxLd], beta[kMaxLd], stop2[kMaxLd], nrm2[kMaxLd];
   double bnrm2[kMaxLd], rnrm2[kMaxLd];
+  double rz2[2 * kMaxLd];
   int active[kMaxLd], iters[kMaxLd], flag[kMaxLd];
+  int act2[2 * kMaxLd], bd[kMaxLd];
 };
 
 struct Work {
   // interface (n_gamma x ldmax)
   double *bG, *xG, *rG, *zG, *pG, *qG, *uG, *dG, *tG;
+  double *r2G, *z2G;       // second residual / preconditioned residual (three-launch iteration)
+  double *qdG;             // D^{-1} q (three-launch iteration)
   // interior (NI x ldmax)
   double *bI, *yI, *wI, *uI, *dI, *tI;
   double *bnrm2, *rnrm2;   // ldmax
@@ -99,6 +103,7 @@ struct dd_ctx {
   size_t bytes = 0;
   int use_mfma = 1;
   int direction_kernel = 0;   // 1: keep p in memory, update it with its own kernel
+  int classic_cg = 0;         // 1: four launches per CG iteration also where three would do
   int num_cu = 0;
   unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
   long long spin_limit = 1ll << 20;
@@ -251,7 +256,7 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   size_t s = prec == DD_MIXED ? 4 : 8;
   b += 2 * kt * s + p->n_gamma * 16;                                  // L, K^-1, diag
   if (prec == DD_MIXED) b += (nig + ngg + nig) * 4;                   // FP32 values
-  b += (9 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                    // work vectors
+  b += (12 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                   // work vectors
   size_t chunks = std::max<size_t>((p->n_gamma + kGChunk - 1) / kGChunk,
                                    (std::max<size_t>(p->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
   b += 3 * chunks * kMaxLd * 8;
@@ -330,7 +335,8 @@ bool kernel_events(dd_ctx *c, int phase, hipEvent_t *e0, hipEvent_t *e1) {
 
 template <int C, typename VT>
 void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
-                  const double *base, double c1, double c2, double *out, int dot, double *pout) {
+                  const double *base, double c1, double c2, double *out, int dot, double *pout,
+                  const double *dinv, double *qd) {
   if (c->n_gamma <= 0) return;
   dim3 g(grid_for(c->n_gamma, kGChunk)), b(kGRows * kWave);
   if (dot) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums
@@ -339,17 +345,17 @@ void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
   if (p.z) {
     if (timed)
       hipExtLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
-                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
-                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
   } else {
     if (timed)
       hipExtLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
-                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
-                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st);
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
   }
 }
 
@@ -383,14 +389,16 @@ void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, do
 #undef DD_UPD
 }
 
+// (qd != nullptr: also qd = D^{-1} out, with D^{-1} = dinv or the identity)
 template <typename VT>
 void gamma_rows(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
-                const double *base, double c1, double c2, double *out, int dot, double *pout) {
+                const double *base, double c1, double c2, double *out, int dot, double *pout,
+                const double *dinv = nullptr, double *qd = nullptr) {
   switch (std::min(ld, 8)) {
-    case 1: launch_gamma<1, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
-    case 2: launch_gamma<2, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
-    case 4: launch_gamma<4, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
-    default: launch_gamma<8, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout); break;
+    case 1: launch_gamma<1, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd); break;
+    case 2: launch_gamma<2, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd); break;
+    case 4: launch_gamma<4, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd); break;
+    default: launch_gamma<8, VT>(c, val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd); break;
   }
 }
 
@@ -454,11 +462,69 @@ void kig_apply(dd_ctx *c, int prec, Src x, int ld, const double *base, double si
 }
 
 void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const double *base,
-                 double c1, double c2, double *out, int dot = 0, double *pout = nullptr) {
+                 double c1, double c2, double *out, int dot = 0, double *pout = nullptr,
+                 const double *dinv = nullptr, double *qd = nullptr) {
   if (prec == DD_FP64)
-    gamma_rows<double>(c, (const double *)c->op[0].g_val, p, z, ld, base, c1, c2, out, dot, pout);
+    gamma_rows<double>(c, (const double *)c->op[0].g_val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd);
   else
-    gamma_rows<float>(c, (const float *)c->op[1].g_val, p, z, ld, base, c1, c2, out, dot, pout);
+    gamma_rows<float>(c, (const float *)c->op[1].g_val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd);
+}
+
+// ------------------------------------------------ three-launch iteration --
+// Launches K1 and K2 of CG iteration k (see k_cg_kig): K2's state
+// workgroup, one workgroup per 64-row interface slice, then the row
+// workgroups.
+template <int C, int E, typename VT>
+void launch_cg_kig_t(dd_ctx *c, const VT *val, int mode, int par, int ld, const CgVec &v,
+                     const int *mask) {
+  const unsigned nsl = grid_for(c->n_gamma, kRowsE);
+  const unsigned g = nsl + grid_for(c->NI, kWavesPerBlock);
+  hipLaunchKernelGGL((k_cg_kig<C, E, VT>), dim3(g), dim3(kBlock), 0, c->stream, mode, par, c->NI,
+                     (int)nsl, c->d_ig_ptr, c->d_ig_col, val, c->n_gamma, ld, v, c->w.yI, c->red, c->st,
+                     mask, c->gamma_parts);
+}
+
+template <typename VT>
+void launch_cg_kig(dd_ctx *c, const VT *val, int mode, int par, int ld, const CgVec &v,
+                   const int *mask) {
+  switch (ld) {
+    case 1: launch_cg_kig_t<1, 1, VT>(c, val, mode, par, ld, v, mask); break;
+    case 2: launch_cg_kig_t<2, 1, VT>(c, val, mode, par, ld, v, mask); break;
+    case 4: launch_cg_kig_t<4, 1, VT>(c, val, mode, par, ld, v, mask); break;
+    case 8: launch_cg_kig_t<8, 2, VT>(c, val, mode, par, ld, v, mask); break;
+    case 16: launch_cg_kig_t<16, 4, VT>(c, val, mode, par, ld, v, mask); break;
+    case 32: launch_cg_kig_t<16, 8, VT>(c, val, mode, par, ld, v, mask); break;
+    default: launch_cg_kig_t<16, 16, VT>(c, val, mode, par, ld, v, mask); break;
+  }
+}
+
+template <int C, typename MT, typename AT>
+void launch_cg_dense_t(dd_ctx *c, const MT *kinv, int mode, int par, int ld, int nrhs, const CgVec &v,
+                       const int *mask, int *host_nact) {
+  const unsigned nsl = grid_for(c->n_gamma, kRowsE) + 1;     // slices and the state workgroup
+  if (ld >= 8 && c->n_rb > 0) {
+    const unsigned nrb = grid_for(c->n_rb, kWavesPerBlock);
+    hipLaunchKernelGGL((k_cg_dense_rb<8, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode,
+                       par, c->n_rb, (int)nsl, c->d_rb_first, kinv, c->d_koff, c->d_ioff, c->d_ni,
+                       c->d_rowsub, c->w.yI, ld, c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask,
+                       host_nact);
+  } else {
+    const unsigned nrb = grid_for(c->NI, kWavesPerBlock);
+    hipLaunchKernelGGL((k_cg_dense<C, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode, par,
+                       c->NI, (int)nsl, kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, c->w.yI, ld,
+                       c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, host_nact);
+  }
+}
+
+template <typename MT, typename AT>
+void launch_cg_dense(dd_ctx *c, const MT *kinv, int mode, int par, int ld, int nrhs, const CgVec &v,
+                     const int *mask, int *host_nact) {
+  switch (std::min(ld, 8)) {
+    case 1: launch_cg_dense_t<1, MT, AT>(c, kinv, mode, par, ld, nrhs, v, mask, host_nact); break;
+    case 2: launch_cg_dense_t<2, MT, AT>(c, kinv, mode, par, ld, nrhs, v, mask, host_nact); break;
+    case 4: launch_cg_dense_t<4, MT, AT>(c, kinv, mode, par, ld, nrhs, v, mask, host_nact); break;
+    default: launch_cg_dense_t<8, MT, AT>(c, kinv, mode, par, ld, nrhs, v, mask, host_nact); break;
+  }
 }
 
 // ---------------------------------------------------------------- factor --
@@ -609,6 +675,31 @@ void collect_timing(dd_ctx *c) {
   c->tev_used = 0;
 }
 
+// K1, K2 and K3 of iteration k (modes 0 and 1); r_{k-1} and z_{k-1} are in
+// rG / zG for even k and in r2G / z2G for odd k.
+void cg3_iteration(dd_ctx *c, int prec, int k, int mode, int ld, int nrhs, int precond, double *x,
+                   const int *mask, int *host_nact) {
+  Work &w = c->w;
+  const Ops &op = c->op[prec];
+  const int par = k & 1;
+  const double *dinv = precond ? op.dinv : nullptr;
+  CgVec v{dinv, x, par ? w.r2G : w.rG, par ? w.rG : w.r2G, par ? w.z2G : w.zG, par ? w.zG : w.z2G,
+          w.pG, w.qG, w.qdG};
+  {
+    PhaseTimer t(c, DD_PHASE_KIG);
+    if (prec == DD_FP64) launch_cg_kig<double>(c, (const double *)op.ig_val, mode, par, ld, v, mask);
+    else launch_cg_kig<float>(c, (const float *)op.ig_val, mode, par, ld, v, mask);
+  }
+  {
+    PhaseTimer t(c, DD_PHASE_INTERIOR);
+    if (prec == DD_FP64)
+      launch_cg_dense<double, double>(c, (const double *)op.kinv, mode, par, ld, nrhs, v, mask, host_nact);
+    else
+      launch_cg_dense<float, float>(c, (const float *)op.kinv, mode, par, ld, nrhs, v, mask, host_nact);
+  }
+  gamma_apply(c, prec, plain(w.pG), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1, nullptr, dinv, w.qdG);
+}
+
 // ------------------------------------------------------------------ solve --
 struct CoreOpts {
   int max_it;
@@ -672,11 +763,18 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // condensation (eq. subForcing summed over subdomains): r = bG - K_GI K_II^{-1} bI
   interior_solve(c, prec, o.apply, bI, w.wI, ld);
   gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
+  // Three launches per iteration where the interiors exist and their inverse
+  // is applied (k_cg_kig); otherwise four (K_IG, interior solve, interface
+  // rows, update), which the persistent kernel also runs.
+  const bool cg3 = c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
+                   o.launch != DD_LAUNCH_PERSISTENT && !c->classic_cg;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
   if (c->n_gamma == 0)            // no init kernel to clear the breakdown flag
     HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
-  if (c->n_gamma > 0)
+  if (cg3)                        // iteration 0: start every column (p_0 = z_0, q_0 = S p_0)
+    cg3_iteration(c, prec, 0, 0, ld, nrhs, o.precond, uG, nullptr, nullptr);
+  else if (c->n_gamma > 0)
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
                   c->direction_kernel, nullptr, 0);
   HIPCHK(c, hipGetLastError());
@@ -738,6 +836,13 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     HIPCHK(c, hipGetLastError());
     return DD_OK;
   };
+  // CG iteration k >= 1 in either scheme
+  auto step = [&](int k, double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
+    if (!cg3) return iteration(pA_, pB_, nact_dst);
+    cg3_iteration(c, prec, k, 1, ld, nrhs, o.precond, uG, nullptr, nact_dst);
+    HIPCHK(c, hipGetLastError());
+    return DD_OK;
+  };
   if (o.launch == DD_LAUNCH_GRAPH && !stop) {
     // G iterations per graph (even, so the direction buffers return to place)
     int G = std::max(2, std::min(32, o.check_every > 0 ? o.check_every : 4));
@@ -759,8 +864,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       c->capturing = true;
       dd_status cs = DD_OK;
       double *qa = pA, *qb = pB;
-      for (int i = 0; i < G && cs == DD_OK; ++i)
-        cs = iteration(qa, qb, i == G - 1 ? c->h_nact_dev : nullptr);
+      for (int i = 0; i < G && cs == DD_OK; ++i)     // iterations 1..G (odd k first)
+        cs = step(1 + i, qa, qb, i == G - 1 ? c->h_nact_dev : nullptr);
       c->capturing = false;
       hipGraph_t graph = nullptr;
       hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
@@ -819,7 +924,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       ++it;
       int slot = it % c->nslots;
       hn[slot] = 0;
-      TRY(iteration(pA, pB, c->h_nact_dev + slot));
+      TRY(step(it, pA, pB, c->h_nact_dev + slot));
       ring_it[slot] = it;
       // look at iteration it - lag, never more than nslots in flight
       int target = it - lag;
@@ -947,6 +1052,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   c->ldmax = next_pow2(max_nrhs);
   if (const char *e = getenv("DD_NO_MFMA")) c->use_mfma = atoi(e) ? 0 : 1;
   if (const char *e = getenv("DD_DIRECTION_KERNEL")) c->direction_kernel = atoi(e) ? 1 : 0;
+  if (const char *e = getenv("DD_CLASSIC_CG")) c->classic_cg = atoi(e) ? 1 : 0;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
@@ -1041,7 +1147,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   // work vectors
   size_t nG = (size_t)std::max(1, c->n_gamma) * c->ldmax, nI = (size_t)std::max(1, NI) * c->ldmax;
   Work &w = c->w;
-  double **gv[] = {&w.bG, &w.xG, &w.rG, &w.zG, &w.pG, &w.qG, &w.uG, &w.dG, &w.tG};
+  double **gv[] = {&w.bG, &w.xG, &w.rG, &w.zG, &w.pG, &w.qG, &w.uG, &w.dG, &w.tG, &w.r2G, &w.z2G, &w.qdG};
   for (double **q : gv)
     if ((s = dalloc(c, q, nG)) != DD_OK) return bail(s);
   double **iv[] = {&w.bI, &w.yI, &w.wI, &w.uI, &w.dI, &w.tI};
@@ -1060,6 +1166,9 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     c->st.active = sb->active;
     c->st.iters = sb->iters;
     c->st.flag = sb->flag;
+    c->st.rz2 = sb->rz2;
+    c->st.act2 = sb->act2;
+    c->st.bd = sb->bd;
     if (hipMemset(sb, 0, sizeof(StateBlock)) != hipSuccess) {
       c->err = "hipMemset failed";
       return bail(DD_EHIP);
@@ -1181,7 +1290,9 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   HIPCHK(c, hipGetLastError());
   struct Cand { int apply, launch, dk, ce; };
   std::vector<Cand> cands;
-  for (int dk = 0; dk < 2; ++dk) {
+  // the direction kernel exists only in the four-launch iteration
+  const int ndk = (c->NI > 0 && !c->classic_cg) ? 1 : 2;
+  for (int dk = 0; dk < ndk; ++dk) {
     for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, dk, lag});
     for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, dk, g});
   }

@@ -160,13 +160,16 @@ def test_batch_invariance(prec):
 
 @pytest.mark.parametrize("name", ["1d-ragged", "2d-const", "2d-pd"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_persistent_launch_matches_kernels(name, prec):
+def test_persistent_launch_matches_kernels(name, prec, monkeypatch):
     """One cooperative persistent kernel for the CG loop gives the same
-    solution, bit for bit, as one launch per phase."""
+    solution, bit for bit, as one launch per phase of the same four-phase
+    iteration (forced here; by default stream launches use three per
+    iteration)."""
     dd = _dd()
     wl, b, uref = problem(name)
     print(f"case persistent {name} prec={prec}", flush=True)
     nrhs = b.shape[1]
+    monkeypatch.setenv("DD_CLASSIC_CG", "1")
     s = dd.Solver(wl.dd, max_nrhs=nrhs)
     s.factor(prec)
     o1 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS)
@@ -213,7 +216,7 @@ def test_autotune_then_auto_solve(prec):
     s.factor(prec)
     res = s.autotune(prec, nrhs, dd.dd_default_opts(tol=1e-12))
     print("  tuned", res, flush=True)
-    assert res["candidates"] >= 8 and res["ms_per_solve"] > 0
+    assert res["candidates"] >= 7 and res["ms_per_solve"] > 0
     assert res["launch"] in (1, 2, 3) and res["apply"] in (1, 2)
     if prec == 1:        # the mixed path also tunes its inner tolerance
         assert res["inner_tol"] in (1e-4, 1e-5, 1e-6)
@@ -253,3 +256,35 @@ def test_factor_rejects_indefinite_block(prec):
     r = s.solve(to_dev(b[:, :1]), prec=prec, opts=dd.dd_default_opts(tol=1e-12))
     assert oracle.rel_err(r.u.cpu().numpy().T, uref[:, :1]).max() <= (1e-10 if prec == 0 else 1e-8)
     s.close()
+
+
+@pytest.mark.parametrize("name", ["1d-4strips", "2d-const-3x2", "2d-pd"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_three_launch_iteration_matches_four_launch(name, prec, monkeypatch):
+    """The three-launch CG iteration (interior-solve recurrence, update fused
+    into the K_IG launch) and the four-launch one are the same method: the
+    same iteration counts (up to one, from rounding) and solutions that agree
+    to the parity gate; both meet it against the monolithic solution."""
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case three vs four launches {name} prec={prec}", flush=True)
+    nrhs = b.shape[1]
+    opts = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS, apply=dd.DD_APPLY_INV)
+    s3 = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s3.factor(prec)
+    r3 = s3.solve(to_dev(b), prec=prec, opts=opts)
+    monkeypatch.setenv("DD_CLASSIC_CG", "1")
+    s4 = dd.Solver(wl.dd, max_nrhs=nrhs)
+    s4.factor(prec)
+    r4 = s4.solve(to_dev(b), prec=prec, opts=opts)
+    i3 = np.array([i["iters"] for i in r3.info])
+    i4 = np.array([i["iters"] for i in r4.info])
+    print("  iters", i3, i4, flush=True)
+    assert np.all(np.abs(i3 - i4) <= 1 + 2 * (prec == 1)), (i3, i4)
+    u3, u4 = r3.u.cpu().numpy().T, r4.u.cpu().numpy().T
+    gate = 1e-10 if prec == 0 else 1e-8
+    assert oracle.rel_err(u3, uref).max() <= gate
+    assert oracle.rel_err(u4, uref).max() <= gate
+    assert oracle.rel_err(u3, u4).max() <= 2 * gate
+    s3.close()
+    s4.close()

@@ -62,10 +62,13 @@ def run_batch(dd, s, b, schedule, prec, opts):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_api_matches_dd_solve(prec):
+def test_batch_api_matches_dd_solve(prec, monkeypatch):
+    """The batch API runs the four-launch CG iteration; dd_solve forced to the
+    same iteration gives the same bits."""
     dd = _dd()
     wl, b, uref = system("2d")
     print(f"case batch api prec={prec}", flush=True)
+    monkeypatch.setenv("DD_CLASSIC_CG", "1")
     s = dd.Solver(wl.dd, max_nrhs=64)
     s.factor(prec)
     opts = dd.dd_default_opts(tol=1e-11)
