@@ -54,17 +54,17 @@ WORKLOADS = {
 # rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of this benchmark on the
 # default workload, each scaled by what the counter read for an elementwise
 # kernel of known traffic (FETCH x2.000, WRITE x1.000): 256 MiB read and written
-# read as 131085.3 KiB fetched and 262148.0 KiB written.  Valid only for the
+# read as 131085.6 KiB fetched and 262148.2 KiB written.  Valid only for the
 # kernel source they were taken on (sha256 prefix of csrc/dd_kernels.h);
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    "src_sha256": "fca7be61cd6bd97a",
+    "src_sha256": "ba23a9c74cb2de10",
     "workload": "cfg2",
     # median over the launches of the CG iterations (full [K_GG | K_GI] sweep)
-    "k_gamma_rows<float>": dict(fetch_kib=23242.3, write_kib=148.2),
-    "k_gamma_rows<double>": dict(fetch_kib=34223.1, write_kib=148.3),
-    "fetch_scale": 262144.0 / 131085.3,
-    "write_scale": 262144.0 / 262148.0,
+    "k_gamma_rows<float>": dict(fetch_kib=23326.2, write_kib=221.8),
+    "k_gamma_rows<double>": dict(fetch_kib=34284.0, write_kib=221.8),
+    "fetch_scale": 262144.0 / 131085.6,
+    "write_scale": 262144.0 / 262148.2,
 }
 
 
@@ -87,29 +87,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gamma_kernel_bytes(dd, nrhs_pad: int, value_bytes: int) -> float:
+def gamma_kernel_bytes(dd, nrhs_pad: int, value_bytes: int, gamma_vectors: int = 3) -> float:
     """Algorithmic HBM bytes of one interface-row launch (q = K_GG p - K_GI w):
     every nonzero of [K_GG | K_GI] once (value + int32 column), the row and
-    split pointers, and each vector once: p and w read, q and the stored
-    direction written."""
+    split pointers, the interior vector w read once, and gamma_vectors
+    interface-vector passes (three-launch CG iteration: p read, q and D^-1 q
+    written; undecomposed system: p read and q written, plus z read and p
+    written when the direction is formed at the gathers)."""
     nnz = dd.kgg.nnz + sum(k.nnz for k in dd.kig)
     ni = sum(len(m) for m in dd.i_maps)
     ng = dd.n_gamma
     return (nnz * (value_bytes + 4) + (2 * ng + 1) * 4
-            + 8.0 * nrhs_pad * (3 * ng + ni))
+            + 8.0 * nrhs_pad * (gamma_vectors * ng + ni))
 
 
 def iteration_bytes(dd, nrhs_pad: int, value_bytes: int) -> float:
-    """Algorithmic bytes of one CG iteration: K_IG rows, the interior inverse
-    blocks, the interface rows and the vector updates (x, r, z, p, q read or
-    written once each)."""
+    """Algorithmic bytes of one CG iteration: K_IG rows (y written), the
+    interior inverse blocks (y read, w read and written), the interface rows,
+    and the interface-vector updates (r, z, p, q, D^-1 q, x: about 10 passes)."""
     nig = sum(k.nnz for k in dd.kig)
     ni = sum(len(m) for m in dd.i_maps)
     kinv = sum(k.size for k in dd.kii)
     return (nig * (value_bytes + 4) + (ni + 1) * 4 + 8.0 * nrhs_pad * ni
-            + kinv * value_bytes + 8.0 * nrhs_pad * 2 * ni
+            + kinv * value_bytes + 8.0 * nrhs_pad * 3 * ni
             + gamma_kernel_bytes(dd, nrhs_pad, value_bytes)
-            + 8.0 * nrhs_pad * 6 * dd.n_gamma)
+            + 8.0 * nrhs_pad * 10 * dd.n_gamma)
 
 
 def factor_flops(dd) -> float:
@@ -259,7 +261,8 @@ def jacobi_cg_leg(dd, workloads, wl, bt, b, tol, steps, warmup, torch, cpu_secon
             roof = None
             if r["gamma_launches"] > 0:
                 avg = r["gamma_ms"] / r["gamma_launches"] * 1e-3
-                algo = gamma_kernel_bytes(und, ld, vb)
+                # direction kept by its own kernel: p read, q written; else also z read, p written
+                algo = gamma_kernel_bytes(und, ld, vb, 2 if tuned.get("direction_kernel") else 4)
                 ach = algo / avg / 1e9
                 roof = dict(bound="hbm", kernel="k_gamma_rows<%s> (q = A p)" % ("double" if vb == 8 else "float"),
                             achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
