@@ -94,6 +94,13 @@ typedef enum {
   DD_APPLY_TRSM = 2    /* forward and backward triangular sweeps with L */
 } dd_apply;
 
+/* A CG iteration on S is three launches (K_IG product with the previous
+ * iteration's update, interior solve with the direction recurrence,
+ * interface rows) or four (K_IG product, interior solve, interface rows,
+ * update).  Untuned solves use three when the explicit inverse is applied and
+ * subdomains exist, at every batch width (a column's result does not depend on
+ * the batch); the autotuner times both forms per width.  The persistent
+ * kernel, the triangular-sweep variant and the batch API use four. */
 typedef enum {
   DD_LAUNCH_AUTO = 0,
   DD_LAUNCH_KERNELS = 1,     /* one kernel launch per phase, host polls convergence */
@@ -180,11 +187,15 @@ typedef struct {
   double ms_per_solve;       /* measured time of one solve of the batch with this schedule */
   int32_t candidates;        /* schedules timed */
   double inner_tol;          /* DD_MIXED: inner tolerance chosen (0 for DD_FP64) */
+  int32_t three_launch;      /* 1: three launches per CG iteration (update fused into the
+                                K_IG launch, direction recurrence in the interior solve);
+                                0: four (K_IG, interior solve, interface rows, update) */
 } dd_tune_result;
 
 /* Autotuner: time every candidate schedule of the CG loop on this context and
  * precision for a batch of nrhs synthetic right-hand sides (launch mode,
- * interior-solve variant, direction handling, polling lag), keep the fastest,
+ * interior-solve variant, three or four launches per iteration, direction
+ * handling, polling lag), keep the fastest,
  * and use it for later dd_solve calls of that precision and batch width whose
  * opts leave apply and launch at AUTO.  For DD_MIXED with base->inner_tol == 0
  * the inner tolerance (1e-4, 1e-5, 1e-6) is then timed with that schedule and

@@ -69,7 +69,7 @@ class dd_tune_result(ctypes.Structure):
     _fields_ = [("apply", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("direction_kernel", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("ms_per_solve", ctypes.c_double), ("candidates", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("three_launch", ctypes.c_int32)]
 
 
 class DDError(RuntimeError):
@@ -250,7 +250,7 @@ def dd_autotune(ctx, prec: int, nrhs: int, opts: dd_solve_opts | None = None) ->
                                 ctypes.byref(r)), ctx)
     return dict(apply=r.apply, launch=r.launch, direction_kernel=r.direction_kernel,
                 check_every=r.check_every, ms_per_solve=r.ms_per_solve, candidates=r.candidates,
-                inner_tol=r.inner_tol)
+                inner_tol=r.inner_tol, three_launch=r.three_launch)
 
 
 def dd_batch_begin(ctx, prec: int, opts: dd_solve_opts | None = None) -> None:

@@ -109,14 +109,19 @@ struct dd_ctx {
   long long spin_limit = 1ll << 20;
   int last_launch = DD_LAUNCH_KERNELS;
   struct GraphEntry {
-    int prec, ld, apply, precond, dk, iters;
+    int prec, ld, apply, precond, dk, iters, cg3;
     double *x;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
   bool capturing = false;
   // autotuned schedules per precision and batch width (log2)
-  struct Tuned { bool set = false; int apply = 0, launch = 0, dk = 0, check_every = 0; double ms = 0, inner_tol = 0; };
+  struct Tuned {
+    bool set = false;
+    int apply = 0, launch = 0, dk = 0, check_every = 0, cg3 = 1;
+    double ms = 0, inner_tol = 0;
+  };
+  int force_cg3 = -1;         // autotuner: -1 schedule decides, 0 four launches, 1 three
   Tuned tuned[2][7];
   // continuous batching
   struct Batch {
@@ -707,7 +712,13 @@ struct CoreOpts {
   int apply;
   int check_every;
   int launch;
+  int cg3;        // 1: three launches per CG iteration where possible
 };
+
+// Untuned solves run three launches per iteration (k_cg_kig) at every batch
+// width, so a column's arithmetic never depends on the batch.  The autotuner
+// may choose four per width (wide batches run them faster: the three-launch
+// K_IG kernel holds more registers there).
 
 // ------------------------------------------------------ persistent launch --
 template <int C, typename VT, typename MT, typename AT>
@@ -766,7 +777,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // Three launches per iteration where the interiors exist and their inverse
   // is applied (k_cg_kig); otherwise four (K_IG, interior solve, interface
   // rows, update), which the persistent kernel also runs.
-  const bool cg3 = c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
+  const bool cg3 = o.cg3 && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
                    o.launch != DD_LAUNCH_PERSISTENT && !c->classic_cg;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
@@ -850,7 +861,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     hipGraphExec_t exec = nullptr;
     for (auto &g : c->graphs)
       if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
-          g.dk == c->direction_kernel && g.iters == G && g.x == uG)
+          g.dk == c->direction_kernel && g.iters == G && g.x == uG && g.cg3 == (cg3 ? 1 : 0))
         exec = g.exec;
     if (!exec) {
       if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -880,7 +891,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       (void)hipGraphDestroy(graph);
       if (ee != hipSuccess)
         return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
-      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, uG, exec});
+      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, cg3 ? 1 : 0, uG, exec});
     }
     // replay; look at the result of launch n - 1 while launch n runs.  The
     // number of active columns only decreases, so a later value is as good.
@@ -1288,16 +1299,20 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   hipLaunchKernelGGL(k_fill_rhs, dim3(256), dim3(256), 0, c->stream, c->n_dof, nrhs, c->n_dof,
                      0x5eedull, b);
   HIPCHK(c, hipGetLastError());
-  struct Cand { int apply, launch, dk, ce; };
+  struct Cand { int apply, launch, dk, ce, cg3; };
   std::vector<Cand> cands;
-  // the direction kernel exists only in the four-launch iteration
-  const int ndk = (c->NI > 0 && !c->classic_cg) ? 1 : 2;
-  for (int dk = 0; dk < ndk; ++dk) {
-    for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, dk, lag});
-    for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, dk, g});
+  // three-launch iteration (when there are interiors), then the four-launch
+  // one with the direction formed at the gathers or kept by its own kernel
+  if (c->NI > 0 && !c->classic_cg) {
+    for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 0, lag, 1});
+    for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 0, g, 1});
   }
-  cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2});
-  cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0});
+  for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 0, lag, 0});
+  for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 0, g, 0});
+  cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 0});
+  cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 0});
+  cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2, 0});
+  cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0, 0});
   const int saved_dk = c->direction_kernel;
   int lg = 0;
   while ((1 << lg) < next_pow2(nrhs)) ++lg;
@@ -1310,6 +1325,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     oc.launch = cd.launch;
     oc.check_every = cd.ce;
     c->direction_kernel = cd.dk;
+    c->force_cg3 = cd.cg3;
     dd_status s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);   // warm-up (captures graphs)
     if (s != DD_OK && s != DD_ENOCONV) continue;
     const int reps = 3;
@@ -1334,6 +1350,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
       oc.check_every = bc.ce;
       oc.inner_tol = itol;
       c->direction_kernel = bc.dk;
+      c->force_cg3 = bc.cg3;
       dd_status s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);
       if (s != DD_OK) continue;
       const int reps = 3;
@@ -1350,12 +1367,14 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     }
   }
   c->direction_kernel = saved_dk;
+  c->force_cg3 = -1;
   c->err.clear();
   auto &t = c->tuned[prec][lg];
   t.set = true;
   t.apply = bc.apply;
   t.launch = bc.launch;
   t.dk = bc.dk;
+  t.cg3 = bc.cg3;
   t.check_every = bc.ce;
   t.ms = best;
   t.inner_tol = prec == DD_MIXED ? best_itol : 0.0;
@@ -1367,6 +1386,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     out->ms_per_solve = best;
     out->candidates = ncand;
     out->inner_tol = t.inner_tol;
+    out->three_launch = bc.cg3;
   }
   return DD_OK;
 }
@@ -1693,6 +1713,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in [0,1)");
   const int L = next_pow2(nrhs);
   if (prec == DD_MIXED) o.inner_tol = resolve_inner_tol(c, prec, L, o.inner_tol);
+  int use_cg3 = 1;
   struct RestoreDk {
     dd_ctx *c;
     int v;
@@ -1707,13 +1728,16 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
       if (o.launch == DD_LAUNCH_AUTO) {
         o.launch = t.launch;
         c->direction_kernel = t.dk;
+        use_cg3 = t.cg3;
         if (o.check_every == 0) o.check_every = t.check_every;
       }
     }
   }
+  if (c->force_cg3 >= 0) use_cg3 = c->force_cg3;
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
               o.check_every,
-              (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS};
+              (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS,
+              use_cg3};
   Work &w = c->w;
   // gather b into the DD layout (both parts in one launch)
   const int n_all = c->NI + c->n_gamma;

@@ -218,6 +218,7 @@ def test_autotune_then_auto_solve(prec):
     print("  tuned", res, flush=True)
     assert res["candidates"] >= 7 and res["ms_per_solve"] > 0
     assert res["launch"] in (1, 2, 3) and res["apply"] in (1, 2)
+    assert res["three_launch"] in (0, 1)
     if prec == 1:        # the mixed path also tunes its inner tolerance
         assert res["inner_tol"] in (1e-4, 1e-5, 1e-6)
     else:
@@ -287,4 +288,34 @@ def test_three_launch_iteration_matches_four_launch(name, prec, monkeypatch):
     assert oracle.rel_err(u4, uref).max() <= gate
     assert oracle.rel_err(u3, u4).max() <= 2 * gate
     s3.close()
+    s4.close()
+
+
+def test_three_launch_wide_batch(monkeypatch):
+    """16 columns (wide-batch kernels of the three-launch iteration): the same
+    iterations (up to one) and solutions as the four-launch iteration within
+    the gate, and every column equal, bit for bit, to the same column solved
+    alone."""
+    dd = _dd()
+    wl, b, uref = problem("2d-const")
+    print("case three-launch wide batch, 16 columns", flush=True)
+    b16 = np.tile(b, (1, 6))[:, :16]
+    opts = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS, apply=dd.DD_APPLY_INV)
+    s = dd.Solver(wl.dd, max_nrhs=16)
+    s.factor(dd.DD_FP64)
+    r = s.solve(to_dev(b16), prec=dd.DD_FP64, opts=opts)
+    u = r.u.cpu().numpy()
+    assert oracle.rel_err(u.T[:, :3], uref).max() <= 1e-10
+    for j in (0, 5, 15):
+        r1 = s.solve(to_dev(b16[:, j:j + 1]), prec=dd.DD_FP64, opts=opts)
+        assert np.array_equal(r1.u.cpu().numpy()[0], u[j]), j
+    monkeypatch.setenv("DD_CLASSIC_CG", "1")
+    s4 = dd.Solver(wl.dd, max_nrhs=16)
+    s4.factor(dd.DD_FP64)
+    r4 = s4.solve(to_dev(b16), prec=dd.DD_FP64, opts=opts)
+    i3 = np.array([i["iters"] for i in r.info])
+    i4 = np.array([i["iters"] for i in r4.info])
+    assert np.all(np.abs(i3 - i4) <= 1), (i3, i4)
+    assert oracle.rel_err(u.T, r4.u.cpu().numpy().T).max() <= 2e-10
+    s.close()
     s4.close()
