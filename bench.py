@@ -258,16 +258,27 @@ def jacobi_cg_leg(dd, workloads, wl, bt, b, tol, steps, warmup, torch, cpu_secon
             tuned = s.autotune(prec, nrhs, opts)
             r = time_path(s, dd, bt, prec, opts, steps, warmup, torch)
             vb = 8 if prec == dd.DD_FP64 else 4
+            # direction kept by its own kernel: p read, q written; else also z read, p written
+            sweep = gamma_kernel_bytes(und, ld, vb, 2 if tuned.get("direction_kernel") else 4)
             roof = None
             if r["gamma_launches"] > 0:
                 avg = r["gamma_ms"] / r["gamma_launches"] * 1e-3
-                # direction kept by its own kernel: p read, q written; else also z read, p written
-                algo = gamma_kernel_bytes(und, ld, vb, 2 if tuned.get("direction_kernel") else 4)
-                ach = algo / avg / 1e9
+                ach = sweep / avg / 1e9
                 roof = dict(bound="hbm", kernel="k_gamma_rows<%s> (q = A p)" % ("double" if vb == 8 else "float"),
                             achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                            algo_bytes_per_launch=algo, avg_launch_us=1e6 * avg,
+                            algo_bytes_per_launch=sweep, avg_launch_us=1e6 * avg,
                             launches=r["gamma_launches"])
+            elif r["loop_launches"] > 0:
+                # graph replay: whole iterations per launch (sweep + update + direction passes)
+                its = sum(i["iters"] for i in r["info"]) / max(1, len(r["info"]))
+                sampled = (steps + TIMING_EVERY - 1) // TIMING_EVERY
+                per_it = sweep + 8.0 * ld * und.n_gamma * (7 + (3 if tuned.get("direction_kernel") else 0))
+                algo = per_it * its / max(1, r["loop_launches"] / sampled)
+                avg = r["loop_ms"] / r["loop_launches"] * 1e-3
+                ach = algo / avg / 1e9
+                roof = dict(bound="hbm", kernel="CG loop launch (graph replay)", achieved=ach, peak=HBM_PEAK_GBS,
+                            unit="GB/s", frac=ach / HBM_PEAK_GBS, algo_bytes_per_launch=algo,
+                            avg_launch_us=1e6 * avg, launches=r["loop_launches"])
             out[name] = dict(value=steps * nrhs / r["seconds"], ms_per_step=1e3 * r["seconds"] / steps,
                              p50_ms=1e3 * statistics.median(r["lat"]), p99_ms=1e3 * pct(r["lat"], 0.99),
                              iters=[i["iters"] for i in r["info"]],
