@@ -1998,6 +1998,143 @@ k_trtri(const T *__restrict__ L, T *__restrict__ X, const long long *__restrict_
   }
 }
 
+// X = L^{-1} in two launches (the one-wave-per-block-column k_trtri above is the
+// fallback when a block column does not fit in LDS).
+//
+// First the inverse of every diagonal 16x16 block, X[R][R] = L[R][R]^{-1}, one
+// wave per (subdomain, block R), strict upper part zero.
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_trtri_diag(const T *__restrict__ L, T *__restrict__ X, const long long *__restrict__ koff,
+             const int *__restrict__ ni) {
+  const int k = blockIdx.x, R = blockIdx.y;
+  const int n = ni[k], nt = (n + 15) / 16;
+  if (R >= nt) return;
+  const T *Lk = L + koff[k];          // column-major
+  T *Xk = X + koff[k];                // row-major
+  __shared__ T D[16][17];
+  __shared__ T Y[16][17];
+  const int r0 = 16 * R, m = min(16, n - r0), lane = threadIdx.x;
+  for (int e = lane; e < 256; e += kWave) {
+    const int i = e % 16, j = e / 16;
+    D[i][j] = (i < m && j < m) ? Lk[(size_t)(r0 + j) * n + r0 + i] : T(i == j ? 1 : 0);
+  }
+  __syncthreads();
+  if (lane < 16) {
+    const int j = lane;               // column j of the inverse by forward substitution
+    for (int i = 0; i < 16; ++i) {
+      T v = T(i == j ? 1 : 0);
+      for (int q = j; q < i; ++q) v -= D[i][q] * Y[q][j];
+      Y[i][j] = i < j ? T(0) : v / D[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < 256; e += kWave) {
+    const int i = e / 16, j = e % 16;
+    if (i < m && j < m) Xk[(size_t)(r0 + i) * n + r0 + j] = Y[i][j];
+  }
+}
+
+// Then the blocks below the diagonal, one workgroup of four waves per
+// (subdomain, block column C):
+//   X[R][C] = -X[R][R] * sum_{C <= Q < R} L[R][Q] X[Q][C],   R = C+1, C+2, ...
+// The column's finished blocks stay in LDS (dynamic, tiles_max * 256 + 2048
+// elements), each in the B-operand order of the 16x16x4 product (element (i, j)
+// at ((i / 4) * 16 + j) * 4 + i % 4, so lane 16 g + c reads its four k-steps as
+// one vector).  Block Q's products belong to wave (Q - C) % 4, which is also
+// the wave that finishes block Q: it alone reads the block back, so one barrier
+// per block row (before the four partial sums are combined) is enough.  The
+// partial sums alternate between two LDS buffers by block-row parity.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_trtri_panel(const T *__restrict__ L, T *__restrict__ X, const long long *__restrict__ koff,
+              const int *__restrict__ ni) {
+  typedef typename Vec4<T>::type V4;
+  extern __shared__ double trtri_lds[];
+  T *Yp = reinterpret_cast<T *>(trtri_lds);          // [2][4 waves][16 x 16] partial sums
+  T *P = Yp + 2 * kWavesPerBlock * 256;              // finished blocks of the column
+  const int k = blockIdx.x, C = blockIdx.y;
+  const int n = ni[k], nt = (n + 15) / 16;
+  if (C >= nt - 1) return;
+  const T *Lk = L + koff[k];          // column-major
+  T *Xk = X + koff[k];                // row-major
+  const int lane = lane_id(), c = lane % 16, g = lane / 16, w = wave_id();
+  const int c0 = 16 * C;
+  for (int e = threadIdx.x; e < 256; e += kBlock) {      // block C is full (C < nt - 1)
+    const int i = e / 16, j = e % 16;
+    P[((i / 4) * 16 + j) * 4 + i % 4] = Xk[(size_t)(c0 + i) * n + c0 + j];
+  }
+  __syncthreads();
+  for (int R = C + 1; R < nt; ++R) {
+    const int r0 = 16 * R, row = r0 + c;
+    const bool rv = row < n;
+    const bool owner = w == (R - C) % kWavesPerBlock;
+    T dA[4];
+    if (owner) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = r0 + 4 * g + t;
+        dA[t] = (rv && col < n) ? Xk[(size_t)row * n + col] : T(0);
+      }
+    }
+    V4 acc0, acc1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc0[r] = acc1[r] = T(0);
+    int Q = C + w;
+    for (; Q + kWavesPerBlock < R; Q += 2 * kWavesPerBlock) {
+      const T *l0 = Lk + (size_t)(16 * Q + 4 * g) * n + row;
+      const T *l1 = l0 + (size_t)16 * kWavesPerBlock * n;
+      T a[8];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = rv ? l0[(size_t)t * n] : T(0);
+        a[4 + t] = rv ? l1[(size_t)t * n] : T(0);
+      }
+      const V4 b0 = *reinterpret_cast<const V4 *>(P + (Q - C) * 256 + 4 * lane);
+      const V4 b1 = *reinterpret_cast<const V4 *>(P + (Q + kWavesPerBlock - C) * 256 + 4 * lane);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc0 = mfma16x16x4(a[t], b0[t], acc0);
+        acc1 = mfma16x16x4(a[4 + t], b1[t], acc1);
+      }
+    }
+    if (Q < R) {
+      const T *l0 = Lk + (size_t)(16 * Q + 4 * g) * n + row;
+      T a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = rv ? l0[(size_t)t * n] : T(0);
+      const V4 b0 = *reinterpret_cast<const V4 *>(P + (Q - C) * 256 + 4 * lane);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc0 = mfma16x16x4(a[t], b0[t], acc0);
+    }
+    T *yw = Yp + (R & 1) * (kWavesPerBlock * 256) + w * 256;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yw[acc_row(T(0), g, r) * 16 + c] = acc0[r] + acc1[r];
+    __syncthreads();
+    if (owner) {
+      const T *y = Yp + (R & 1) * (kWavesPerBlock * 256);
+      V4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[r] = T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int o = (4 * g + t) * 16 + c;
+        const T b = (y[o] + y[256 + o]) + (y[512 + o] + y[768 + o]);
+        z = mfma16x16x4(dA[t], b, z);
+      }
+      T *pr = P + (R - C) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = acc_row(T(0), g, r);
+        const T v = -z[r];
+        pr[((i / 4) * 16 + c) * 4 + i % 4] = v;
+        if (r0 + i < n) Xk[(size_t)(r0 + i) * n + c0 + c] = v;
+      }
+    }
+  }
+}
+static_assert(kWavesPerBlock == 4, "k_trtri_panel combines four partial sums");
+
 // tiles[t] = (subdomain, I << 16 | J) for the output tiles I >= J of every block.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -2128,6 +2265,92 @@ k_schur_diag(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
     if (!(d > 0.0)) { *bad = j + 1; d = 1.0; }
     dinv[j] = 1.0 / d;
   }
+}
+
+// The same diagonal on the matrix cores.  With X_k = L_k^{-1} (K_II^k = L_k L_k^T),
+//   (K_GI^k (K_II^k)^{-1} K_IG^k)_jj = || X_k K_IG^k e_j ||^2,
+// so each subdomain contributes the column sums of squares of W_k = X_k K_IG^k.
+//
+// K_IG^k is packed densely into 16-column strips of 16x16 tiles, each tile in
+// the f64 16x16x4 B-operand order: element (row 16K + 4g + t, column 16J + c)
+// of strip J sits at ((J * nt + K) * 256) + (16 g + c) * 4 + t, so lane
+// l = 16 g + c reads its four k-steps of a tile as one 32-byte vector.
+__global__ void k_pack_strips(long long n, const double *__restrict__ val,
+                              const long long *__restrict__ pos, double *__restrict__ packed) {
+  for (long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x; a < n;
+       a += (long long)gridDim.x * blockDim.x)
+    atomicAdd(packed + pos[a], val[a]);      // repeated (row, column) entries add up
+}
+
+// One workgroup per strip item (k, J, K_first, K_last), the first and last row
+// tiles of strip J that hold nonzeros.  W's row tiles I < K_first are zero;
+// row tile I >= K_first sums X[I][K] V[K][J] over K_first <= K <= min(I, K_last)
+// (X is lower triangular).  The row tiles go round-robin to the waves; each
+// lane adds the squares of its accumulator rows, the lanes of one column and
+// then the waves are combined in a fixed order, so dloc[goff[k] + 16 J + c]
+// (column 16 J + c of subdomain k's local interface) has the same bits on
+// every run.  X in the factor's precision, W in FP64.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_schur_wsq(const T *__restrict__ X, const double *__restrict__ packed,
+            const long long *__restrict__ koff, const long long *__restrict__ voff,
+            const int *__restrict__ ni, const int *__restrict__ goff, const int4 *__restrict__ items,
+            double *__restrict__ dloc) {
+  __shared__ double part[kWavesPerBlock][16];
+  const int4 it = items[blockIdx.x];
+  const int k = it.x, J = it.y, kf = it.z, kl = it.w;
+  const int n = ni[k], nt = (n + 15) / 16;
+  const int lane = lane_id(), c = lane % 16, g = lane / 16, w = wave_id();
+  const T *Xk = X + koff[k];
+  const double *V = packed + voff[k] + (size_t)J * nt * 256 + 4 * lane;
+  double ssq = 0.0;
+  for (int I = kf + w; I < nt; I += kWavesPerBlock) {
+    const int row = 16 * I + c;
+    const T *xr = Xk + (size_t)(row < n ? row : 0) * n;
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int ke = I < kl ? I : kl;
+    for (int K = kf; K <= ke; ++K) {
+      const int q = 16 * K + 4 * g;
+      const dbl4 b = *reinterpret_cast<const dbl4 *>(V + (size_t)K * 256);
+      double a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = (row < n && q + t < n) ? (double)xr[q + t] : 0.0;
+      acc0 = mfma16x16x4(a[0], b[0], acc0);
+      acc1 = mfma16x16x4(a[1], b[1], acc1);
+      acc0 = mfma16x16x4(a[2], b[2], acc0);
+      acc1 = mfma16x16x4(a[3], b[3], acc1);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = acc0[r] + acc1[r];
+      ssq += v * v;
+    }
+  }
+  ssq += __shfl_xor(ssq, 16, kWave);
+  ssq += __shfl_xor(ssq, 32, kWave);
+  if (g == 0) part[w][c] = ssq;
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int t = threadIdx.x, jl = 16 * J + t;
+    if (jl < goff[k + 1] - goff[k]) dloc[goff[k] + jl] = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+  }
+}
+static_assert(kWavesPerBlock == 4, "k_schur_wsq combines four waves");
+
+// d_j = (K_GG)_jj - sum over the subdomains k next to interface dof j (in
+// subdomain order) of their contributions dloc[dent[e]], dptr[j] <= e < dptr[j+1].
+__global__ void k_schur_diag_sum(int nrows, const double *__restrict__ kgg_diag,
+                                 const int *__restrict__ dptr, const int *__restrict__ dent,
+                                 const double *__restrict__ dloc, double *__restrict__ diag,
+                                 double *__restrict__ dinv, int *__restrict__ bad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrows) return;
+  double s = 0.0;
+  for (int e = dptr[j]; e < dptr[j + 1]; ++e) s += dloc[dent[e]];
+  double d = kgg_diag[j] - s;
+  diag[j] = d;
+  if (!(d > 0.0)) { *bad = j + 1; d = 1.0; }
+  dinv[j] = 1.0 / d;
 }
 
 // FP64 -> FP32 copy (mixed-precision operators).

@@ -7,6 +7,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -76,6 +77,15 @@ struct dd_ctx {
   int n_rb = 0, *d_rb_first = nullptr;   // row blocks of kRB rows (never crossing subdomains)
   int n_gram = 0;                         // 16x16 lower output tiles of all K_II^{-1} blocks
   int2 *d_gram_tiles = nullptr;
+  // diag(S) on the matrix cores: K_IG^k packed into 16-column strips (positions
+  // of every K_IG entry), strip work items, per-subdomain local interface slots
+  // and, per interface dof, its slots in subdomain order
+  long long vpack = 0;
+  int nloc = 0, n_wsq = 0;
+  long long *d_vpos = nullptr, *d_voff = nullptr;
+  int *d_goff = nullptr, *d_dptr = nullptr, *d_dent = nullptr;
+  int4 *d_wsq_items = nullptr;
+  double *d_kgg_diag = nullptr;
   int *d_ni = nullptr, *d_ioff = nullptr, *d_rowsub = nullptr, *d_imap = nullptr,
       *d_gmap = nullptr;
   long long *d_koff = nullptr;
@@ -104,7 +114,9 @@ struct dd_ctx {
   int use_mfma = 1;
   int direction_kernel = 0;   // 1: keep p in memory, update it with its own kernel
   int classic_cg = 0;         // 1: four launches per CG iteration also where three would do
+  int old_trtri = 0;          // 1: L^{-1} by one wave per block column (no LDS panel)
   int num_cu = 0;
+  size_t max_lds = 65536;     // LDS bytes one workgroup may use
   unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
   long long spin_limit = 1ll << 20;
   int last_launch = DD_LAUNCH_KERNELS;
@@ -568,21 +580,60 @@ dd_status factor_impl(dd_ctx *c, int pi) {
     if (status[k])
       return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
                                      std::to_string(status[k] - 1));
+  HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream));
   if (c->n_sub == 0) {
     // no interiors: nothing to invert (S = K_GG)
   } else if (c->use_mfma) {
-    // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set)
+    // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set);
+    // diag(S) from the column sums of squares of X K_IG, also on MFMA
+    struct Tmp { std::vector<void *> p; ~Tmp() { for (void *q : p) (void)hipFree(q); } } tmp;
+    auto talloc = [&](void **q, size_t bytes) -> hipError_t {
+      hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 1));
+      if (e == hipSuccess) tmp.p.push_back(*q);
+      return e;
+    };
     T *X = nullptr;
-    HIPCHK(c, hipMalloc(&X, std::max<size_t>(n, 1) * sizeof(T)));
-    struct FreeX { T *p; ~FreeX() { (void)hipFree(p); } } fx{X};
-    dim3 gt(c->n_sub, (c->max_ni + 15) / 16);
-    hipLaunchKernelGGL((k_trtri<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
+    double *packed = nullptr, *dloc = nullptr;
+    HIPCHK(c, talloc((void **)&X, n * sizeof(T)));
+    if (c->n_gamma > 0) {
+      HIPCHK(c, talloc((void **)&packed, (size_t)c->vpack * sizeof(double)));
+      HIPCHK(c, talloc((void **)&dloc, (size_t)c->nloc * sizeof(double)));
+      HIPCHK(c, hipMemsetAsync(packed, 0, (size_t)c->vpack * sizeof(double), c->stream));
+      HIPCHK(c, hipMemsetAsync(dloc, 0, (size_t)c->nloc * sizeof(double), c->stream));
+      if (c->nnz_ig > 0)
+        hipLaunchKernelGGL(k_pack_strips, dim3(std::min<unsigned>(grid_for(c->nnz_ig, 256), 4096)), dim3(256), 0,
+                           c->stream, (long long)c->nnz_ig, c->d_ig_val64, c->d_vpos, packed);
+      HIPCHK(c, hipGetLastError());
+    }
+    const int ntmax = (c->max_ni + 15) / 16;
+    dim3 gt(c->n_sub, ntmax);
+    const size_t lds = ((size_t)ntmax * 256 + 2 * kWavesPerBlock * 256) * sizeof(T);
+    if (lds <= c->max_lds && !c->old_trtri) {
+      hipLaunchKernelGGL((k_trtri_diag<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
+      HIPCHK(c, hipGetLastError());
+      if (ntmax > 1) {
+        HIPCHK(c, hipFuncSetAttribute((const void *)k_trtri_panel<T>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((k_trtri_panel<T>), dim3(c->n_sub, ntmax - 1), dim3(kBlock), lds, c->stream,
+                           (const T *)L, X, c->d_koff, c->d_ni);
+      }
+    } else {
+      hipLaunchKernelGGL((k_trtri<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
+    }
     HIPCHK(c, hipGetLastError());
     if (c->n_gram > 0)
       hipLaunchKernelGGL((k_gram<T>), dim3(grid_for(c->n_gram, kWavesPerBlock)), dim3(kBlock), 0, c->stream,
                          (const T *)X, Kinv, c->d_koff, c->d_ni, c->d_gram_tiles, c->n_gram);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipStreamSynchronize(c->stream));     // X is freed on return
+    if (c->n_gamma > 0) {
+      if (c->n_wsq > 0)
+        hipLaunchKernelGGL((k_schur_wsq<T>), dim3(c->n_wsq), dim3(kBlock), 0, c->stream, (const T *)X, packed,
+                           c->d_koff, c->d_voff, c->d_ni, c->d_goff, c->d_wsq_items, dloc);
+      hipLaunchKernelGGL(k_schur_diag_sum, dim3(grid_for(c->n_gamma, 256)), dim3(256), 0, c->stream,
+                         c->n_gamma, c->d_kgg_diag, c->d_dptr, c->d_dent, dloc, o.diag, o.dinv, c->d_bad);
+      HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));     // the temporaries are freed on return
   } else {
     dim3 ginv(c->n_sub, (c->max_ni + kInvCols - 1) / kInvCols);
     hipLaunchKernelGGL((k_inverse<T>), ginv, dim3(kBlock), 0, c->stream, (const T *)L, Kinv,
@@ -599,8 +650,7 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                        (float *)o.g_val);
     HIPCHK(c, hipGetLastError());
   }
-  HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream));
-  if (c->n_gamma > 0)
+  if (c->n_gamma > 0 && !(c->n_sub > 0 && c->use_mfma))
     hipLaunchKernelGGL((k_schur_diag<T>), dim3(grid_for(c->n_gamma, kWavesPerBlock)), dim3(kBlock),
                        0, c->stream, c->n_gamma, c->d_g_ptr, c->d_g_split, c->d_g_col,
                        c->d_g_val64, (const T *)Kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub,
@@ -1064,9 +1114,13 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if (const char *e = getenv("DD_NO_MFMA")) c->use_mfma = atoi(e) ? 0 : 1;
   if (const char *e = getenv("DD_DIRECTION_KERNEL")) c->direction_kernel = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_CLASSIC_CG")) c->classic_cg = atoi(e) ? 1 : 0;
+  if (const char *e = getenv("DD_BLOCKWAVE_TRTRI")) c->old_trtri = atoi(e) ? 1 : 0;
   {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+      c->num_cu = prop.multiProcessorCount;
+      c->max_lds = prop.sharedMemPerBlock;
+    }
     if (c->num_cu <= 0) c->num_cu = 1;
   }
   // host-side structure
@@ -1144,6 +1198,51 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     }
     c->n_gram = (int)gt.size();
     if ((s = upload(c, &c->d_gram_tiles, gt.data(), gt.size())) != DD_OK) return bail(s);
+  }
+  {
+    std::vector<long long> voff(c->n_sub + 1, 0), vpos;
+    std::vector<int> goff(c->n_sub + 1, 0);
+    std::vector<int4> items;
+    vpos.reserve(igval.size());
+    for (int k = 0; k < c->n_sub; ++k) {
+      const dd_subdomain &sd = p->sub[k];
+      const int nt = (sd.n_i + 15) / 16, ns = (sd.n_g + 15) / 16;
+      voff[k + 1] = voff[k] + (long long)nt * ns * 256;
+      goff[k + 1] = goff[k] + sd.n_g;
+      std::vector<int> kf(ns, INT_MAX), kl(ns, -1);
+      for (int i = 0; i < sd.n_i; ++i)
+        for (int a = sd.kig_rowptr[i]; a < sd.kig_rowptr[i + 1]; ++a) {
+          const int jl = sd.kig_col[a], J = jl / 16, K = i / 16;
+          kf[J] = std::min(kf[J], K);
+          kl[J] = std::max(kl[J], K);
+          vpos.push_back(voff[k] + ((long long)J * nt + K) * 256 + ((i % 16) / 4 * 16 + jl % 16) * 4 + i % 4);
+        }
+      for (int J = 0; J < ns; ++J)
+        if (kl[J] >= 0) items.push_back(make_int4(k, J, kf[J], kl[J]));
+    }
+    std::vector<int> dptr(c->n_gamma + 1, 0), dent(goff[c->n_sub]);
+    for (int k = 0; k < c->n_sub; ++k)
+      for (int jl = 0; jl < p->sub[k].n_g; ++jl) ++dptr[p->sub[k].g_map[jl] + 1];
+    for (int j = 0; j < c->n_gamma; ++j) dptr[j + 1] += dptr[j];
+    {
+      std::vector<int> fill(dptr.begin(), dptr.end() - 1);
+      for (int k = 0; k < c->n_sub; ++k)
+        for (int jl = 0; jl < p->sub[k].n_g; ++jl) dent[fill[p->sub[k].g_map[jl]]++] = goff[k] + jl;
+    }
+    std::vector<double> kd(c->n_gamma, 0.0);
+    for (int j = 0; j < c->n_gamma; ++j)
+      for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a)
+        if (p->kgg_col[a] == j) kd[j] += p->kgg_val[a];
+    c->vpack = voff[c->n_sub];
+    c->nloc = goff[c->n_sub];
+    c->n_wsq = (int)items.size();
+    if ((s = upload(c, &c->d_vpos, vpos.data(), vpos.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_voff, voff.data(), voff.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_goff, goff.data(), goff.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_wsq_items, items.data(), items.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_dptr, dptr.data(), dptr.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_dent, dent.data(), dent.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_kgg_diag, kd.data(), kd.size())) != DD_OK) return bail(s);
   }
   if ((s = upload(c, &c->d_imap, imap.data(), NI)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_gmap, p->gamma_map, c->n_gamma)) != DD_OK) return bail(s);

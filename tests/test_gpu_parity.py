@@ -70,7 +70,8 @@ def test_factor_parity(name, prec):
 
 
 def test_factor_vector_vs_mfma(monkeypatch):
-    """The MFMA trailing update and the vector-FMA one give the same factor."""
+    """The MFMA trailing update and the vector-FMA one give the same factor,
+    and the two formulations of diag(S) agree."""
     dd = _dd()
     wl, _, _ = problem("2d-const-3x2")
     print("case factor mfma/vector", flush=True)
@@ -82,8 +83,34 @@ def test_factor_vector_vs_mfma(monkeypatch):
     for k in range(wl.dd.n_sub):
         a, b = s1.factor_block(k), s2.factor_block(k)
         assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    # diag(S): column sums of squares of L^-1 K_IG (matrix cores) against the
+    # quadratic forms with K_II^-1 (vector path)
+    d1, d2 = s1.schur_diag(dd.DD_FP64), s2.schur_diag(dd.DD_FP64)
+    assert np.abs(d1 - d2).max() <= 1e-13 * np.abs(d2).max()
     s1.close()
     s2.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_inverse_factor_panel_vs_blockwave(monkeypatch, prec):
+    """L^-1 by LDS-resident block columns (four waves, inverted diagonal blocks)
+    and by one wave per block column give the same diag(S) and solution."""
+    dd = _dd()
+    wl, b, _ = problem("2d-pd")
+    print(f"case trtri panel/blockwave prec={prec}", flush=True)
+    opts = dd.dd_default_opts(tol=1e-12)
+    out = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("DD_BLOCKWAVE_TRTRI", env)
+        s = dd.Solver(wl.dd, max_nrhs=b.shape[1])
+        s.factor(prec)
+        u = s.solve(torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda:0"), prec=prec, opts=opts).u
+        out.append((s.schur_diag(prec), u.cpu().numpy()))
+        s.close()
+    (d1, u1), (d2, u2) = out
+    tol = 1e-13 if prec == dd.DD_FP64 else 1e-5
+    assert np.abs(d1 - d2).max() <= tol * np.abs(d2).max()
+    assert np.abs(u1 - u2).max() <= 1e-10 * np.abs(u2).max()
 
 
 @pytest.mark.parametrize("name", list(SMALL))
