@@ -1861,6 +1861,201 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
   }
 }
 
+// The whole factorisation in one launch, left-looking by 16-wide block columns:
+// one workgroup per (subdomain k, block column J) computes
+//   A[J:, J] -= sum_{Q < J} L[J:, Q] L[J, Q]^T,   L[J][J] = chol(A[J][J]),
+//   L[I][J] = A[I][J] L[J][J]^{-T}  (I > J),
+// the last step as the MFMA product L[I][J]^T = L[J][J]^{-1} A[I][J]^T with the
+// inverted diagonal block (which is also X[J][J] of X = L^{-1}, written to Xd
+// when given, row-major).  Wave w keeps its row tiles I = J + w + 4m,
+// m < OWN, in accumulator registers across the whole sum.
+//
+// Workgroups take tickets t = J * n_sub + k in the order they start, so a
+// workgroup only ever waits for block columns of smaller tickets, which have
+// already started: the waits cannot deadlock whatever the residency.  A
+// finished block column is written with device-coherent stores, waited for
+// (vmcnt 0) and published in done[k * ntmax + J]; readers poll the flags with
+// device-coherent loads (64 flags per poll) and read the columns the same way,
+// so no cache write-back or invalidate is involved.  Every poll is bounded:
+// after kFlowSpin sleeps the wave raises *timeout and stops waiting, so the
+// launch always drains (the factor is then garbage and the host reports it).
+// A non-positive pivot raises status[k] = column + 1 unless a smaller column
+// of the same subdomain already did (those finished before this one waited).
+constexpr int kFlowSpin = 1 << 18;
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_coherent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T, int OWN>
+__global__ void __launch_bounds__(kBlock)
+k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const int *__restrict__ ni,
+             int n_sub, int ntmax, int *__restrict__ status, unsigned *__restrict__ ticket,
+             int *__restrict__ done, int *__restrict__ timeout, T *__restrict__ Xd) {
+  typedef typename Vec4<T>::type V4;
+  __shared__ int s_ticket;
+  __shared__ T D[16][17];                    // diagonal block, then its factor
+  __shared__ T Di[16][17];                   // inverse of the factor's diagonal block
+  __shared__ T S[kWavesPerBlock][16][17];    // per-wave tile transpose
+  if (threadIdx.x == 0) s_ticket = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int k = s_ticket % n_sub, J = s_ticket / n_sub;
+  const int n = ni[k], nt = (n + 15) / 16;
+  if (J >= nt) return;
+  T *A = blocks + koff[k];                   // column-major: A[i][j] at j * n + i
+  int *dk = done + (size_t)k * ntmax;
+  const int lane = lane_id(), c = lane % 16, g = lane / 16, w = wave_id();
+  const int cj = 16 * J + c;
+  V4 acc[OWN];
+#pragma unroll
+  for (int m = 0; m < OWN; ++m) {
+    const int I = J + w + 4 * m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + acc_row(T(0), g, r);
+      acc[m][r] = (I < nt && row < n && cj < n) ? A[(size_t)cj * n + row] : T(0);
+    }
+  }
+  int avail = 0;                             // block columns known finished
+  bool waited_out = false;
+  for (int Q = 0; Q < J; ++Q) {
+    if (Q >= avail) {
+      unsigned long long fin = 0;
+      for (int it = 0;; ++it) {
+        const int f = (Q + lane < J) ? load_coherent(dk + Q + lane) : 0;
+        fin = __ballot(f != 0);
+        if ((fin & 1ull) || waited_out) break;
+        if (it >= kFlowSpin) {
+          waited_out = true;
+          if (lane == 0) store_coherent(timeout, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      avail = waited_out ? J : Q + (~fin == 0ull ? 64 : __builtin_ctzll(~fin));
+    }
+    const T *col = A + (size_t)(16 * Q + 4 * g) * n;
+    T b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) b[t] = cj < n ? load_coherent(col + (size_t)t * n + cj) : T(0);
+#pragma unroll
+    for (int m = 0; m < OWN; ++m) {
+      const int I = J + w + 4 * m;
+      if (I < nt) {
+        const int row = 16 * I + c;
+        T a[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = row < n ? -load_coherent(col + (size_t)t * n + row) : T(0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[m] = mfma16x16x4(a[t], b[t], acc[m]);
+      }
+    }
+  }
+  const int kb = min(16, n - 16 * J);
+  if (w == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) D[acc_row(T(0), g, r)][c] = acc[0][r];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // Cholesky of the diagonal block in registers: lane l < 16 holds row l;
+    // step j broadcasts the pivot and column j by shuffles.  Entries right of
+    // the diagonal become garbage and are never read.
+    T a[16], rd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = D[lane % 16][q];
+    int fail = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      rd[j] = T(1);                          // identity past the block's end
+      if (j < kb) {
+        T d = __shfl(a[j], j, kWave);
+        if (!(d > T(0))) {
+          if (fail == 0) fail = 16 * J + j + 1;
+          d = T(1);
+        }
+        const T piv = sqrt(d);
+        rd[j] = T(1) / piv;
+        if (lane == j) a[j] = piv;
+        else if (lane > j) a[j] *= rd[j];
+#pragma unroll
+        for (int m = j + 1; m < 16; ++m) {
+          const T lmj = __shfl(a[j], m, kWave);
+          if (lane > j) a[m] -= a[j] * lmj;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (lane < 16) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) D[lane][q] = q < lane ? a[q] : (q == lane && lane < kb ? a[q] : T(0));
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // column `lane` of the inverse by forward substitution (reciprocal pivots)
+    T y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      T v = T(i == lane ? 1 : 0);
+#pragma unroll
+      for (int q = 0; q < i; ++q) v -= D[i][q] * y[q];
+      y[i] = v * rd[i];
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Di[i][lane] = y[i];
+    }
+    if (fail && lane == 0 && load_coherent(status + k) == 0) store_coherent(status + k, fail);
+    for (int e = lane; e < 256; e += kWave) {
+      const int i = e % 16, j = e / 16;
+      if (i < kb && j < kb && i >= j) store_coherent(A + (size_t)(16 * J + j) * n + 16 * J + i, D[i][j]);
+    }
+  }
+  __syncthreads();
+  if (Xd && w == 0) {
+    T *Xk = Xd + koff[k];
+    for (int e = lane; e < 256; e += kWave) {
+      const int i = e / 16, j = e % 16;
+      if (i < kb && j < kb) Xk[(size_t)(16 * J + i) * n + 16 * J + j] = Di[i][j];
+    }
+  }
+  T da[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) da[t] = Di[c][4 * g + t];
+#pragma unroll
+  for (int m = 0; m < OWN; ++m) {
+    const int I = J + w + 4 * m;
+    if (I > J && I < nt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S[w][acc_row(T(0), g, r)][c] = acc[m][r];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      T bt[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bt[t] = S[w][c][4 * g + t];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      V4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[r] = T(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) z = mfma16x16x4(da[t], bt[t], z);
+      const int row = 16 * I + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int colj = 16 * J + acc_row(T(0), g, r);
+        if (row < n && colj < n) store_coherent(A + (size_t)colj * n + row, z[r]);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0): this thread's stores are done
+  __syncthreads();
+  if (threadIdx.x == 0) store_coherent(dk + J, 1);
+}
+
 // Trailing update of panel J: A22 -= L21 L21^T on the 16x16 lower tiles of
 // every subdomain; grid (tile chunks, subdomains), one wave per tile.
 template <typename T>

@@ -115,6 +115,8 @@ struct dd_ctx {
   int direction_kernel = 0;   // 1: keep p in memory, update it with its own kernel
   int classic_cg = 0;         // 1: four launches per CG iteration also where three would do
   int old_trtri = 0;          // 1: L^{-1} by one wave per block column (no LDS panel)
+  int panel_potrf = 0;        // 1: Cholesky by two launches per 16-wide panel
+  int *d_flow = nullptr;      // single-launch Cholesky: ticket, timeout, done flags
   int num_cu = 0;
   size_t max_lds = 65536;     // LDS bytes one workgroup may use
   unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
@@ -545,6 +547,30 @@ void launch_cg_dense(dd_ctx *c, const MT *kinv, int mode, int par, int ld, int n
 }
 
 // ---------------------------------------------------------------- factor --
+// Single-launch left-looking Cholesky for blocks of up to 16 * 4 * 16 rows
+// (row tiles per wave held in registers: the smallest OWN >= ceil(tiles / 4)).
+// Returns false (nothing launched) when the blocks are larger.
+template <typename T>
+bool launch_potrf_flow(dd_ctx *c, T *L, T *Xd) {
+  const int ntmax = (c->max_ni + 15) / 16, need = (ntmax + 3) / 4;
+  const dim3 grid((unsigned)(c->n_sub * ntmax)), blk(kBlock);
+  unsigned *ticket = (unsigned *)c->d_flow;
+  int *timeout = c->d_flow + 1, *done = c->d_flow + 2;
+#define DD_FLOW(OWN)                                                                                  \
+  hipLaunchKernelGGL((k_potrf_flow<T, OWN>), grid, blk, 0, c->stream, L, c->d_koff, c->d_ni, c->n_sub, \
+                     ntmax, c->d_status, ticket, done, timeout, Xd)
+  if (need <= 2) DD_FLOW(2);
+  else if (need <= 4) DD_FLOW(4);
+  else if (need <= 6) DD_FLOW(6);
+  else if (need <= 8) DD_FLOW(8);
+  else if (need <= 10) DD_FLOW(10);
+  else if (need <= 12) DD_FLOW(12);
+  else if (need <= 16) DD_FLOW(16);
+  else return false;
+#undef DD_FLOW
+  return true;
+}
+
 template <typename T>
 dd_status factor_impl(dd_ctx *c, int pi) {
   Ops &o = c->op[pi];
@@ -556,26 +582,50 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   else
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, n, c->d_kii64, (float *)L);
   HIPCHK(c, hipGetLastError());
-  // panel by panel: the diagonal block and the rows below it (one workgroup per
-  // subdomain), then the trailing update of all subdomains' tiles
+  // temporaries of the MFMA inverse path: X = L^{-1}, packed K_IG strips, diag(S) parts
+  struct Tmp { std::vector<void *> p; ~Tmp() { for (void *q : p) (void)hipFree(q); } } tmp;
+  auto talloc = [&](void **q, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 1));
+    if (e == hipSuccess) tmp.p.push_back(*q);
+    return e;
+  };
+  const bool mfma_inv = c->n_sub > 0 && c->use_mfma;
+  const int ntmax = (c->max_ni + 15) / 16;
+  const size_t trtri_lds = ((size_t)ntmax * 256 + 2 * kWavesPerBlock * 256) * sizeof(T);
+  const bool panel_trtri = trtri_lds <= c->max_lds && !c->old_trtri;
+  T *X = nullptr;
+  if (mfma_inv) HIPCHK(c, talloc((void **)&X, n * sizeof(T)));
   if (c->n_sub > 0) HIPCHK(c, hipMemsetAsync(c->d_status, 0, c->n_sub * sizeof(int), c->stream));
-  const int npanels = (c->max_ni + kNB - 1) / kNB;
-  for (int J = 0; J < npanels; ++J) {
-    hipLaunchKernelGGL((k_potrf_panel<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
-                       c->d_ni, c->d_status, J);
-    const int m = c->max_ni - kNB * (J + 1);
-    if (m > 0) {
-      const int t16 = (m + 15) / 16;
-      const int nt = t16 * (t16 + 1) / 2;
-      hipLaunchKernelGGL((k_potrf_update<T>), dim3(grid_for(nt, kWavesPerBlock), c->n_sub), dim3(kBlock), 0,
-                         c->stream, L, c->d_koff, c->d_ni, J, c->use_mfma);
+  bool flow = false;
+  if (c->use_mfma && c->n_sub > 0 && !c->panel_potrf) {
+    // one launch; it also writes the diagonal blocks of X
+    HIPCHK(c, hipMemsetAsync(c->d_flow, 0, (2 + (size_t)c->n_sub * ntmax) * sizeof(int), c->stream));
+    flow = launch_potrf_flow<T>(c, L, panel_trtri ? X : nullptr);
+    HIPCHK(c, hipGetLastError());
+  }
+  if (!flow) {
+    // panel by panel: the diagonal block and the rows below it (one workgroup per
+    // subdomain), then the trailing update of all subdomains' tiles
+    for (int J = 0; J < ntmax; ++J) {
+      hipLaunchKernelGGL((k_potrf_panel<T>), dim3(c->n_sub), dim3(kBlock), 0, c->stream, L, c->d_koff,
+                         c->d_ni, c->d_status, J);
+      const int m = c->max_ni - kNB * (J + 1);
+      if (m > 0) {
+        const int t16 = (m + 15) / 16;
+        const int nt = t16 * (t16 + 1) / 2;
+        hipLaunchKernelGGL((k_potrf_update<T>), dim3(grid_for(nt, kWavesPerBlock), c->n_sub), dim3(kBlock), 0,
+                           c->stream, L, c->d_koff, c->d_ni, J, c->use_mfma);
+      }
     }
   }
   HIPCHK(c, hipGetLastError());
   std::vector<int> status(c->n_sub);
+  int flow_timeout = 0;
   if (c->n_sub > 0)
     HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (flow) HIPCHK(c, hipMemcpyAsync(&flow_timeout, c->d_flow + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flow_timeout) return fail(c, DD_EHIP, "factorisation: a block column waited too long for its predecessors");
   for (int k = 0; k < c->n_sub; ++k)
     if (status[k])
       return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
@@ -586,15 +636,7 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   } else if (c->use_mfma) {
     // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set);
     // diag(S) from the column sums of squares of X K_IG, also on MFMA
-    struct Tmp { std::vector<void *> p; ~Tmp() { for (void *q : p) (void)hipFree(q); } } tmp;
-    auto talloc = [&](void **q, size_t bytes) -> hipError_t {
-      hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 1));
-      if (e == hipSuccess) tmp.p.push_back(*q);
-      return e;
-    };
-    T *X = nullptr;
     double *packed = nullptr, *dloc = nullptr;
-    HIPCHK(c, talloc((void **)&X, n * sizeof(T)));
     if (c->n_gamma > 0) {
       HIPCHK(c, talloc((void **)&packed, (size_t)c->vpack * sizeof(double)));
       HIPCHK(c, talloc((void **)&dloc, (size_t)c->nloc * sizeof(double)));
@@ -605,16 +647,15 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                            c->stream, (long long)c->nnz_ig, c->d_ig_val64, c->d_vpos, packed);
       HIPCHK(c, hipGetLastError());
     }
-    const int ntmax = (c->max_ni + 15) / 16;
     dim3 gt(c->n_sub, ntmax);
-    const size_t lds = ((size_t)ntmax * 256 + 2 * kWavesPerBlock * 256) * sizeof(T);
-    if (lds <= c->max_lds && !c->old_trtri) {
-      hipLaunchKernelGGL((k_trtri_diag<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
+    if (panel_trtri) {
+      if (!flow)      // the flow factorisation wrote the diagonal blocks already
+        hipLaunchKernelGGL((k_trtri_diag<T>), gt, dim3(kWave), 0, c->stream, (const T *)L, X, c->d_koff, c->d_ni);
       HIPCHK(c, hipGetLastError());
       if (ntmax > 1) {
         HIPCHK(c, hipFuncSetAttribute((const void *)k_trtri_panel<T>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL((k_trtri_panel<T>), dim3(c->n_sub, ntmax - 1), dim3(kBlock), lds, c->stream,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)trtri_lds));
+        hipLaunchKernelGGL((k_trtri_panel<T>), dim3(c->n_sub, ntmax - 1), dim3(kBlock), trtri_lds, c->stream,
                            (const T *)L, X, c->d_koff, c->d_ni);
       }
     } else {
@@ -1115,6 +1156,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if (const char *e = getenv("DD_DIRECTION_KERNEL")) c->direction_kernel = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_CLASSIC_CG")) c->classic_cg = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_BLOCKWAVE_TRTRI")) c->old_trtri = atoi(e) ? 1 : 0;
+  if (const char *e = getenv("DD_PANEL_POTRF")) c->panel_potrf = atoi(e) ? 1 : 0;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
@@ -1298,6 +1340,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   }
   if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_flow, 2 + (size_t)c->n_sub * ((c->max_ni + 15) / 16))) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->batch.d_mask, kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_solve_mask, kMaxLd)) != DD_OK) return bail(s);

@@ -92,6 +92,32 @@ def test_factor_vector_vs_mfma(monkeypatch):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_single_launch_cholesky_vs_panels(monkeypatch, prec):
+    """The one-launch left-looking Cholesky (block columns waiting on flags)
+    and the two-launches-per-panel right-looking one give the same factor,
+    diag(S) and solution, on blocks of uneven size."""
+    dd = _dd()
+    wl, b, _ = problem("2d-pd")
+    print(f"case cholesky flow/panels prec={prec}", flush=True)
+    opts = dd.dd_default_opts(tol=1e-12)
+    out = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("DD_PANEL_POTRF", env)
+        s = dd.Solver(wl.dd, max_nrhs=b.shape[1])
+        s.factor(prec)
+        u = s.solve(torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda:0"), prec=prec, opts=opts).u
+        out.append(([s.factor_block(k, prec) for k in range(wl.dd.n_sub)], s.schur_diag(prec),
+                    u.cpu().numpy()))
+        s.close()
+    (l1, d1, u1), (l2, d2, u2) = out
+    tol = 1e-13 if prec == dd.DD_FP64 else 1e-5
+    for a, c in zip(l1, l2):
+        assert np.abs(a - c).max() <= tol * np.abs(c).max()
+    assert np.abs(d1 - d2).max() <= tol * np.abs(d2).max()
+    assert np.abs(u1 - u2).max() <= 1e-10 * np.abs(u2).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_inverse_factor_panel_vs_blockwave(monkeypatch, prec):
     """L^-1 by LDS-resident block columns (four waves, inverted diagonal blocks)
     and by one wave per block column give the same diag(S) and solution."""
