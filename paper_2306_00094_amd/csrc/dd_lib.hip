@@ -117,6 +117,8 @@ struct dd_ctx {
   int old_trtri = 0;          // 1: L^{-1} by one wave per block column (no LDS panel)
   int panel_potrf = 0;        // 1: Cholesky by two launches per 16-wide panel
   int *d_flow = nullptr;      // single-launch Cholesky: ticket, timeout, done flags
+  double *fac_x = nullptr, *fac_packed = nullptr, *fac_dloc = nullptr;   // factor work space
+  bool packed_ready = false;
   int num_cu = 0;
   size_t max_lds = 65536;     // LDS bytes one workgroup may use
   unsigned *d_bar = nullptr;  // persistent-launch barrier: count, generation, abort
@@ -280,6 +282,11 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
                                    (std::max<size_t>(p->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
   b += 3 * chunks * kMaxLd * 8;
   b += (chunks / kPGroup + 1) * (kMaxLd * 8 + kCounterStride * 4);
+  if (p->n_sub > 0) {                     // factor work space: X, packed K_IG strips, diag(S) parts
+    b += kt * 8;
+    for (int k = 0; k < p->n_sub; ++k)
+      b += ((size_t)(p->sub[k].n_i + 15) / 16) * ((p->sub[k].n_g + 15) / 16) * 256 * 8 + p->sub[k].n_g * 8;
+  }
   return b;
 }
 
@@ -582,19 +589,22 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   else
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, n, c->d_kii64, (float *)L);
   HIPCHK(c, hipGetLastError());
-  // temporaries of the MFMA inverse path: X = L^{-1}, packed K_IG strips, diag(S) parts
-  struct Tmp { std::vector<void *> p; ~Tmp() { for (void *q : p) (void)hipFree(q); } } tmp;
-  auto talloc = [&](void **q, size_t bytes) -> hipError_t {
-    hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 1));
-    if (e == hipSuccess) tmp.p.push_back(*q);
-    return e;
-  };
+  // work space of the MFMA inverse path, kept for later factorisations: X = L^{-1}
+  // (FP64-sized, serves both precisions), K_IG packed into strips (packed once:
+  // the values do not change after setup), per-subdomain diag(S) parts
   const bool mfma_inv = c->n_sub > 0 && c->use_mfma;
   const int ntmax = (c->max_ni + 15) / 16;
   const size_t trtri_lds = ((size_t)ntmax * 256 + 2 * kWavesPerBlock * 256) * sizeof(T);
   const bool panel_trtri = trtri_lds <= c->max_lds && !c->old_trtri;
-  T *X = nullptr;
-  if (mfma_inv) HIPCHK(c, talloc((void **)&X, n * sizeof(T)));
+  if (mfma_inv && !c->fac_x) {
+    dd_status st;
+    if ((st = dalloc(c, &c->fac_x, n)) != DD_OK) return st;
+    if (c->n_gamma > 0) {
+      if ((st = dalloc(c, &c->fac_packed, (size_t)c->vpack)) != DD_OK) return st;
+      if ((st = dalloc(c, &c->fac_dloc, (size_t)c->nloc)) != DD_OK) return st;
+    }
+  }
+  T *X = mfma_inv ? (T *)c->fac_x : nullptr;
   if (c->n_sub > 0) HIPCHK(c, hipMemsetAsync(c->d_status, 0, c->n_sub * sizeof(int), c->stream));
   bool flow = false;
   if (c->use_mfma && c->n_sub > 0 && !c->panel_potrf) {
@@ -619,33 +629,24 @@ dd_status factor_impl(dd_ctx *c, int pi) {
     }
   }
   HIPCHK(c, hipGetLastError());
-  std::vector<int> status(c->n_sub);
-  int flow_timeout = 0;
-  if (c->n_sub > 0)
-    HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  if (flow) HIPCHK(c, hipMemcpyAsync(&flow_timeout, c->d_flow + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (flow_timeout) return fail(c, DD_EHIP, "factorisation: a block column waited too long for its predecessors");
-  for (int k = 0; k < c->n_sub; ++k)
-    if (status[k])
-      return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
-                                     std::to_string(status[k] - 1));
+  // the pivots are checked once at the end (a failed pivot is replaced by 1, so
+  // the rest of the factorisation stays finite)
   HIPCHK(c, hipMemsetAsync(c->d_bad, 0, sizeof(int), c->stream));
   if (c->n_sub == 0) {
     // no interiors: nothing to invert (S = K_GG)
   } else if (c->use_mfma) {
     // K_II^{-1} = X^T X with X = L^{-1}, both steps on MFMA (X in a temporary block set);
     // diag(S) from the column sums of squares of X K_IG, also on MFMA
-    double *packed = nullptr, *dloc = nullptr;
-    if (c->n_gamma > 0) {
-      HIPCHK(c, talloc((void **)&packed, (size_t)c->vpack * sizeof(double)));
-      HIPCHK(c, talloc((void **)&dloc, (size_t)c->nloc * sizeof(double)));
+    double *packed = c->fac_packed, *dloc = c->fac_dloc;
+    if (c->n_gamma > 0 && !c->packed_ready) {
+      // strips without nonzeros keep zero parts (never written by k_schur_wsq)
       HIPCHK(c, hipMemsetAsync(packed, 0, (size_t)c->vpack * sizeof(double), c->stream));
       HIPCHK(c, hipMemsetAsync(dloc, 0, (size_t)c->nloc * sizeof(double), c->stream));
       if (c->nnz_ig > 0)
         hipLaunchKernelGGL(k_pack_strips, dim3(std::min<unsigned>(grid_for(c->nnz_ig, 256), 4096)), dim3(256), 0,
                            c->stream, (long long)c->nnz_ig, c->d_ig_val64, c->d_vpos, packed);
       HIPCHK(c, hipGetLastError());
+      c->packed_ready = true;
     }
     dim3 gt(c->n_sub, ntmax);
     if (panel_trtri) {
@@ -674,7 +675,6 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                          c->n_gamma, c->d_kgg_diag, c->d_dptr, c->d_dent, dloc, o.diag, o.dinv, c->d_bad);
       HIPCHK(c, hipGetLastError());
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));     // the temporaries are freed on return
   } else {
     dim3 ginv(c->n_sub, (c->max_ni + kInvCols - 1) / kInvCols);
     hipLaunchKernelGGL((k_inverse<T>), ginv, dim3(kBlock), 0, c->stream, (const T *)L, Kinv,
@@ -697,9 +697,18 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                        c->d_g_val64, (const T *)Kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub,
                        o.diag, o.dinv, c->d_bad);
   HIPCHK(c, hipGetLastError());
-  int bad = 0;
+  int bad = 0, flow_timeout = 0;
+  std::vector<int> status(c->n_sub);
+  if (c->n_sub > 0)
+    HIPCHK(c, hipMemcpyAsync(status.data(), c->d_status, c->n_sub * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (flow) HIPCHK(c, hipMemcpyAsync(&flow_timeout, c->d_flow + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&bad, c->d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flow_timeout) return fail(c, DD_EHIP, "factorisation: a block column waited too long for its predecessors");
+  for (int k = 0; k < c->n_sub; ++k)
+    if (status[k])
+      return fail(c, DD_ENOTSPD, "subdomain " + std::to_string(k) + " not SPD at column " +
+                                     std::to_string(status[k] - 1));
   if (bad)
     return fail(c, DD_ENOTSPD, "diag(S) not positive at interface row " + std::to_string(bad - 1));
   o.ready = true;
