@@ -1874,7 +1874,10 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
 // workgroup only ever waits for block columns of smaller tickets, which have
 // already started: the waits cannot deadlock whatever the residency.  A
 // finished block column is written with device-coherent stores, waited for
-// (vmcnt 0) and published in done[k * ntmax + J]; readers poll the flags with
+// (vmcnt 0) and published in done[k * ntmax + J]; its tile (J+1, J) is
+// published first in done[(n_sub + k) * ntmax + J], which is all the next
+// column's diagonal tile needs, so that column factors its diagonal block
+// while this one is still storing the rest.  Readers poll the flags with
 // device-coherent loads (64 flags per poll) and read the columns the same way,
 // so no cache write-back or invalidate is involved.  Every poll is bounded:
 // after kFlowSpin sleeps the wave raises *timeout and stops waiting, so the
@@ -1906,7 +1909,8 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
   const int n = ni[k], nt = (n + 15) / 16;
   if (J >= nt) return;
   T *A = blocks + koff[k];                   // column-major: A[i][j] at j * n + i
-  int *dk = done + (size_t)k * ntmax;
+  int *dk = done + (size_t)k * ntmax;                       // column finished
+  int *ek = done + (size_t)(n_sub + k) * ntmax;             // its first tile below the diagonal stored
   const int lane = lane_id(), c = lane % 16, g = lane / 16, w = wave_id();
   const int cj = 16 * J + c;
   V4 acc[OWN];
@@ -1919,24 +1923,27 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
       acc[m][r] = (I < nt && row < n && cj < n) ? A[(size_t)cj * n + row] : T(0);
     }
   }
+  // wait until block column Q is finished (flags polled 64 at a time), bounded
   int avail = 0;                             // block columns known finished
   bool waited_out = false;
-  for (int Q = 0; Q < J; ++Q) {
-    if (Q >= avail) {
-      unsigned long long fin = 0;
-      for (int it = 0;; ++it) {
-        const int f = (Q + lane < J) ? load_coherent(dk + Q + lane) : 0;
-        fin = __ballot(f != 0);
-        if ((fin & 1ull) || waited_out) break;
-        if (it >= kFlowSpin) {
-          waited_out = true;
-          if (lane == 0) store_coherent(timeout, 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+  auto wait_done = [&](int Q) {
+    if (Q < avail) return;
+    unsigned long long fin = 0;
+    for (int it = 0;; ++it) {
+      const int f = (Q + lane < J) ? load_coherent(dk + Q + lane) : 0;
+      fin = __ballot(f != 0);
+      if ((fin & 1ull) || waited_out) break;
+      if (it >= kFlowSpin) {
+        waited_out = true;
+        if (lane == 0) store_coherent(timeout, 1);
+        break;
       }
-      avail = waited_out ? J : Q + (~fin == 0ull ? 64 : __builtin_ctzll(~fin));
+      __builtin_amdgcn_s_sleep(2);
     }
+    avail = waited_out ? J : Q + (~fin == 0ull ? 64 : __builtin_ctzll(~fin));
+  };
+  // subtract L[I][Q] L[J][Q]^T from the row tiles m0 <= m < m1 of this wave
+  auto update = [&](int Q, int m0, int m1) {
     const T *col = A + (size_t)(16 * Q + 4 * g) * n;
     T b[4];
 #pragma unroll
@@ -1944,7 +1951,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
 #pragma unroll
     for (int m = 0; m < OWN; ++m) {
       const int I = J + w + 4 * m;
-      if (I < nt) {
+      if (m >= m0 && m < m1 && I < nt) {
         const int row = 16 * I + c;
         T a[4];
 #pragma unroll
@@ -1953,6 +1960,24 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
         for (int t = 0; t < 4; ++t) acc[m] = mfma16x16x4(a[t], b[t], acc[m]);
       }
     }
+  };
+  for (int Q = 0; Q + 1 < J; ++Q) {
+    wait_done(Q);
+    update(Q, 0, OWN);
+  }
+  if (J > 0 && w == 0) {
+    // the diagonal tile needs only tile (J, J-1) of the last column, which its
+    // owner publishes (early flag) before the rest of that column
+    for (int it = 0;; ++it) {
+      if (waited_out || load_coherent(ek + J - 1) != 0) break;
+      if (it >= kFlowSpin) {
+        waited_out = true;
+        if (lane == 0) store_coherent(timeout, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    update(J - 1, 0, 1);
   }
   const int kb = min(16, n - 16 * J);
   if (w == 0) {
@@ -2009,10 +2034,15 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
       for (int i = 0; i < 16; ++i) Di[i][lane] = y[i];
     }
     if (fail && lane == 0 && load_coherent(status + k) == 0) store_coherent(status + k, fail);
+    __builtin_amdgcn_s_waitcnt(0x0F70);      // status settled before this column's early flag
     for (int e = lane; e < 256; e += kWave) {
       const int i = e % 16, j = e / 16;
       if (i < kb && j < kb && i >= j) store_coherent(A + (size_t)(16 * J + j) * n + 16 * J + i, D[i][j]);
     }
+  }
+  if (J > 0) {                               // the rest of the last column's update
+    wait_done(J - 1);
+    update(J - 1, w == 0 ? 1 : 0, OWN);
   }
   __syncthreads();
   if (Xd && w == 0) {
@@ -2048,6 +2078,10 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
       for (int r = 0; r < 4; ++r) {
         const int colj = 16 * J + acc_row(T(0), g, r);
         if (row < n && colj < n) store_coherent(A + (size_t)colj * n + row, z[r]);
+      }
+      if (w == 1 && m == 0) {                // tile (J+1, J): early flag of this column
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        if (lane == 0) store_coherent(ek + J, 1);
       }
     }
   }
@@ -2478,7 +2512,7 @@ __global__ void k_pack_strips(long long n, const double *__restrict__ val,
 }
 
 // One workgroup per strip item (k, J, K_first, K_last), the first and last row
-// tiles of strip J that hold nonzeros.  W's row tiles I < K_first are zero;
+// tiles of strip J that hold nonzeros (k < 0: padding, nothing to do).  W's row tiles I < K_first are zero;
 // row tile I >= K_first sums X[I][K] V[K][J] over K_first <= K <= min(I, K_last)
 // (X is lower triangular).  The row tiles go round-robin to the waves; each
 // lane adds the squares of its accumulator rows, the lanes of one column and
@@ -2493,6 +2527,7 @@ k_schur_wsq(const T *__restrict__ X, const double *__restrict__ packed,
             double *__restrict__ dloc) {
   __shared__ double part[kWavesPerBlock][16];
   const int4 it = items[blockIdx.x];
+  if (it.x < 0) return;                      // padding of the XCD-interleaved item list
   const int k = it.x, J = it.y, kf = it.z, kl = it.w;
   const int n = ni[k], nt = (n + 15) / 16;
   const int lane = lane_id(), c = lane % 16, g = lane / 16, w = wave_id();

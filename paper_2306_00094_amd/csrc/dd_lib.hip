@@ -609,7 +609,7 @@ dd_status factor_impl(dd_ctx *c, int pi) {
   bool flow = false;
   if (c->use_mfma && c->n_sub > 0 && !c->panel_potrf) {
     // one launch; it also writes the diagonal blocks of X
-    HIPCHK(c, hipMemsetAsync(c->d_flow, 0, (2 + (size_t)c->n_sub * ntmax) * sizeof(int), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_flow, 0, (2 + 2 * (size_t)c->n_sub * ntmax) * sizeof(int), c->stream));
     flow = launch_potrf_flow<T>(c, L, panel_trtri ? X : nullptr);
     HIPCHK(c, hipGetLastError());
   }
@@ -1271,6 +1271,44 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
       for (int J = 0; J < ns; ++J)
         if (kl[J] >= 0) items.push_back(make_int4(k, J, kf[J], kl[J]));
     }
+    {
+      // Workgroup b runs on XCD b % 8 (round-robin dispatch), and each XCD has
+      // its own L2: give every subdomain's strips one XCD, so its X_k is cached
+      // once.  Subdomains go to XCDs by decreasing work (tile products), each to
+      // the least loaded; within an XCD the longest strips come first, and the
+      // XCD lists are interleaved (k = -1 pads a short list).
+      constexpr int kXcd = 8;
+      auto work = [&](const int4 &it) {
+        const int nt = (p->sub[it.x].n_i + 15) / 16;
+        long long w = 0;
+        for (int I = it.z; I < nt; ++I) w += std::min(I, it.w) - it.z + 1;
+        return w;
+      };
+      std::vector<long long> wk(c->n_sub, 0);
+      for (const int4 &it : items) wk[it.x] += work(it);
+      std::vector<int> order(c->n_sub);
+      for (int k = 0; k < c->n_sub; ++k) order[k] = k;
+      std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return wk[a2] > wk[b2]; });
+      std::vector<int> xcd_of(c->n_sub, 0);
+      long long load[kXcd] = {0};
+      for (int k : order) {
+        int x = 0;
+        for (int y = 1; y < kXcd; ++y)
+          if (load[y] < load[x]) x = y;
+        xcd_of[k] = x;
+        load[x] += wk[k];
+      }
+      std::vector<std::vector<int4>> bins(kXcd);
+      for (const int4 &it : items) bins[xcd_of[it.x]].push_back(it);
+      size_t len = 0;
+      for (auto &b : bins) {
+        std::stable_sort(b.begin(), b.end(), [&](const int4 &u, const int4 &v) { return work(u) > work(v); });
+        len = std::max(len, b.size());
+      }
+      items.clear();
+      for (size_t i = 0; i < len; ++i)
+        for (int x = 0; x < kXcd; ++x) items.push_back(i < bins[x].size() ? bins[x][i] : make_int4(-1, 0, 0, 0));
+    }
     std::vector<int> dptr(c->n_gamma + 1, 0), dent(goff[c->n_sub]);
     for (int k = 0; k < c->n_sub; ++k)
       for (int jl = 0; jl < p->sub[k].n_g; ++jl) ++dptr[p->sub[k].g_map[jl] + 1];
@@ -1349,7 +1387,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   }
   if ((s = dalloc(c, &c->red.counter, 8)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_status, c->n_sub)) != DD_OK) return bail(s);
-  if ((s = dalloc(c, &c->d_flow, 2 + (size_t)c->n_sub * ((c->max_ni + 15) / 16))) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_flow, 2 + 2 * (size_t)c->n_sub * ((c->max_ni + 15) / 16))) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_bar, 4)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->batch.d_mask, kMaxLd)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_solve_mask, kMaxLd)) != DD_OK) return bail(s);
