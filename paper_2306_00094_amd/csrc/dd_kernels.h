@@ -2378,21 +2378,31 @@ k_gram(const T *__restrict__ X, T *__restrict__ Kinv, const long long *__restric
   T *Kk = Kinv + koff[k];
   const int lane = lane_id(), ci = lane % 16, g = lane / 16;
   const int ia = 16 * I + ci, jb = 16 * J + ci;
-  typename Vec4<T>::type acc;
+  // four independent accumulators over rows r0, r0 + 4, r0 + 8, r0 + 12 (the
+  // loads of 16 rows go out together), summed in a fixed order at the end
+  typename Vec4<T>::type acc[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = T(0);
-  for (int r0 = 16 * I; r0 < n; r0 += 4) {
-    const int r = r0 + g;
-    const T a = (r < n && ia < n) ? Xk[(size_t)r * n + ia] : T(0);
-    const T b = (r < n && jb < n) ? Xk[(size_t)r * n + jb] : T(0);
-    acc = mfma16x16x4(a, b, acc);
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[u][r] = T(0);
+  for (int r0 = 16 * I; r0 < n; r0 += 16) {
+    T a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 4 * u + g;
+      a[u] = (r < n && ia < n) ? Xk[(size_t)r * n + ia] : T(0);
+      b[u] = (r < n && jb < n) ? Xk[(size_t)r * n + jb] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4(a[u], b[u], acc[u]);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
+    const T v = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
     const int i = 16 * I + acc_row(T(0), g, r), j = 16 * J + ci;
     if (i < n && j < n && (I > J || i >= j)) {
-      Kk[(size_t)j * n + i] = acc[r];
-      Kk[(size_t)i * n + j] = acc[r];
+      Kk[(size_t)j * n + i] = v;
+      Kk[(size_t)i * n + j] = v;
     }
   }
 }
@@ -2539,7 +2549,27 @@ k_schur_wsq(const T *__restrict__ X, const double *__restrict__ packed,
     const T *xr = Xk + (size_t)(row < n ? row : 0) * n;
     dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int ke = I < kl ? I : kl;
-    for (int K = kf; K <= ke; ++K) {
+    int K = kf;
+    for (; K + 1 <= ke; K += 2) {            // two row tiles per step: their loads go out together
+      const int q = 16 * K + 4 * g;
+      const dbl4 b0 = *reinterpret_cast<const dbl4 *>(V + (size_t)K * 256);
+      const dbl4 b1 = *reinterpret_cast<const dbl4 *>(V + (size_t)(K + 1) * 256);
+      double a[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int qt = q + (t < 4 ? t : 12 + t);
+        a[t] = (row < n && qt < n) ? (double)xr[qt] : 0.0;
+      }
+      acc0 = mfma16x16x4(a[0], b0[0], acc0);
+      acc1 = mfma16x16x4(a[1], b0[1], acc1);
+      acc0 = mfma16x16x4(a[2], b0[2], acc0);
+      acc1 = mfma16x16x4(a[3], b0[3], acc1);
+      acc0 = mfma16x16x4(a[4], b1[0], acc0);
+      acc1 = mfma16x16x4(a[5], b1[1], acc1);
+      acc0 = mfma16x16x4(a[6], b1[2], acc0);
+      acc1 = mfma16x16x4(a[7], b1[3], acc1);
+    }
+    if (K <= ke) {
       const int q = 16 * K + 4 * g;
       const dbl4 b = *reinterpret_cast<const dbl4 *>(V + (size_t)K * 256);
       double a[4];
