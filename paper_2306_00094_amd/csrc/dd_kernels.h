@@ -1880,8 +1880,9 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
 // while this one is still storing the rest.  Readers poll the flags with
 // device-coherent loads (64 flags per poll) and read the columns the same way,
 // so no cache write-back or invalidate is involved.  Every poll is bounded:
-// after kFlowSpin sleeps the wave raises *timeout and stops waiting, so the
-// launch always drains (the factor is then garbage and the host reports it).
+// after `spin` sleeps (kFlowSpin unless the host sets a smaller limit) the wave
+// raises *timeout and stops waiting, so the launch always drains (the factor
+// is then garbage and the host reports it).
 // A non-positive pivot raises status[k] = column + 1 unless a smaller column
 // of the same subdomain already did (those finished before this one waited).
 constexpr int kFlowSpin = 1 << 18;
@@ -1897,7 +1898,7 @@ template <typename T, int OWN>
 __global__ void __launch_bounds__(kBlock)
 k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const int *__restrict__ ni,
              int n_sub, int ntmax, int *__restrict__ status, unsigned *__restrict__ ticket,
-             int *__restrict__ done, int *__restrict__ timeout, T *__restrict__ Xd) {
+             int *__restrict__ done, int *__restrict__ timeout, T *__restrict__ Xd, int spin) {
   typedef typename Vec4<T>::type V4;
   __shared__ int s_ticket;
   __shared__ T D[16][17];                    // diagonal block, then its factor
@@ -1933,7 +1934,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
       const int f = (Q + lane < J) ? load_coherent(dk + Q + lane) : 0;
       fin = __ballot(f != 0);
       if ((fin & 1ull) || waited_out) break;
-      if (it >= kFlowSpin) {
+      if (it >= spin) {
         waited_out = true;
         if (lane == 0) store_coherent(timeout, 1);
         break;
@@ -1970,7 +1971,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
     // owner publishes (early flag) before the rest of that column
     for (int it = 0;; ++it) {
       if (waited_out || load_coherent(ek + J - 1) != 0) break;
-      if (it >= kFlowSpin) {
+      if (it >= spin) {
         waited_out = true;
         if (lane == 0) store_coherent(timeout, 1);
         break;

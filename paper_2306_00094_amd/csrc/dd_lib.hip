@@ -116,6 +116,7 @@ struct dd_ctx {
   int classic_cg = 0;         // 1: four launches per CG iteration also where three would do
   int old_trtri = 0;          // 1: L^{-1} by one wave per block column (no LDS panel)
   int panel_potrf = 0;        // 1: Cholesky by two launches per 16-wide panel
+  int flow_spin = kFlowSpin;  // bound of each wait in the single-launch Cholesky (sleeps)
   int *d_flow = nullptr;      // single-launch Cholesky: ticket, timeout, done flags
   double *fac_x = nullptr, *fac_packed = nullptr, *fac_dloc = nullptr;   // factor work space
   bool packed_ready = false;
@@ -565,7 +566,7 @@ bool launch_potrf_flow(dd_ctx *c, T *L, T *Xd) {
   int *timeout = c->d_flow + 1, *done = c->d_flow + 2;
 #define DD_FLOW(OWN)                                                                                  \
   hipLaunchKernelGGL((k_potrf_flow<T, OWN>), grid, blk, 0, c->stream, L, c->d_koff, c->d_ni, c->n_sub, \
-                     ntmax, c->d_status, ticket, done, timeout, Xd)
+                     ntmax, c->d_status, ticket, done, timeout, Xd, c->flow_spin)
   if (need <= 2) DD_FLOW(2);
   else if (need <= 4) DD_FLOW(4);
   else if (need <= 6) DD_FLOW(6);
@@ -1166,6 +1167,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if (const char *e = getenv("DD_CLASSIC_CG")) c->classic_cg = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_BLOCKWAVE_TRTRI")) c->old_trtri = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_PANEL_POTRF")) c->panel_potrf = atoi(e) ? 1 : 0;
+  if (const char *e = getenv("DD_FLOW_SPIN")) c->flow_spin = std::max(0, std::min(atoi(e), kFlowSpin));
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {

@@ -69,6 +69,64 @@ def test_factor_parity(name, prec):
     s.close()
 
 
+# interior blocks past the sizes of the small cases: 853 rows (54 row tiles,
+# sixteen tiles per wave in the one-launch Cholesky) and 1138 rows (72 row
+# tiles: the per-panel Cholesky, and an L^-1 block column that just fills the
+# 160 KB of LDS in FP64)
+LARGE = {
+    "1d-853": lambda: workloads.spec_1d(n=1800, strips=2, nrhs=1),
+    "1d-1138": lambda: workloads.spec_1d(n=2400, strips=2, nrhs=1),
+}
+
+
+@pytest.mark.parametrize("name", list(LARGE))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_factor_large_blocks(name, prec):
+    dd = _dd()
+    spec = LARGE[name]()
+    wl = workloads.build(spec)
+    b = workloads.rhs(spec)
+    print(f"case factor large {name} prec={prec} n_i={[k.shape[0] for k in wl.dd.kii]}", flush=True)
+    s = dd.Solver(wl.dd, max_nrhs=1)
+    s.factor(prec)
+    tol = 1e-12 if prec == dd.DD_FP64 else 2e-5
+    for k in range(wl.dd.n_sub):
+        L_ref = np.linalg.cholesky(wl.dd.kii[k])
+        L = s.factor_block(k, prec)
+        err = np.abs(L - L_ref).max() / np.abs(L_ref).max()
+        assert err <= tol, (k, err)
+    d_ref = oracle.DDOracle(wl.dd).schur_diag()
+    derr = np.abs(s.schur_diag(prec) - d_ref).max() / np.abs(d_ref).max()
+    assert derr <= (1e-12 if prec == dd.DD_FP64 else 1e-4), derr
+    res = s.solve(to_dev(b), prec=prec, opts=dd.dd_default_opts(tol=1e-12))
+    uref = oracle.monolithic_solve(wl.asm.A, b)
+    err = oracle.rel_err(res.u.cpu().numpy().T, uref).max()
+    assert err <= (1e-10 if prec == dd.DD_FP64 else 1e-8), err
+    s.close()
+
+
+def test_single_launch_cholesky_wait_bound(monkeypatch):
+    """With the wait bound forced to zero from the host, block columns give up
+    at once on predecessors that are still running: the launch still drains
+    and dd_factor reports DD_EHIP instead of returning a factor.  A context
+    with the normal bound then factors and solves correctly."""
+    dd = _dd()
+    wl, b, uref = problem("2d-const")
+    print("case cholesky wait bound", flush=True)
+    monkeypatch.setenv("DD_FLOW_SPIN", "0")
+    s = dd.Solver(wl.dd, max_nrhs=b.shape[1])
+    with pytest.raises(dd.DDError) as ei:
+        s.factor(dd.DD_FP64)
+    assert ei.value.status == dd.DD_EHIP and "waited too long" in str(ei.value)
+    s.close()
+    monkeypatch.delenv("DD_FLOW_SPIN")
+    s = dd.Solver(wl.dd, max_nrhs=b.shape[1])
+    s.factor(dd.DD_FP64)
+    res = s.solve(to_dev(b), prec=dd.DD_FP64, opts=dd.dd_default_opts(tol=1e-12))
+    assert oracle.rel_err(res.u.cpu().numpy().T, uref).max() <= 1e-10
+    s.close()
+
+
 def test_factor_vector_vs_mfma(monkeypatch):
     """The MFMA trailing update and the vector-FMA one give the same factor,
     and the two formulations of diag(S) agree."""
