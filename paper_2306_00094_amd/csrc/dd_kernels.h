@@ -1886,6 +1886,16 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
 // A non-positive pivot raises status[k] = column + 1 unless a smaller column
 // of the same subdomain already did (those finished before this one waited).
 constexpr int kFlowSpin = 1 << 18;
+// Value of v in lane l (l uniform) as a wave-uniform scalar.
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float bcast_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 template <typename T>
 __device__ __forceinline__ T load_coherent(const T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1987,7 +1997,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     // Cholesky of the diagonal block in registers: lane l < 16 holds row l;
-    // step j broadcasts the pivot and column j by shuffles.  Entries right of
+    // step j broadcasts the pivot and column j lane by lane (v_readlane).  Entries right of
     // the diagonal become garbage and are never read.
     T a[16], rd[16];
 #pragma unroll
@@ -1997,7 +2007,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
     for (int j = 0; j < 16; ++j) {
       rd[j] = T(1);                          // identity past the block's end
       if (j < kb) {
-        T d = __shfl(a[j], j, kWave);
+        T d = bcast_lane(a[j], j);
         if (!(d > T(0))) {
           if (fail == 0) fail = 16 * J + j + 1;
           d = T(1);
@@ -2008,7 +2018,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
         else if (lane > j) a[j] *= rd[j];
 #pragma unroll
         for (int m = j + 1; m < 16; ++m) {
-          const T lmj = __shfl(a[j], m, kWave);
+          const T lmj = bcast_lane(a[j], m);
           if (lane > j) a[m] -= a[j] * lmj;
         }
       }
@@ -2035,7 +2045,6 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
       for (int i = 0; i < 16; ++i) Di[i][lane] = y[i];
     }
     if (fail && lane == 0 && load_coherent(status + k) == 0) store_coherent(status + k, fail);
-    __builtin_amdgcn_s_waitcnt(0x0F70);      // status settled before this column's early flag
     for (int e = lane; e < 256; e += kWave) {
       const int i = e % 16, j = e / 16;
       if (i < kb && j < kb && i >= j) store_coherent(A + (size_t)(16 * J + j) * n + 16 * J + i, D[i][j]);
@@ -2045,6 +2054,7 @@ k_potrf_flow(T *__restrict__ blocks, const long long *__restrict__ koff, const i
     wait_done(J - 1);
     update(J - 1, w == 0 ? 1 : 0, OWN);
   }
+  if (w == 0) __builtin_amdgcn_s_waitcnt(0x0F70);   // the status store settles before the early flag
   __syncthreads();
   if (Xd && w == 0) {
     T *Xk = Xd + koff[k];
