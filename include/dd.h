@@ -153,7 +153,12 @@ dd_status dd_setup(const dd_problem *prob, void *hip_stream, int32_t max_nrhs,
 /* Factor every K_II^k (batched Cholesky), form the interior-solve operators
  * and the exact diag(S) preconditioner in precision `prec`.  May be called
  * again with the other precision; both sets of factors are then kept.
- * DD_ENOTSPD names the subdomain and column of the first failed pivot. */
+ * DD_ENOTSPD names the subdomain and column of the first failed pivot, or the
+ * interface row whose diag(S) entry is not positive.  DD_EHIP also covers a
+ * block column of the one-launch Cholesky whose bounded wait for the columns
+ * before it ran out (the factors are then not usable).  The first call
+ * allocates the work space of the inverse and of diag(S) (counted by
+ * dd_footprint); later calls reuse it. */
 dd_status dd_factor(dd_ctx *ctx, dd_precision prec);
 
 /* Solve A u = b for nrhs columns.  b_dev and u_dev: D, column-major n_dof x
