@@ -576,6 +576,9 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
              RedBuf red, ColState st, const double *__restrict__ dinv,
              double *__restrict__ qd) {
   constexpr int RPW = kWave / G, CH = NW * RPW;
+  // three-launch iteration (qd given): nothing to do once every column stopped
+  // (st.flag[1], written by the interior-solve launch just before)
+  if (qd && st.flag[1] == 0) return;
   __shared__ double prod[CH * kMaxLd];
   const int wv = wave_id(), lane = lane_id();
   const int jl = wv * RPW + lane / G;          // row within the chunk
@@ -925,6 +928,10 @@ __global__ void __launch_bounds__(kBlock)
 k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
          const int *__restrict__ col, const VT *__restrict__ val, int nG, int ld, CgVec v,
          double *__restrict__ y, RedBuf red, ColState st, const int *__restrict__ mask, int npq) {
+  // every column stopped at the previous iteration (st.flag[1], written by its
+  // K2): nothing to update or apply (an iteration launched ahead of the host's
+  // convergence check)
+  if (mode == 1 && st.flag[1] == 0) return;
   __shared__ double salpha[kMaxLd];
   __shared__ int supd[kMaxLd];
   __shared__ double lds[kRowsE * 4 * E];
@@ -1197,6 +1204,11 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
            const int *__restrict__ rowsub, const double *__restrict__ y, int ld, double *__restrict__ w,
            int nG, int nrhs, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
            ColState st, const int *__restrict__ mask, int *__restrict__ host_nact) {
+  if (mode == 1 && st.flag[1] == 0) {       // every column stopped (see k_cg_kig)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
+      __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
   __shared__ double sbeta[kMaxLd];
   __shared__ int sinit[kMaxLd];
   __shared__ int scnt[kMaxLd];
@@ -1301,6 +1313,11 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
               const double *__restrict__ y, int ld, double *__restrict__ w, int nG, int nrhs,
               const double *__restrict__ z, double *__restrict__ p, RedBuf red, ColState st,
               const int *__restrict__ mask, int *__restrict__ host_nact) {
+  if (mode == 1 && st.flag[1] == 0) {       // every column stopped (see k_cg_kig)
+    if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
+      __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
   __shared__ double sbeta[kMaxLd];
   __shared__ int sinit[kMaxLd];
   __shared__ int scnt[kMaxLd];
