@@ -265,9 +265,13 @@ enum {
  * sample of the calls. */
 dd_status dd_set_timing(dd_ctx *ctx, uint32_t phase_mask, int32_t reset);
 
-/* Accumulated milliseconds and launch counts per phase since the last
- * the last reset (ms, launches: H, DD_NPHASES entries each).  Synchronises
- * the context's stream. */
+/* Accumulated milliseconds and launch counts per phase since the last reset
+ * (ms, launches: H, DD_NPHASES entries each).  DD_PHASE_GAMMA counts the
+ * interface-row launches that swept the matrix: in the three-launch iteration
+ * those of iterations 0 .. K-1 (K the largest iteration count of the solve's
+ * columns), not the launches that returned at once because every column had
+ * stopped (an iteration enqueued ahead of the convergence check).
+ * Synchronises the context's stream. */
 dd_status dd_get_timing(dd_ctx *ctx, double *ms, int64_t *launches);
 
 /* Last error message of ctx (or of the last failed dd_setup when ctx is NULL).

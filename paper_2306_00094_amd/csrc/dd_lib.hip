@@ -157,6 +157,7 @@ struct dd_ctx {
   std::vector<hipEvent_t> tev;          // event pool, pairs (start, stop)
   std::vector<int> tev_phase;           // phase of each recorded pair
   size_t tev_used = 0;
+  int tev_cg3_ld = 0;                   // recorded pairs come from a three-launch CG loop of this width
   double t_ms[DD_NPHASES] = {0};
   long long t_count[DD_NPHASES] = {0};
   std::string err;
@@ -769,13 +770,29 @@ struct PhaseTimer {
   }
 };
 
-// Accumulate the recorded pairs (the stream must be idle).
-void collect_timing(dd_ctx *c) {
+// Accumulate the recorded pairs (the stream must be idle).  When the pairs
+// come from a three-launch CG loop (tev_cg3_ld > 0; h holds its final column
+// state), its interface-row launches that swept the matrix are those of
+// iterations 0 .. K-1, K the largest iteration count of its columns: the launch
+// of iteration K and those enqueued after it return at once (every column had
+// stopped) and are left out.
+void collect_timing(dd_ctx *c, const StateBlock *h) {
+  long keep_gamma = -1;                  // < 0: every interface-row pair counts
+  if (c->tev_cg3_ld > 0 && h) {
+    keep_gamma = 0;
+    for (int j = 0; j < c->tev_cg3_ld; ++j) keep_gamma = std::max<long>(keep_gamma, h->iters[j]);
+  }
+  c->tev_cg3_ld = 0;
   for (size_t i = 0; i + 1 < c->tev_used; i += 2) {
+    const int ph = c->tev_phase[i / 2];
+    if (ph == DD_PHASE_GAMMA && keep_gamma >= 0) {
+      if (keep_gamma == 0) continue;
+      --keep_gamma;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->tev[i], c->tev[i + 1]) == hipSuccess) {
-      c->t_ms[c->tev_phase[i / 2]] += ms;
-      c->t_count[c->tev_phase[i / 2]] += 1;
+      c->t_ms[ph] += ms;
+      c->t_count[ph] += 1;
     }
   }
   c->tev_used = 0;
@@ -880,6 +897,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // rows, update), which the persistent kernel also runs.
   const bool cg3 = o.cg3 && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
                    o.launch != DD_LAUNCH_PERSISTENT && !c->classic_cg;
+  c->tev_cg3_ld = cg3 ? ld : 0;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
   if (c->n_gamma == 0)            // no init kernel to clear the breakdown flag
@@ -1081,7 +1099,7 @@ inline double inner_stop2(double inner_tol, double tol, double rn2, double bn2) 
 dd_status fetch_state(dd_ctx *c, StateBlock *h) {
   HIPCHK(c, hipMemcpyAsync(h, c->d_state, sizeof(StateBlock), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->tev_used) collect_timing(c);
+  if (c->tev_used) collect_timing(c, h);
   if (h->flag[0]) return fail(c, DD_ENOTSPD, "CG breakdown: p^T S p <= 0");
   return DD_OK;
 }
@@ -1860,8 +1878,9 @@ dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask, int32_t reset) {
       c->t_count[i] = 0;
     }
   } else if (c->tev_used > 0) {       // keep what was recorded so far
+    HIPCHK(c, hipMemcpyAsync(c->h_state, c->d_state, sizeof(StateBlock), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    collect_timing(c);
+    collect_timing(c, c->h_state);
   }
   c->timing_mask = phase_mask & ((1u << DD_NPHASES) - 1u);
   return DD_OK;
@@ -1869,8 +1888,9 @@ dd_status dd_set_timing(dd_ctx *c, uint32_t phase_mask, int32_t reset) {
 
 dd_status dd_get_timing(dd_ctx *c, double *ms, int64_t *launches) {
   if (!c || !ms || !launches) return fail(c, DD_EINVAL, "NULL argument");
+  HIPCHK(c, hipMemcpyAsync(c->h_state, c->d_state, sizeof(StateBlock), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->tev_used) collect_timing(c);
+  if (c->tev_used) collect_timing(c, c->h_state);
   for (int i = 0; i < DD_NPHASES; ++i) {
     ms[i] = c->t_ms[i];
     launches[i] = c->t_count[i];

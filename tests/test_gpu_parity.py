@@ -127,6 +127,34 @@ def test_single_launch_cholesky_wait_bound(monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("lag", [1, 4])
+def test_interface_row_timing_counts_sweeps(lag):
+    """Phase timing of the interface-row launches counts the launches that
+    swept the matrix: iteration 0 and every iteration before the last (whose
+    interior-solve launch stops the column), not the launches enqueued after
+    the column stopped, which return at once.  The solution does not depend
+    on the polling lag."""
+    dd = _dd()
+    wl, b, uref = problem("2d-const")
+    print(f"case gamma timing lag={lag}", flush=True)
+    s = dd.Solver(wl.dd, max_nrhs=1)
+    s.factor(dd.DD_FP64)
+    bd = to_dev(b[:, :1])
+    o = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS, check_every=lag, apply=dd.DD_APPLY_INV)
+    ref = s.solve(bd, prec=dd.DD_FP64, opts=dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS,
+                                                                 check_every=1, apply=dd.DD_APPLY_INV))
+    dd.dd_set_timing(s.ctx, 1 << dd.DD_PHASE_GAMMA, reset=True)
+    res = s.solve(bd, prec=dd.DD_FP64, opts=o)
+    ms, n = dd.dd_get_timing(s.ctx)
+    dd.dd_set_timing(s.ctx, 0)
+    its = res.info[0]["iters"]
+    print("  iters", its, "timed launches", n[dd.DD_PHASE_GAMMA], "ms", ms[dd.DD_PHASE_GAMMA], flush=True)
+    assert n[dd.DD_PHASE_GAMMA] == its
+    assert np.array_equal(res.u.cpu().numpy(), ref.u.cpu().numpy())
+    assert oracle.rel_err(res.u.cpu().numpy().T, uref[:, :1]).max() <= 1e-10
+    s.close()
+
+
 def test_factor_vector_vs_mfma(monkeypatch):
     """The MFMA trailing update and the vector-FMA one give the same factor,
     and the two formulations of diag(S) agree."""
