@@ -1211,41 +1211,50 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   c->NI = NI;
   c->ktot = kt;
   std::vector<int> rowsub(NI), imap(NI);
-  std::vector<double> kii(kt);
-  std::vector<int> igptr(NI + 1, 0), igcol;
-  std::vector<double> igval;
-  for (int k = 0; k < c->n_sub; ++k) {
-    const dd_subdomain &s = p->sub[k];
-    memcpy(&kii[c->koff[k]], s.k_ii, sizeof(double) * (size_t)s.n_i * s.n_i);
-    for (int i = 0; i < s.n_i; ++i) {
-      int r = c->ioff[k] + i;
-      rowsub[r] = k;
-      imap[r] = s.i_map[i];
-      for (int a = s.kig_rowptr[i]; a < s.kig_rowptr[i + 1]; ++a) {
-        igcol.push_back(s.g_map[s.kig_col[a]]);
-        igval.push_back(s.kig_val[a]);
+  size_t nig = 0;
+  for (int k = 0; k < c->n_sub; ++k) nig += (size_t)p->sub[k].kig_rowptr[p->sub[k].n_i];
+  std::vector<int> igptr(NI + 1, 0), igcol(nig);
+  std::vector<double> igval(nig);
+  {
+    size_t at = 0;
+    for (int k = 0; k < c->n_sub; ++k) {
+      const dd_subdomain &s = p->sub[k];
+      for (int i = 0; i < s.n_i; ++i) {
+        const int r = c->ioff[k] + i;
+        rowsub[r] = k;
+        imap[r] = s.i_map[i];
+        for (int a = s.kig_rowptr[i]; a < s.kig_rowptr[i + 1]; ++a, ++at) {
+          igcol[at] = s.g_map[s.kig_col[a]];
+          igval[at] = s.kig_val[a];
+        }
+        igptr[r + 1] = (int)at;
       }
-      igptr[r + 1] = (int)igcol.size();
     }
   }
-  // interface rows: [K_GG entries | K_GI entries (transposes of K_IG^k)]
-  std::vector<std::vector<std::pair<int, double>>> gi(c->n_gamma);
-  for (int r = 0; r < NI; ++r)
-    for (int a = igptr[r]; a < igptr[r + 1]; ++a) gi[igcol[a]].push_back({r, igval[a]});
-  std::vector<int> gptr(c->n_gamma + 1, 0), gsplit(c->n_gamma, 0), gcol;
-  std::vector<double> gval;
-  for (int j = 0; j < c->n_gamma; ++j) {
-    for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a) {
-      gcol.push_back(p->kgg_col[a]);
-      gval.push_back(p->kgg_val[a]);
+  // interface rows: [K_GG entries | K_GI entries (transposes of K_IG^k), by
+  // increasing interior row], filled by counting
+  std::vector<int> gptr(c->n_gamma + 1, 0), gsplit(c->n_gamma, 0);
+  for (int j = 0; j < c->n_gamma; ++j) gptr[j + 1] = p->kgg_rowptr[j + 1] - p->kgg_rowptr[j];
+  for (size_t a = 0; a < nig; ++a) ++gptr[igcol[a] + 1];
+  for (int j = 0; j < c->n_gamma; ++j) gptr[j + 1] += gptr[j];
+  std::vector<int> gcol(gptr[c->n_gamma]);
+  std::vector<double> gval(gptr[c->n_gamma]);
+  {
+    std::vector<int> fill(c->n_gamma);
+    for (int j = 0; j < c->n_gamma; ++j) {
+      const int b = p->kgg_rowptr[j], len = p->kgg_rowptr[j + 1] - b;
+      if (len) {
+        memcpy(&gcol[gptr[j]], p->kgg_col + b, sizeof(int) * len);
+        memcpy(&gval[gptr[j]], p->kgg_val + b, sizeof(double) * len);
+      }
+      gsplit[j] = fill[j] = gptr[j] + len;
     }
-    gsplit[j] = (int)gcol.size();
-    // gi[j] is already ordered by interior row (rows visited in order)
-    for (auto &e : gi[j]) {
-      gcol.push_back(e.first);
-      gval.push_back(e.second);
-    }
-    gptr[j + 1] = (int)gcol.size();
+    for (int r = 0; r < NI; ++r)
+      for (int a = igptr[r]; a < igptr[r + 1]; ++a) {
+        const int j = igcol[a];
+        gcol[fill[j]] = r;
+        gval[fill[j]++] = igval[a];
+      }
   }
   c->nnz_ig = igcol.size();
   c->nnz_g = gcol.size();
@@ -1355,7 +1364,14 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   }
   if ((s = upload(c, &c->d_imap, imap.data(), NI)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_gmap, p->gamma_map, c->n_gamma)) != DD_OK) return bail(s);
-  if ((s = upload(c, &c->d_kii64, kii.data(), kt)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &c->d_kii64, (size_t)kt)) != DD_OK) return bail(s);
+  for (int k = 0; k < c->n_sub; ++k)          // straight from the caller's blocks
+    if (c->ni[k] > 0 &&
+        hipMemcpy(c->d_kii64 + c->koff[k], p->sub[k].k_ii, sizeof(double) * (size_t)c->ni[k] * c->ni[k],
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "hipMemcpy of K_II failed";
+      return bail(DD_EHIP);
+    }
   if ((s = upload(c, &c->d_ig_ptr, igptr.data(), NI + 1)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_ig_col, igcol.data(), igcol.size())) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_ig_val64, igval.data(), igval.size())) != DD_OK) return bail(s);
