@@ -1878,8 +1878,9 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
   }
 }
 
-// The whole factorisation in one launch, left-looking by 16-wide block columns:
-// one workgroup per (subdomain k, block column J) computes
+// The whole factorisation (the Cholesky factors K_II^k = L_k L_k^T of eq.
+// splittingBlockCholesky) in one launch, left-looking by 16-wide block
+// columns: one workgroup per (subdomain k, block column J) computes
 //   A[J:, J] -= sum_{Q < J} L[J:, Q] L[J, Q]^T,   L[J][J] = chol(A[J][J]),
 //   L[I][J] = A[I][J] L[J][J]^{-T}  (I > J),
 // the last step as the MFMA product L[I][J]^T = L[J][J]^{-1} A[I][J]^T with the
@@ -1901,7 +1902,8 @@ k_potrf_panel(T *__restrict__ blocks, const long long *__restrict__ koff,
 // raises *timeout and stops waiting, so the launch always drains (the factor
 // is then garbage and the host reports it).
 // A non-positive pivot raises status[k] = column + 1 unless a smaller column
-// of the same subdomain already did (those finished before this one waited).
+// of the same subdomain already did: the status store of column J settles
+// before J's early flag, which column J+1 waits for before its own pivots.
 constexpr int kFlowSpin = 1 << 18;
 // Value of v in lane l (l uniform) as a wave-uniform scalar.
 __device__ __forceinline__ double bcast_lane(double v, int l) {
@@ -2255,8 +2257,9 @@ k_trtri(const T *__restrict__ L, T *__restrict__ X, const long long *__restrict_
   }
 }
 
-// X = L^{-1} in two launches (the one-wave-per-block-column k_trtri above is the
-// fallback when a block column does not fit in LDS).
+// X = L^{-1} (for the explicit K_II^{-1} = X^T X applied in every interior
+// solve, eq. splittingBlockCholesky) in two launches (the one-wave-per-block-
+// column k_trtri above is the fallback when a block column does not fit in LDS).
 //
 // First the inverse of every diagonal 16x16 block, X[R][R] = L[R][R]^{-1}, one
 // wave per (subdomain, block R), strict upper part zero.
@@ -2534,7 +2537,8 @@ k_schur_diag(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
   }
 }
 
-// The same diagonal on the matrix cores.  With X_k = L_k^{-1} (K_II^k = L_k L_k^T),
+// The same diagonal (of S_k in eq. subSchurComplement, summed over the
+// subdomains) on the matrix cores.  With X_k = L_k^{-1} (K_II^k = L_k L_k^T),
 //   (K_GI^k (K_II^k)^{-1} K_IG^k)_jj = || X_k K_IG^k e_j ||^2,
 // so each subdomain contributes the column sums of squares of W_k = X_k K_IG^k.
 //
