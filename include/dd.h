@@ -192,9 +192,12 @@ typedef struct {
   double ms_per_solve;       /* measured time of one solve of the batch with this schedule */
   int32_t candidates;        /* schedules timed */
   double inner_tol;          /* DD_MIXED: inner tolerance chosen (0 for DD_FP64) */
-  int32_t three_launch;      /* 1: three launches per CG iteration (update fused into the
-                                K_IG launch, direction recurrence in the interior solve);
-                                0: four (K_IG, interior solve, interface rows, update) */
+  int32_t three_launch;      /* bit 0 set: three launches per CG iteration (update fused
+                                into the K_IG launch, direction recurrence in the interior
+                                solve), clear: four (K_IG, interior solve, interface rows,
+                                update); bit 1 (DD_MIXED only): the FP32-data products
+                                gather FP32 copies of the vectors they multiply (half the
+                                gathered bytes; pays off for wide batches) */
 } dd_tune_result;
 
 /* Autotuner: time every candidate schedule of the CG loop on this context and

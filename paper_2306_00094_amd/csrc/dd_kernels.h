@@ -203,6 +203,23 @@ struct Src {
   const double *q;       // kind 2: S p of the previous iteration
   const double *dinv;    // kind 2: 1 / diagonal of the preconditioner (nullptr: none)
   const int *upd;        // kind 2: 1 if column c takes the step
+  const float *x32 = nullptr;   // FP32 copy of x (kind 0), gathered instead of x when given
+};
+
+// FP32 copies of the vectors that the FP32-data products of the mixed inner
+// solve gather (K_IG z, K_IG D^{-1} q in K1; K_GG p, K_GI w in K3).  Each is
+// written next to its FP64 vector by the launch that produces it and read, in
+// place of that vector, by the gathers of the next launch: half the gathered
+// bytes, with rounding at the level of the FP32 matrix entries.  The Krylov
+// vectors, their updates and every dot product stay FP64.  All nullptr: the
+// gathers read the FP64 vectors.
+struct Gather32 {
+  const float *z_old;   // z_{k-1}                (read by K1's rows)
+  float *z;             // z_k                    (written by K1's slices)
+  const float *qd;      // D^{-1} q_{k-1}         (read by K1's rows)
+  float *p;             // p_k                    (written by K2's slices, read by K3)
+  float *w;             // w_k                    (written by K2's rows, read by K3)
+  float *qd_out;        // D^{-1} q_k             (written by K3)
 };
 
 template <int C, bool OTF>
@@ -264,7 +281,8 @@ __device__ __forceinline__ void load_slots(int k, int e, const int *__restrict__
   }
 }
 
-template <int C, typename VT, int OTF, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
+template <int C, typename VT, int OTF, int U = Unroll<C>::U, int G = kWave, bool PIPE = false,
+          bool F32 = false>
 __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict__ col,
                                             const VT *__restrict__ val, const Src &x, int ld,
                                             int cp, double (&acc)[C]) {
@@ -285,7 +303,11 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
     for (int u = 0; u < U; ++u) {
       v[u] = vn[u];
       if (cn[u] >= 0) {
-        if constexpr (OTF == 2) src_load_z<C>(x, cn[u], ld, cp, bt, up, xv[u]);
+        if constexpr (F32) {               // FP32 copy of a plain vector
+          const size_t off = (size_t)cn[u] * ld + cp;
+#pragma unroll
+          for (int c = 0; c < C; ++c) xv[u][c] = (double)x.x32[off + c];
+        } else if constexpr (OTF == 2) src_load_z<C>(x, cn[u], ld, cp, bt, up, xv[u]);
         else src_load<C, OTF != 0>(x, (size_t)cn[u] * ld + cp, bt, xv[u]);
       } else {
 #pragma unroll
@@ -304,11 +326,13 @@ __device__ __forceinline__ void csr_row_acc(int b, int e, const int *__restrict_
 // Two-part row: entries [b, s) gather from x1 into acc1, entries [s, e) from
 // x2 into acc2, in one masked loop (each accumulator sees its entries in
 // increasing order; slots of the other part add exact zeros).
-template <int C, typename VT, bool OTF1, int U = Unroll<C>::U, int G = kWave, bool PIPE = false>
+template <int C, typename VT, bool OTF1, int U = Unroll<C>::U, int G = kWave, bool PIPE = false,
+          bool F32 = false>
 __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__restrict__ col,
                                              const VT *__restrict__ val, const Src &x1,
                                              const Src &x2, int ld, int cp, double (&acc1)[C],
-                                             double (&acc2)[C]) {
+                                             double (&acc2)[C], const float *__restrict__ x1f = nullptr,
+                                             const float *__restrict__ x2f = nullptr) {
   double bt1[C], bt2[C];
   src_beta<C, OTF1>(x1, cp, bt1);
   src_beta<C, false>(x2, cp, bt2);
@@ -327,6 +351,11 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
       if (cn[u] < 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c) xv[u][c] = 0.0;
+      } else if constexpr (F32) {         // FP32 copies of plain vectors
+        const float *xf = idx < s ? x1f : x2f;
+        const size_t off = (size_t)cn[u] * ld + cp;
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[u][c] = (double)xf[off + c];
       } else if (idx < s) {
         src_load<C, OTF1>(x1, (size_t)cn[u] * ld + cp, bt1, xv[u]);
       } else {
@@ -354,11 +383,12 @@ __device__ __forceinline__ void csr_row_acc2(int b, int s, int e, const int *__r
 // of csr_row_acc): au += val * xs[j] and av += val * qs[j].  SCALED: the
 // gathered entries are multiplied by the preconditioner entry d_j = xs.dinv[j]
 // (1 without one); WITHV = false: the second sum is skipped.
-template <int C, typename VT, bool SCALED, bool WITHV, int U = (Unroll<C>::U + 1) / 2>
+template <int C, typename VT, bool SCALED, bool WITHV, int U = (Unroll<C>::U + 1) / 2, bool F32 = false>
 __device__ __forceinline__ void csr_row_acc_uv(int b, int e, const int *__restrict__ col,
                                                const VT *__restrict__ val, const Src &rs,
                                                const Src &qs, int ld, int cp, double (&au)[C],
-                                               double (&av)[C]) {
+                                               double (&av)[C], const float *__restrict__ rs32 = nullptr,
+                                               const float *__restrict__ qs32 = nullptr) {
   int k = b + lane_id();
   while (k < e) {
     double v[U];
@@ -372,8 +402,13 @@ __device__ __forceinline__ void csr_row_acc_uv(int b, int e, const int *__restri
         const double d = (SCALED && rs.dinv) ? rs.dinv[cc[u]] : 1.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          xr[u][c] = SCALED ? d * rs.x[off + c] : rs.x[off + c];
-          xq[u][c] = WITHV ? qs.x[off + c] : 0.0;
+          if constexpr (F32) {             // FP32 copies (never scaled: iterations k >= 1)
+            xr[u][c] = (double)rs32[off + c];
+            xq[u][c] = WITHV ? (double)qs32[off + c] : 0.0;
+          } else {
+            xr[u][c] = SCALED ? d * rs.x[off + c] : rs.x[off + c];
+            xq[u][c] = WITHV ? qs.x[off + c] : 0.0;
+          }
         }
       } else {
 #pragma unroll
@@ -419,7 +454,8 @@ k_csr_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ col,
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
-    csr_row_acc<C, VT, OTF>(b, e, col, val, x, ld, cp, acc);
+    if (!OTF && x.x32) csr_row_acc<C, VT, OTF, Unroll<C>::U, kWave, false, true>(b, e, col, val, x, ld, cp, acc);
+    else csr_row_acc<C, VT, OTF>(b, e, col, val, x, ld, cp, acc);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
     if (lane_id() == 0) {
@@ -444,7 +480,8 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
              const double *__restrict__ base, double sign, double *__restrict__ out,
              // optional sparse part (interior residual): out -= K_IG u_G
              const int *__restrict__ sptr, const int *__restrict__ scol,
-             const double *__restrict__ sval, const double *__restrict__ sx) {
+             const double *__restrict__ sval, const double *__restrict__ sx,
+             float *__restrict__ out32 = nullptr) {   // FP32 copy of out (gathered later)
   int r = blockIdx.x * kWavesPerBlock + wave_id();
   if (r >= nrows) return;
   int k = rowsub[r];
@@ -490,7 +527,9 @@ k_dense_rows(int nrows, const MT *__restrict__ blocks, const long long *__restri
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         size_t o = (size_t)r * ld + cp + c;
-        out[o] = (base ? base[o] : 0.0) + sign * ((double)acc[c] + sacc[c]);
+        const double ov = (base ? base[o] : 0.0) + sign * ((double)acc[c] + sacc[c]);
+        out[o] = ov;
+        if (out32) out32[o] = (float)ov;
       }
     }
   }
@@ -508,7 +547,8 @@ __global__ void __launch_bounds__(kBlock)
 k_dense_rows_rb(int nblk, const int *__restrict__ rb_first, const MT *__restrict__ blocks,
                 const long long *__restrict__ koff, const int *__restrict__ ioff,
                 const int *__restrict__ ni, const int *__restrict__ rowsub,
-                const double *__restrict__ y, int ld, double *__restrict__ out) {
+                const double *__restrict__ y, int ld, double *__restrict__ out,
+                float *__restrict__ out32 = nullptr) {
   const int bk = blockIdx.x * kWavesPerBlock + wave_id();
   if (bk >= nblk) return;
   const int r0 = rb_first[bk];
@@ -542,8 +582,11 @@ k_dense_rows_rb(int nblk, const int *__restrict__ rb_first, const MT *__restrict
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         AT v = wave_sum(acc[r][c]);
-        if (lane_id() == 0 && r < nr)
-          out[(size_t)(r0 + r) * ld + cp + c] = 0.0 + 1.0 * ((double)v + 0.0);
+        if (lane_id() == 0 && r < nr) {
+          const double ov = 0.0 + 1.0 * ((double)v + 0.0);
+          out[(size_t)(r0 + r) * ld + cp + c] = ov;
+          if (out32) out32[(size_t)(r0 + r) * ld + cp + c] = (float)ov;
+        }
       }
     }
   }
@@ -574,7 +617,7 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
              RedBuf red, ColState st, const double *__restrict__ dinv,
-             double *__restrict__ qd) {
+             double *__restrict__ qd, Gather32 g32) {
   constexpr int RPW = kWave / G, CH = NW * RPW;
   // three-launch iteration (qd given): nothing to do once every column stopped
   // (st.flag[1], written by the interior-solve launch just before)
@@ -597,7 +640,12 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
       src_load<C, OTF>(p, (size_t)j * ld + cp, bt, pj);
     }
     if (j < nrows) {
-      if (c1 != 0.0 && c2 != 0.0) csr_row_acc2<C, VT, OTF, U, G, PIPE>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
+      if (c1 != 0.0 && c2 != 0.0) {
+        if (!OTF && g32.p)
+          csr_row_acc2<C, VT, OTF, U, G, PIPE, true>(b, s, e, col, val, p, zs, ld, cp, a1, a2, g32.p, g32.w);
+        else
+          csr_row_acc2<C, VT, OTF, U, G, PIPE>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
+      }
       else if (c1 != 0.0) csr_row_acc<C, VT, OTF, U, G, PIPE>(b, s, col, val, p, ld, cp, a1);
       else if (c2 != 0.0) csr_row_acc<C, VT, false, U, G, PIPE>(s, e, col, val, zs, ld, cp, a2);
     }
@@ -614,7 +662,11 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
           size_t o = (size_t)j * ld + cp + c;
           q = (base ? base[o] : 0.0) + c1 * a1[c] + c2 * a2[c];
           out[o] = q;
-          if (qd) qd[o] = dinv ? dinv[j] * q : q;   // D^{-1} q for the next K_IG launch
+          if (qd) {                         // D^{-1} q for the next K_IG launch
+            const double dq = dinv ? dinv[j] * q : q;
+            qd[o] = dq;
+            if (g32.qd_out) g32.qd_out[o] = (float)dq;
+          }
           if (dot) {
             if (pout) pout[o] = pj[c];      // this row of the direction, kept for the update
             q *= pj[c];
@@ -653,9 +705,10 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
-             RedBuf red, ColState st, const double *__restrict__ dinv, double *__restrict__ qd) {
+             RedBuf red, ColState st, const double *__restrict__ dinv, double *__restrict__ qd,
+             Gather32 g32) {
   gamma_rows_body<C, VT, OTF, G, U, PIPE, NW>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2,
-                                              out, dot, pout, red, st, dinv, qd);
+                                              out, dot, pout, red, st, dinv, qd, g32);
 }
 
 
@@ -686,7 +739,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
             int use_precond, int *__restrict__ host_nact, int init_p_is_z,
-            const int *__restrict__ mask, int npq, int cpw) {
+            const int *__restrict__ mask, int npq, int cpw, float *__restrict__ p32 = nullptr) {
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ double salpha[kMaxLd];
   __shared__ int sact[kMaxLd];
@@ -763,7 +816,10 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         double zv = use_precond ? dv[k] * rr_ : rr_;
         if (act) z[o] = zv;
         else zv = z[o];
-        if (init) p[o] = init_p_is_z ? zv : 0.0;   // direction z, or none yet (beta = 0)
+        if (init) {                                 // direction z, or none yet (beta = 0)
+          p[o] = init_p_is_z ? zv : 0.0;
+          if (p32) p32[o] = init_p_is_z ? (float)zv : 0.f;
+        }
         rz = rr_ * zv;
         rrv[k] = rr_ * rr_;
       }
@@ -883,6 +939,7 @@ struct CgVec {
   const double *qd;     // D^{-1} S p_{k-1} (written with q by the interface-row kernel)
 };
 
+
 __device__ __forceinline__ bool cg_starts(int mode, const int *mask, int c) {
   return mode == 0 || (mode == 2 && mask[c] != 0);
 }
@@ -927,7 +984,8 @@ template <int C, int E, typename VT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
          const int *__restrict__ col, const VT *__restrict__ val, int nG, int ld, CgVec v,
-         double *__restrict__ y, RedBuf red, ColState st, const int *__restrict__ mask, int npq) {
+         double *__restrict__ y, RedBuf red, ColState st, const int *__restrict__ mask, int npq,
+         Gather32 g32) {
   // every column stopped at the previous iteration (st.flag[1], written by its
   // K2): nothing to update or apply (an iteration launched ahead of the host's
   // convergence check)
@@ -968,6 +1026,9 @@ k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
       for (int c = 0; c < C; ++c) { au[c] = 0.0; av[c] = 0.0; }
       if (row < nrows) {
         if (mode == 0) csr_row_acc_uv<C, VT, true, false>(b, e, col, val, rs, rs, ld, cp, au, av);
+        else if (g32.z_old)
+          csr_row_acc_uv<C, VT, false, true, (Unroll<C>::U + 1) / 2, true>(b, e, col, val, zs, qs, ld, cp, au,
+                                                                          av, g32.z_old, g32.qd);
         else csr_row_acc_uv<C, VT, false, true>(b, e, col, val, zs, qs, ld, cp, au, av);
       }
 #pragma unroll
@@ -1044,6 +1105,7 @@ k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
         const double zv = v.dinv ? d * rn : rn;
         v.r_new[o] = rn;
         v.z[o] = zv;
+        if (g32.z) g32.z[o] = (float)zv;
         rz = rn * zv;
         rrv[k] = rn * rn;
       }
@@ -1181,7 +1243,8 @@ __device__ __forceinline__ void cg_k2_slice_pre(int nG, int ld, const double *__
 }
 __device__ __forceinline__ void cg_k2_slice(int nG, int ld, const double *__restrict__ z,
                                             double *__restrict__ p, const double *sbeta,
-                                            const int *sinit, double z0, double p0) {
+                                            const int *sinit, double z0, double p0,
+                                            float *__restrict__ p32) {
   const int row0 = ((int)blockIdx.x - 1) * kRowsE;
   for (int e = threadIdx.x; e < kRowsE * ld; e += kBlock) {
     const int lr = e / ld, c = e - lr * ld, j = row0 + lr;
@@ -1190,7 +1253,9 @@ __device__ __forceinline__ void cg_k2_slice(int nG, int ld, const double *__rest
     const bool first = e == (int)threadIdx.x;
     const double zv = first ? z0 : z[o];
     const double pv = first ? p0 : p[o];
-    p[o] = sinit[c] ? zv : fma(sbeta[c], pv, zv);
+    const double pn = sinit[c] ? zv : fma(sbeta[c], pv, zv);
+    p[o] = pn;
+    if (p32) p32[o] = (float)pn;
   }
 }
 
@@ -1203,7 +1268,7 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
            const long long *__restrict__ koff, const int *__restrict__ ioff, const int *__restrict__ ni,
            const int *__restrict__ rowsub, const double *__restrict__ y, int ld, double *__restrict__ w,
            int nG, int nrhs, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
-           ColState st, const int *__restrict__ mask, int *__restrict__ host_nact) {
+           ColState st, const int *__restrict__ mask, int *__restrict__ host_nact, Gather32 g32) {
   if (mode == 1 && st.flag[1] == 0) {       // every column stopped (see k_cg_kig)
     if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
       __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1224,7 +1289,7 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
     if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
     cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
                   sinit, scnt, sbk);
-    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0);
+    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
     return;
   }
   // (launched with C == ld <= 4: one pass covers every column)
@@ -1299,7 +1364,9 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
   cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, false, early, in0, 0, nullptr, sbeta, sinit, scnt, sbk);
   if (have && lane < ld) {
     const int c = lane;
-    w[(size_t)r * ld + c] = sinit[c] ? t : fma(sbeta[c], wp, t);
+    const double wn = sinit[c] ? t : fma(sbeta[c], wp, t);
+    w[(size_t)r * ld + c] = wn;
+    if (g32.w) g32.w[(size_t)r * ld + c] = (float)wn;
   }
 }
 
@@ -1312,7 +1379,7 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
               const int *__restrict__ ioff, const int *__restrict__ ni, const int *__restrict__ rowsub,
               const double *__restrict__ y, int ld, double *__restrict__ w, int nG, int nrhs,
               const double *__restrict__ z, double *__restrict__ p, RedBuf red, ColState st,
-              const int *__restrict__ mask, int *__restrict__ host_nact) {
+              const int *__restrict__ mask, int *__restrict__ host_nact, Gather32 g32) {
   if (mode == 1 && st.flag[1] == 0) {       // every column stopped (see k_cg_kig)
     if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
       __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1333,7 +1400,7 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
     if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
     cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
                   sinit, scnt, sbk);
-    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0);
+    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
     return;
   }
   const int bk = ((int)blockIdx.x - nsl) * kWavesPerBlock + wv;
@@ -1379,7 +1446,9 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
   for (int rr = 0; rr < nr; ++rr)
     for (int c = lane; c < ld; c += kWave) {
       const size_t o = (size_t)(r0 + rr) * ld + c;
-      w[o] = sinit[c] ? st_[wv][rr][c] : fma(sbeta[c], w[o], st_[wv][rr][c]);
+      const double wn = sinit[c] ? st_[wv][rr][c] : fma(sbeta[c], w[o], st_[wv][rr][c]);
+      w[o] = wn;
+      if (g32.w) g32.w[o] = (float)wn;
     }
 }
 
@@ -1393,11 +1462,15 @@ __global__ void k_set_stop(int ld, double f2, const double *__restrict__ v, ColS
 // instead of being formed where it is gathered).
 __global__ void __launch_bounds__(kBlock)
 k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p,
-               ColState st) {
+               ColState st, float *__restrict__ p32 = nullptr) {
   size_t n = (size_t)nrows * ld;
   for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
     int c = (int)(e % ld);
-    if (st.active[c]) p[e] = fma(st.beta[c], p[e], z[e]);
+    if (st.active[c]) {
+      const double pn = fma(st.beta[c], p[e], z[e]);
+      p[e] = pn;
+      if (p32) p32[e] = (float)pn;      // copy gathered by the FP32-data products
+    }
   }
 }
 

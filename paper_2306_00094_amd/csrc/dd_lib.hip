@@ -58,6 +58,9 @@ struct Work {
   double *bG, *xG, *rG, *zG, *pG, *qG, *uG, *dG, *tG;
   double *r2G, *z2G;       // second residual / preconditioned residual (three-launch iteration)
   double *qdG;             // D^{-1} q (three-launch iteration)
+  // FP32 gather copies of the mixed three-launch iteration: z by parity (like
+  // zG / z2G), D^{-1} q and p (n_gamma x ldmax), w (NI x ldmax)
+  float *z32A, *z32B, *qd32, *p32, *w32;
   // interior (NI x ldmax)
   double *bI, *yI, *wI, *uI, *dI, *tI;
   double *bnrm2, *rnrm2;   // ldmax
@@ -117,6 +120,8 @@ struct dd_ctx {
   int old_trtri = 0;          // 1: L^{-1} by one wave per block column (no LDS panel)
   int panel_potrf = 0;        // 1: Cholesky by two launches per 16-wide panel
   int flow_spin = kFlowSpin;  // bound of each wait in the single-launch Cholesky (sleeps)
+  int gather32 = 0;           // 1: untuned mixed three-launch solves gather FP32 vector copies
+  Gather32 g32{};             // FP32 gather copies of the three-launch iteration being launched
   int *d_flow = nullptr;      // single-launch Cholesky: ticket, timeout, done flags
   double *fac_x = nullptr, *fac_packed = nullptr, *fac_dloc = nullptr;   // factor work space
   bool packed_ready = false;
@@ -138,7 +143,8 @@ struct dd_ctx {
     int apply = 0, launch = 0, dk = 0, check_every = 0, cg3 = 1;
     double ms = 0, inner_tol = 0;
   };
-  int force_cg3 = -1;         // autotuner: -1 schedule decides, 0 four launches, 1 three
+  int force_cg3 = -1;         // autotuner: -1 schedule decides, else the schedule bits (bit 0 three
+                              // launches, bit 1 FP32 gathers)
   Tuned tuned[2][7];
   // continuous batching
   struct Batch {
@@ -321,23 +327,23 @@ void csr_rows(dd_ctx *c, int nrows, const int *ptr, const int *col, const VT *va
 template <int C, typename MT, typename AT>
 void launch_dense(dd_ctx *c, const MT *blocks, const double *y, int ld, const double *base,
                   double sign, double *out, const int *sptr, const int *scol, const double *sval,
-                  const double *sx) {
+                  const double *sx, float *out32) {
   if (c->NI <= 0) return;
   hipLaunchKernelGGL((k_dense_rows<C, MT, AT>), dim3(grid_for(c->NI, kWavesPerBlock)),
                      dim3(kBlock), 0, c->stream, c->NI, blocks, c->d_koff, c->d_ioff, c->d_ni,
-                     c->d_rowsub, y, ld, base, sign, out, sptr, scol, sval, sx);
+                     c->d_rowsub, y, ld, base, sign, out, sptr, scol, sval, sx, out32);
 }
 
 template <typename MT, typename AT>
 void dense_rows(dd_ctx *c, const MT *blocks, const double *y, int ld, const double *base,
                 double sign, double *out, const int *sptr = nullptr, const int *scol = nullptr,
-                const double *sval = nullptr, const double *sx = nullptr) {
+                const double *sval = nullptr, const double *sx = nullptr, float *out32 = nullptr) {
   switch (std::min(ld, 16)) {
-    case 1: launch_dense<1, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
-    case 2: launch_dense<2, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
-    case 4: launch_dense<4, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
-    case 8: launch_dense<8, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
-    default: launch_dense<16, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx); break;
+    case 1: launch_dense<1, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx, out32); break;
+    case 2: launch_dense<2, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx, out32); break;
+    case 4: launch_dense<4, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx, out32); break;
+    case 8: launch_dense<8, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx, out32); break;
+    default: launch_dense<16, MT, AT>(c, blocks, y, ld, base, sign, out, sptr, scol, sval, sx, out32); break;
   }
 }
 
@@ -373,17 +379,17 @@ void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
   if (p.z) {
     if (timed)
       hipExtLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
-                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
-                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
   } else {
     if (timed)
       hipExtLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
-                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
-                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd);
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
   }
 }
 
@@ -406,7 +412,7 @@ void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, do
   const int E = std::max(1, cpw * kRowsE * ld / kBlock);
 #define DD_UPD(EE)                                                                              \
   hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x, \
-                     r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw)
+                     r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p)
   switch (E) {
     case 1: DD_UPD(1); break;
     case 2: DD_UPD(2); break;
@@ -464,16 +470,21 @@ void interior_solve(dd_ctx *c, int prec, int apply, const double *y, double *z, 
     const dim3 g(grid_for(c->n_rb, kWavesPerBlock)), b(kBlock);
     if (prec == DD_FP64)
       hipLaunchKernelGGL((k_dense_rows_rb<8, double, double>), g, b, 0, c->stream, c->n_rb, c->d_rb_first,
-                         (const double *)c->op[0].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z);
+                         (const double *)c->op[0].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z,
+                         c->g32.w);
     else
       hipLaunchKernelGGL((k_dense_rows_rb<8, float, float>), g, b, 0, c->stream, c->n_rb, c->d_rb_first,
-                         (const float *)c->op[1].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z);
+                         (const float *)c->op[1].kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, y, ld, z,
+                         c->g32.w);
     return;
   }
+  // (c->g32.w: FP32 copy of w for the FP32-data gathers of the interface rows)
   if (prec == DD_FP64)
-    dense_rows<double, double>(c, (const double *)c->op[0].kinv, y, ld, nullptr, 1.0, z);
+    dense_rows<double, double>(c, (const double *)c->op[0].kinv, y, ld, nullptr, 1.0, z, nullptr, nullptr,
+                               nullptr, nullptr, c->g32.w);
   else
-    dense_rows<float, float>(c, (const float *)c->op[1].kinv, y, ld, nullptr, 1.0, z);
+    dense_rows<float, float>(c, (const float *)c->op[1].kinv, y, ld, nullptr, 1.0, z, nullptr, nullptr,
+                             nullptr, nullptr, c->g32.w);
 }
 
 // y = K_IG x (+ base, sign) with the coupling values of `prec`.
@@ -509,7 +520,7 @@ void launch_cg_kig_t(dd_ctx *c, const VT *val, int mode, int par, int ld, const 
   const unsigned g = nsl + grid_for(c->NI, kWavesPerBlock);
   hipLaunchKernelGGL((k_cg_kig<C, E, VT>), dim3(g), dim3(kBlock), 0, c->stream, mode, par, c->NI,
                      (int)nsl, c->d_ig_ptr, c->d_ig_col, val, c->n_gamma, ld, v, c->w.yI, c->red, c->st,
-                     mask, c->gamma_parts);
+                     mask, c->gamma_parts, c->g32);
 }
 
 template <typename VT>
@@ -535,12 +546,12 @@ void launch_cg_dense_t(dd_ctx *c, const MT *kinv, int mode, int par, int ld, int
     hipLaunchKernelGGL((k_cg_dense_rb<8, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode,
                        par, c->n_rb, (int)nsl, c->d_rb_first, kinv, c->d_koff, c->d_ioff, c->d_ni,
                        c->d_rowsub, c->w.yI, ld, c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask,
-                       host_nact);
+                       host_nact, c->g32);
   } else {
     const unsigned nrb = grid_for(c->NI, kWavesPerBlock);
     hipLaunchKernelGGL((k_cg_dense<C, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode, par,
                        c->NI, (int)nsl, kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, c->w.yI, ld,
-                       c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, host_nact);
+                       c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, host_nact, c->g32);
   }
 }
 
@@ -801,13 +812,17 @@ void collect_timing(dd_ctx *c, const StateBlock *h) {
 // K1, K2 and K3 of iteration k (modes 0 and 1); r_{k-1} and z_{k-1} are in
 // rG / zG for even k and in r2G / z2G for odd k.
 void cg3_iteration(dd_ctx *c, int prec, int k, int mode, int ld, int nrhs, int precond, double *x,
-                   const int *mask, int *host_nact) {
+                   const int *mask, int *host_nact, bool gather32) {
   Work &w = c->w;
   const Ops &op = c->op[prec];
   const int par = k & 1;
   const double *dinv = precond ? op.dinv : nullptr;
   CgVec v{dinv, x, par ? w.r2G : w.rG, par ? w.rG : w.r2G, par ? w.z2G : w.zG, par ? w.zG : w.z2G,
           w.pG, w.qG, w.qdG};
+  // the FP32-data products of the mixed path gather FP32 copies of z, D^{-1} q, p and w
+  if (prec == DD_MIXED && gather32)
+    c->g32 = Gather32{par ? w.z32B : w.z32A, par ? w.z32A : w.z32B, w.qd32, w.p32, w.w32, w.qd32};
+  struct ResetG32 { dd_ctx *c; ~ResetG32() { c->g32 = Gather32{}; } } reset_g32{c};
   {
     PhaseTimer t(c, DD_PHASE_KIG);
     if (prec == DD_FP64) launch_cg_kig<double>(c, (const double *)op.ig_val, mode, par, ld, v, mask);
@@ -830,7 +845,7 @@ struct CoreOpts {
   int apply;
   int check_every;
   int launch;
-  int cg3;        // 1: three launches per CG iteration where possible
+  int cg3;        // bit 0: three launches per CG iteration where possible; bit 1: FP32 gathers (mixed)
 };
 
 // Untuned solves run three launches per iteration (k_cg_kig) at every batch
@@ -895,18 +910,29 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // Three launches per iteration where the interiors exist and their inverse
   // is applied (k_cg_kig); otherwise four (K_IG, interior solve, interface
   // rows, update), which the persistent kernel also runs.
-  const bool cg3 = o.cg3 && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
+  const bool cg3 = (o.cg3 & 1) && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
                    o.launch != DD_LAUNCH_PERSISTENT && !c->classic_cg;
+  // FP32 gather copies for the FP32-data products (mixed): in the three-launch
+  // iteration, or in the four-launch one with the direction kept by its kernel
+  const bool g32 = (o.cg3 & 2) && prec == DD_MIXED && c->NI > 0 && c->n_gamma > 0 &&
+                   o.apply != DD_APPLY_TRSM && o.launch != DD_LAUNCH_PERSISTENT &&
+                   (cg3 || c->direction_kernel);
+  const int sched = (cg3 ? 1 : 0) | (g32 ? 2 : 0);
+  struct ResetG32 { dd_ctx *c; ~ResetG32() { c->g32 = Gather32{}; } } reset_g32{c};
   c->tev_cg3_ld = cg3 ? ld : 0;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
   double *pA = w.pG, *pB = w.xG;
   if (c->n_gamma == 0)            // no init kernel to clear the breakdown flag
     HIPCHK(c, hipMemsetAsync(c->st.flag, 0, sizeof(int), c->stream));
   if (cg3)                        // iteration 0: start every column (p_0 = z_0, q_0 = S p_0)
-    cg3_iteration(c, prec, 0, 0, ld, nrhs, o.precond, uG, nullptr, nullptr);
-  else if (c->n_gamma > 0)
+    cg3_iteration(c, prec, 0, 0, ld, nrhs, o.precond, uG, nullptr, nullptr, g32);
+  else if (c->n_gamma > 0) {
+    // four launches: p (from the init and the direction kernel) and w (from the
+    // interior solve) also written in FP32 for the gathers of the loop below
+    if (g32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
                   c->direction_kernel, nullptr, 0);
+  }
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
     dd_status ps = prec == DD_FP64
@@ -936,6 +962,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
     const bool dk = c->direction_kernel != 0;
     Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
+    if (dk && g32) P.x32 = w.p32;
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     // (formed at the K_IG gathers, which also store it into pB for the rest of
     // the iteration; without interiors the interface rows form and store it)
@@ -959,7 +986,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,
-                         w.zG, pA_, c->st);
+                         w.zG, pA_, c->st, c->g32.p);
     } else {
       std::swap(pA_, pB_);
     }
@@ -969,7 +996,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // CG iteration k >= 1 in either scheme
   auto step = [&](int k, double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
     if (!cg3) return iteration(pA_, pB_, nact_dst);
-    cg3_iteration(c, prec, k, 1, ld, nrhs, o.precond, uG, nullptr, nact_dst);
+    cg3_iteration(c, prec, k, 1, ld, nrhs, o.precond, uG, nullptr, nact_dst, g32);
     HIPCHK(c, hipGetLastError());
     return DD_OK;
   };
@@ -980,7 +1007,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     hipGraphExec_t exec = nullptr;
     for (auto &g : c->graphs)
       if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
-          g.dk == c->direction_kernel && g.iters == G && g.x == uG && g.cg3 == (cg3 ? 1 : 0))
+          g.dk == c->direction_kernel && g.iters == G && g.x == uG && g.cg3 == sched)
         exec = g.exec;
     if (!exec) {
       if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1010,7 +1037,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       (void)hipGraphDestroy(graph);
       if (ee != hipSuccess)
         return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
-      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, cg3 ? 1 : 0, uG, exec});
+      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, sched, uG, exec});
     }
     // replay; look at the result of launch n - 1 while launch n runs.  The
     // number of active columns only decreases, so a later value is as good.
@@ -1069,6 +1096,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       }
     }
   }
+  c->g32 = Gather32{};
   // back substitution (eq. backwardSubstitution): uI = K_II^{-1} (bI - K_IG uG)
   kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
   interior_solve(c, prec, o.apply, w.yI, uI, ld);
@@ -1186,6 +1214,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if (const char *e = getenv("DD_BLOCKWAVE_TRTRI")) c->old_trtri = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_PANEL_POTRF")) c->panel_potrf = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_FLOW_SPIN")) c->flow_spin = std::max(0, std::min(atoi(e), kFlowSpin));
+  if (const char *e = getenv("DD_GATHER32")) c->gather32 = atoi(e) ? 1 : 0;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
@@ -1388,6 +1417,10 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   double **iv[] = {&w.bI, &w.yI, &w.wI, &w.uI, &w.dI, &w.tI};
   for (double **q : iv)
     if ((s = dalloc(c, q, nI)) != DD_OK) return bail(s);
+  float **gf[] = {&w.z32A, &w.z32B, &w.qd32, &w.p32};
+  for (float **q : gf)
+    if ((s = dalloc(c, q, nG)) != DD_OK) return bail(s);
+  if ((s = dalloc(c, &w.w32, nI)) != DD_OK) return bail(s);
   if ((s = dalloc(c, &c->d_state, 1)) != DD_OK) return bail(s);
   {
     StateBlock *sb = c->d_state;
@@ -1531,11 +1564,19 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   if (c->NI > 0 && !c->classic_cg) {
     for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 0, lag, 1});
     for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 0, g, 1});
+    if (prec == DD_MIXED) {      // the FP32-data products gathering FP32 vector copies
+      for (int lag : {1, 2}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 0, lag, 3});
+      cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 0, 4, 3});
+    }
   }
   for (int lag : {1, 2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 0, lag, 0});
   for (int g : {2, 4}) cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 0, g, 0});
   cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 0});
   cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 0});
+  if (prec == DD_MIXED && c->NI > 0) {   // the same with FP32 gathers
+    cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 2});
+    cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 2});
+  }
   cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2, 0});
   cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0, 0});
   const int saved_dk = c->direction_kernel;
@@ -1961,6 +2002,8 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     }
   }
   if (c->force_cg3 >= 0) use_cg3 = c->force_cg3;
+  if (c->gather32) use_cg3 |= 2;
+  if (prec != DD_MIXED) use_cg3 &= 1;     // FP32 gathers serve FP32 data only
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
               o.check_every,
               (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS,

@@ -357,7 +357,7 @@ def test_autotune_then_auto_solve(prec):
     print("  tuned", res, flush=True)
     assert res["candidates"] >= 7 and res["ms_per_solve"] > 0
     assert res["launch"] in (1, 2, 3) and res["apply"] in (1, 2)
-    assert res["three_launch"] in (0, 1)
+    assert res["three_launch"] in ((0, 1) if prec == 0 else (0, 1, 2, 3))   # bit 1: FP32 gathers (mixed)
     if prec == 1:        # the mixed path also tunes its inner tolerance
         assert res["inner_tol"] in (1e-4, 1e-5, 1e-6)
     else:
@@ -428,6 +428,41 @@ def test_three_launch_iteration_matches_four_launch(name, prec, monkeypatch):
     assert oracle.rel_err(u3, u4).max() <= 2 * gate
     s3.close()
     s4.close()
+
+
+@pytest.mark.parametrize("iteration", ["three", "four"])
+@pytest.mark.parametrize("name", ["1d-ragged", "2d-const", "2d-pd"])
+def test_mixed_fp32_gathers(name, iteration, monkeypatch):
+    """The mixed path with its FP32-data products gathering FP32 copies of
+    the vectors they multiply (three-launch iteration: z, D^-1 q, p, w;
+    four-launch iteration with the direction kernel: p, w): the refined
+    solution meets the mixed gate against the monolithic solution, graph
+    replays give the bits of stream launches, and every column of a
+    16-column batch equals, bit for bit, the same column solved alone."""
+    dd = _dd()
+    wl, b, uref = problem(name)
+    print(f"case mixed fp32 gathers {name} {iteration} launches", flush=True)
+    monkeypatch.setenv("DD_GATHER32", "1")
+    if iteration == "four":
+        monkeypatch.setenv("DD_CLASSIC_CG", "1")
+        monkeypatch.setenv("DD_DIRECTION_KERNEL", "1")
+    s = dd.Solver(wl.dd, max_nrhs=16)
+    s.factor(dd.DD_MIXED)
+    o1 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_KERNELS, apply=dd.DD_APPLY_INV)
+    o2 = dd.dd_default_opts(tol=1e-12, launch=dd.DD_LAUNCH_GRAPH, check_every=4, apply=dd.DD_APPLY_INV)
+    r1 = s.solve(to_dev(b), prec=dd.DD_MIXED, opts=o1)
+    err = oracle.rel_err(r1.u.cpu().numpy().T, uref)
+    print("  err", err, [i["iters"] for i in r1.info], flush=True)
+    assert err.max() <= 1e-8
+    r2 = s.solve(to_dev(b), prec=dd.DD_MIXED, opts=o2)
+    assert [i["iters"] for i in r1.info] == [i["iters"] for i in r2.info]
+    assert np.array_equal(r1.u.cpu().numpy(), r2.u.cpu().numpy())
+    b16 = np.tile(b, (1, 16))[:, :16]
+    r16 = s.solve(to_dev(b16), prec=dd.DD_MIXED, opts=o1).u.cpu().numpy()
+    for j in (0, 7, 15):
+        one = s.solve(to_dev(b16[:, j:j + 1]), prec=dd.DD_MIXED, opts=o1).u.cpu().numpy()
+        assert np.array_equal(r16[j], one[0]), j
+    s.close()
 
 
 def test_three_launch_wide_batch(monkeypatch):
