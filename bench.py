@@ -54,7 +54,7 @@ WORKLOADS = {
 # rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of this benchmark on the
 # default workload, each scaled by what the counter read for an elementwise
 # kernel of known traffic (FETCH x2.000, WRITE x1.000): 256 MiB read and written
-# read as 131085.6 KiB fetched and 262148.2 KiB written.  Valid only for the
+# read as about 131085 KiB fetched and 262148 KiB written.  Valid only for the
 # kernel source they were taken on (sha256 prefix of csrc/dd_kernels.h);
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
@@ -235,6 +235,41 @@ def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
                 fallbacks=load["fallbacks"] + burst["fallbacks"])
 
 
+def wide_batch_leg(dd, workloads, torch, steps=3, warmup=1):
+    """Mixed against plain FP64 on a wide batch: the 2D bond-based peridynamic
+    system (h = 1/160, 50 562 dofs, 8x8 jittered subdomains) with its 32
+    seeded right-hand sides in one batch, each path autotuned for that width
+    (the mixed path may choose FP32 gathers), at relative residual 1e-9.
+    Reports the time per batch, solves/s (32 per batch), iterations and the
+    largest true relative residual of each path."""
+    import numpy as np
+    cfg = WORKLOADS["cfg4"]
+    spec = getattr(workloads, cfg["spec"])()
+    wl = workloads.build(spec)
+    b = workloads.rhs(spec)
+    nrhs = b.shape[1]
+    bt = torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda:0").contiguous()
+    s = dd.Solver(wl.dd, max_nrhs=nrhs)
+    out = dict(workload=cfg["desc"], nrhs=nrhs, rel_resid=cfg["tol"])
+    try:
+        for name, prec in (("fp64", dd.DD_FP64), ("mixed", dd.DD_MIXED)):
+            s.factor(prec)
+            opts = dd.dd_default_opts(tol=cfg["tol"])
+            tuned = s.autotune(prec, nrhs, opts)
+            r = time_path(s, dd, bt, prec, opts, steps, warmup, torch)
+            out[name] = dict(ms_per_batch=1e3 * r["seconds"] / steps,
+                             solves_per_s=steps * nrhs / r["seconds"],
+                             iters_max=max(i["iters"] for i in r["info"]),
+                             rel_resid_max=max(i["rel_resid"] for i in r["info"]),
+                             schedule=tuned)
+            log(f"bench: wide batch prec={prec} {out[name]['ms_per_batch']:.1f} ms/batch "
+                f"its={out[name]['iters_max']} schedule={tuned}")
+    finally:
+        s.close()
+    out["mixed_vs_fp64"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    return out
+
+
 def jacobi_cg_leg(dd, workloads, wl, bt, b, tol, steps, warmup, torch, cpu_seconds):
     """The paper's baseline solver on the same system: CG on the whole matrix
     with diag(A) as preconditioner (section "Considered solver strategies"),
@@ -313,6 +348,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--no-wide-batch", action="store_true",
+                    help="skip the mixed-vs-FP64 leg on the 32-column peridynamic batch")
     ap.add_argument("--no-jacobi-cg", action="store_true",
                     help="skip the baseline leg (Jacobi-preconditioned CG on the whole system)")
     ap.add_argument("--launch", default="auto", choices=["auto", "kernels", "graph", "persistent"],
@@ -473,6 +510,11 @@ def main():
         jcg["dd_speedup"] = {k: res_v / jcg[k]["value"]
                              for k, res_v in (("fp64", fp64["value"]), ("mixed", mixed["value"]))}
         line["jacobi_cg"] = jcg
+    if not args.no_wide_batch:
+        log("bench: wide-batch leg (peridynamic system, 32 right-hand sides) ...")
+        t = time.perf_counter()
+        line["wide_batch"] = wide_batch_leg(dd, workloads, torch)
+        log(f"bench: wide-batch leg done in {time.perf_counter() - t:.1f} s")
     if args.serving_requests > 0:
         log(f"bench: serving leg ({args.serving_requests} requests) ...")
         t = time.perf_counter()

@@ -611,7 +611,7 @@ constexpr int kGChunk = kGRows * kGRowsPerWave;   // rows per workgroup / partia
 template <int C> struct GUnroll { static constexpr int U = C == 1 ? 8 : (C <= 4 ? 4 : (C <= 8 ? 2 : 1)); };
 
 template <int C, typename VT, bool OTF, int G = kGLanes, int U = GUnroll<C>::U, bool PIPE = false,
-          int NW = kGRows>
+          int NW = kGRows, bool G32 = false>
 __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
              const double *__restrict__ z, int ld, const double *__restrict__ base, double c1,
@@ -641,7 +641,7 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
     }
     if (j < nrows) {
       if (c1 != 0.0 && c2 != 0.0) {
-        if (!OTF && g32.p)
+        if constexpr (G32 && !OTF)
           csr_row_acc2<C, VT, OTF, U, G, PIPE, true>(b, s, e, col, val, p, zs, ld, cp, a1, a2, g32.p, g32.w);
         else
           csr_row_acc2<C, VT, OTF, U, G, PIPE>(b, s, e, col, val, p, zs, ld, cp, a1, a2);
@@ -665,7 +665,9 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
           if (qd) {                         // D^{-1} q for the next K_IG launch
             const double dq = dinv ? dinv[j] * q : q;
             qd[o] = dq;
-            if (g32.qd_out) g32.qd_out[o] = (float)dq;
+            if constexpr (G32) {
+              if (g32.qd_out) g32.qd_out[o] = (float)dq;
+            }
           }
           if (dot) {
             if (pout) pout[o] = pj[c];      // this row of the direction, kept for the update
@@ -699,7 +701,7 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
 }
 
 template <int C, typename VT, bool OTF, int G = kGLanes, int U = GUnroll<C>::U, bool PIPE = false,
-          int NW = kGRows>
+          int NW = kGRows, bool G32 = false>
 __global__ void __launch_bounds__(NW * kWave)
 k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
              const int *__restrict__ col, const VT *__restrict__ val, Src p,
@@ -707,8 +709,8 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
              double c2, double *__restrict__ out, int dot, double *__restrict__ pout,
              RedBuf red, ColState st, const double *__restrict__ dinv, double *__restrict__ qd,
              Gather32 g32) {
-  gamma_rows_body<C, VT, OTF, G, U, PIPE, NW>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2,
-                                              out, dot, pout, red, st, dinv, qd, g32);
+  gamma_rows_body<C, VT, OTF, G, U, PIPE, NW, G32>(nrows, ptr, split, col, val, p, z, ld, base, c1, c2,
+                                                   out, dot, pout, red, st, dinv, qd, g32);
 }
 
 
@@ -980,7 +982,7 @@ __device__ __forceinline__ void cg_k1_column(int mode, const int *mask, int c, i
 // take four interior rows each.  Wave w reduces the step length of columns
 // w, w+4, ...; the loads of its first column are issued before its row work.
 // E = elements per thread of a slice (64 ld / 256).
-template <int C, int E, typename VT>
+template <int C, int E, typename VT, bool G32 = false>
 __global__ void __launch_bounds__(kBlock)
 k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
          const int *__restrict__ col, const VT *__restrict__ val, int nG, int ld, CgVec v,
@@ -1026,7 +1028,7 @@ k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
       for (int c = 0; c < C; ++c) { au[c] = 0.0; av[c] = 0.0; }
       if (row < nrows) {
         if (mode == 0) csr_row_acc_uv<C, VT, true, false>(b, e, col, val, rs, rs, ld, cp, au, av);
-        else if (g32.z_old)
+        else if constexpr (G32)
           csr_row_acc_uv<C, VT, false, true, (Unroll<C>::U + 1) / 2, true>(b, e, col, val, zs, qs, ld, cp, au,
                                                                           av, g32.z_old, g32.qd);
         else csr_row_acc_uv<C, VT, false, true>(b, e, col, val, zs, qs, ld, cp, au, av);
@@ -1105,7 +1107,7 @@ k_cg_kig(int mode, int par, int nrows, int nsl, const int *__restrict__ ptr,
         const double zv = v.dinv ? d * rn : rn;
         v.r_new[o] = rn;
         v.z[o] = zv;
-        if (g32.z) g32.z[o] = (float)zv;
+        if constexpr (G32) g32.z[o] = (float)zv;
         rz = rn * zv;
         rrv[k] = rn * rn;
       }
@@ -1241,6 +1243,7 @@ __device__ __forceinline__ void cg_k2_slice_pre(int nG, int ld, const double *__
     p0 = p[(size_t)j * ld + (e - lr * ld)];
   }
 }
+template <bool G32>
 __device__ __forceinline__ void cg_k2_slice(int nG, int ld, const double *__restrict__ z,
                                             double *__restrict__ p, const double *sbeta,
                                             const int *sinit, double z0, double p0,
@@ -1255,14 +1258,14 @@ __device__ __forceinline__ void cg_k2_slice(int nG, int ld, const double *__rest
     const double pv = first ? p0 : p[o];
     const double pn = sinit[c] ? zv : fma(sbeta[c], pv, zv);
     p[o] = pn;
-    if (p32) p32[o] = (float)pn;
+    if constexpr (G32) p32[o] = (float)pn;
   }
 }
 
 // K2: workgroup 0 writes the column state, workgroups 1 .. nsl-1 update the
 // direction slices, the others take interior rows: one row per wave (row
 // arithmetic of k_dense_rows), w = result + beta w_prev.
-template <int C, typename MT, typename AT>
+template <int C, typename MT, typename AT, bool G32 = false>
 __global__ void __launch_bounds__(kBlock)
 k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
            const long long *__restrict__ koff, const int *__restrict__ ioff, const int *__restrict__ ni,
@@ -1289,7 +1292,7 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
     if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
     cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
                   sinit, scnt, sbk);
-    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
+    if (!leader) cg_k2_slice<G32>(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
     return;
   }
   // (launched with C == ld <= 4: one pass covers every column)
@@ -1366,13 +1369,13 @@ k_cg_dense(int mode, int par, int nrows, int nsl, const MT *__restrict__ blocks,
     const int c = lane;
     const double wn = sinit[c] ? t : fma(sbeta[c], wp, t);
     w[(size_t)r * ld + c] = wn;
-    if (g32.w) g32.w[(size_t)r * ld + c] = (float)wn;
+    if constexpr (G32) g32.w[(size_t)r * ld + c] = (float)wn;
   }
 }
 
 // K2 for wide batches (ld >= 8): kRB rows per wave (row arithmetic of
 // k_dense_rows_rb), results parked in LDS until beta is known.
-template <int C, typename MT, typename AT>
+template <int C, typename MT, typename AT, bool G32 = false>
 __global__ void __launch_bounds__(kBlock)
 k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_first,
               const MT *__restrict__ blocks, const long long *__restrict__ koff,
@@ -1400,7 +1403,7 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
     if (!leader) cg_k2_slice_pre(nG, ld, z, p, z0, p0);
     cg_k2_scalars(mode, par, ld, nrhs, mask, red, st, nch, leader, false, CgK2In{}, flag0, host_nact, sbeta,
                   sinit, scnt, sbk);
-    if (!leader) cg_k2_slice(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
+    if (!leader) cg_k2_slice<G32>(nG, ld, z, p, sbeta, sinit, z0, p0, g32.p);
     return;
   }
   const int bk = ((int)blockIdx.x - nsl) * kWavesPerBlock + wv;
@@ -1448,7 +1451,7 @@ k_cg_dense_rb(int mode, int par, int nblk, int nsl, const int *__restrict__ rb_f
       const size_t o = (size_t)(r0 + rr) * ld + c;
       const double wn = sinit[c] ? st_[wv][rr][c] : fma(sbeta[c], w[o], st_[wv][rr][c]);
       w[o] = wn;
-      if (g32.w) g32.w[o] = (float)wn;
+      if constexpr (G32) g32.w[o] = (float)wn;
     }
 }
 

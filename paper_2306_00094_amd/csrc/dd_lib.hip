@@ -383,6 +383,14 @@ void launch_gamma(dd_ctx *c, const VT *val, Src p, const double *z, int ld,
     else
       hipLaunchKernelGGL((k_gamma_rows<C, VT, true>), g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
                          c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
+  } else if (c->g32.p) {       // FP32 gathers of p and w (FP32-data products of the mixed path)
+    constexpr auto kern = k_gamma_rows<C, VT, false, kGLanes, GUnroll<C>::U, false, kGRows, true>;
+    if (timed)
+      hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
+                            c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
+    else
+      hipLaunchKernelGGL(kern, g, b, 0, c->stream, c->n_gamma, c->d_g_ptr,
+                         c->d_g_split, c->d_g_col, val, p, z, ld, base, c1, c2, out, dot, pout, c->red, c->st, dinv, qd, c->g32);
   } else {
     if (timed)
       hipExtLaunchKernelGGL((k_gamma_rows<C, VT, false>), g, b, 0, c->stream, e0, e1, 0, c->n_gamma, c->d_g_ptr,
@@ -518,9 +526,14 @@ void launch_cg_kig_t(dd_ctx *c, const VT *val, int mode, int par, int ld, const 
                      const int *mask) {
   const unsigned nsl = grid_for(c->n_gamma, kRowsE);
   const unsigned g = nsl + grid_for(c->NI, kWavesPerBlock);
-  hipLaunchKernelGGL((k_cg_kig<C, E, VT>), dim3(g), dim3(kBlock), 0, c->stream, mode, par, c->NI,
-                     (int)nsl, c->d_ig_ptr, c->d_ig_col, val, c->n_gamma, ld, v, c->w.yI, c->red, c->st,
-                     mask, c->gamma_parts, c->g32);
+  if (c->g32.z_old)
+    hipLaunchKernelGGL((k_cg_kig<C, E, VT, true>), dim3(g), dim3(kBlock), 0, c->stream, mode, par, c->NI,
+                       (int)nsl, c->d_ig_ptr, c->d_ig_col, val, c->n_gamma, ld, v, c->w.yI, c->red, c->st,
+                       mask, c->gamma_parts, c->g32);
+  else
+    hipLaunchKernelGGL((k_cg_kig<C, E, VT>), dim3(g), dim3(kBlock), 0, c->stream, mode, par, c->NI,
+                       (int)nsl, c->d_ig_ptr, c->d_ig_col, val, c->n_gamma, ld, v, c->w.yI, c->red, c->st,
+                       mask, c->gamma_parts, c->g32);
 }
 
 template <typename VT>
@@ -543,15 +556,23 @@ void launch_cg_dense_t(dd_ctx *c, const MT *kinv, int mode, int par, int ld, int
   const unsigned nsl = grid_for(c->n_gamma, kRowsE) + 1;     // slices and the state workgroup
   if (ld >= 8 && c->n_rb > 0) {
     const unsigned nrb = grid_for(c->n_rb, kWavesPerBlock);
-    hipLaunchKernelGGL((k_cg_dense_rb<8, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode,
-                       par, c->n_rb, (int)nsl, c->d_rb_first, kinv, c->d_koff, c->d_ioff, c->d_ni,
-                       c->d_rowsub, c->w.yI, ld, c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask,
-                       host_nact, c->g32);
+#define DD_K2RB(G)                                                                                     \
+  hipLaunchKernelGGL((k_cg_dense_rb<8, MT, AT, G>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode,     \
+                     par, c->n_rb, (int)nsl, c->d_rb_first, kinv, c->d_koff, c->d_ioff, c->d_ni,           \
+                     c->d_rowsub, c->w.yI, ld, c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, \
+                     host_nact, c->g32)
+    if (c->g32.w) DD_K2RB(true);
+    else DD_K2RB(false);
+#undef DD_K2RB
   } else {
     const unsigned nrb = grid_for(c->NI, kWavesPerBlock);
-    hipLaunchKernelGGL((k_cg_dense<C, MT, AT>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode, par,
-                       c->NI, (int)nsl, kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, c->w.yI, ld,
-                       c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, host_nact, c->g32);
+#define DD_K2(G)                                                                                        \
+  hipLaunchKernelGGL((k_cg_dense<C, MT, AT, G>), dim3(nsl + nrb), dim3(kBlock), 0, c->stream, mode, par,    \
+                     c->NI, (int)nsl, kinv, c->d_koff, c->d_ioff, c->d_ni, c->d_rowsub, c->w.yI, ld,        \
+                     c->w.wI, c->n_gamma, nrhs, v.z, v.p, c->red, c->st, mask, host_nact, c->g32)
+    if (c->g32.w) DD_K2(true);
+    else DD_K2(false);
+#undef DD_K2
   }
 }
 
