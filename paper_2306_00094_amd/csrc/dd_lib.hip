@@ -286,6 +286,7 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   b += 2 * kt * s + p->n_gamma * 16;                                  // L, K^-1, diag
   if (prec == DD_MIXED) b += (nig + ngg + nig) * 4;                   // FP32 values
   b += (12 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                   // work vectors
+  b += (4 * (size_t)p->n_gamma + NI) * ld * 4;                        // FP32 gather copies
   size_t chunks = std::max<size_t>((p->n_gamma + kGChunk - 1) / kGChunk,
                                    (std::max<size_t>(p->n_gamma, NI) + kRowsE - 1) / kRowsE) + 1;
   b += 3 * chunks * kMaxLd * 8;
