@@ -185,13 +185,13 @@ def cpu_baseline(wl, b, tol, budget_s):
                        f"{dt:.1f} s", threads_available=os.cpu_count())
 
 
-def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
+def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000, gather32: int = 1):
     """Continuous-batching serving run (paper_2306_00094_amd.serving) over
     four resident systems: the 1D constant kernel, the benchmark system and
     half-scale 2D constant and fractional systems.  Requests carry 1-16
     seeded right-hand sides.  First all requests arrive at once (saturated
     throughput), then Poisson arrivals at 0.8x that request rate (latency
-    under load)."""
+    under load).  Mixed precision, with FP32 gathers unless gather32 = 0."""
     import numpy as np
     from paper_2306_00094_amd import serving
     specs = {
@@ -214,7 +214,7 @@ def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
             out.append(serving.Request(key=k, b=np.asfortranarray(loads[k][:, :m]), arrival=float(t), rid=i))
         return out
 
-    opts = dd.dd_default_opts(tol=1e-9)
+    opts = dd.dd_default_opts(tol=1e-9, gather32=gather32)
     srv = serving.Server(systems, prec=dd.DD_MIXED, opts=opts, iters_per_step=4)
     try:
         # every system resident (factors formed) before anything is timed
@@ -229,6 +229,7 @@ def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000):
     finally:
         srv.shutdown()
     return dict(systems=keys, requests=nreq, rhs_per_request="1-16", rel_resid=1e-9, precision="mixed",
+                fp32_gathers=bool(gather32),
                 saturated_solves_per_s=burst["solves_per_s"], saturated_p50_ms=burst["p50_ms"],
                 saturated_p99_ms=burst["p99_ms"], offered_requests_per_s=rate,
                 solves_per_s=load["solves_per_s"], p50_ms=load["p50_ms"], p99_ms=load["p99_ms"],

@@ -121,6 +121,10 @@ typedef struct {
   int32_t launch;        /* dd_launch */
   int32_t check_every;   /* DD_LAUNCH_KERNELS: host polls convergence every N iterations (0 = auto) */
   int32_t verify;        /* 1 = compute the true FP64 residual ||b - A u|| / ||b|| into info */
+  int32_t gather32;      /* DD_MIXED: the FP32-data products gather FP32 copies of the vectors
+                            they multiply (half the gathered bytes; pays off for wide
+                            batches): -1 = automatic (dd_solve: the autotuned schedule, else
+                            off; batches: off), 0 = off, 1 = on */
 } dd_solve_opts;
 
 typedef struct {
@@ -133,7 +137,8 @@ typedef struct {
 } dd_solve_info;
 
 /* Fill opts with defaults: tol 1e-10, max_it 1000, precond 1, max_refine 8,
- * inner_tol 0 (automatic), fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1. */
+ * inner_tol 0 (automatic), fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1,
+ * gather32 -1 (automatic). */
 void dd_default_opts(dd_solve_opts *opts);
 
 /* Device bytes a context for `prob` would hold (matrices, factors for
@@ -225,7 +230,10 @@ enum { DD_SLOT_FREE = 0, DD_SLOT_RUNNING = 1, DD_SLOT_DONE = 2, DD_SLOT_FALLBACK
  * DD_SLOT_FALLBACK: mixed-precision refinement stalled; the request should be
  * solved with FP64 factors (e.g. dd_solve on another context). */
 
-/* Open a batch: precision and tolerances (opts) for every slot. */
+/* Open a batch: precision and tolerances (opts) for every slot.  With
+ * DD_MIXED and opts->gather32 == 1 the session keeps the direction in memory
+ * and its FP32-data products gather FP32 vector copies; apply, launch and
+ * check_every are not used (every step launches its kernels directly). */
 dd_status dd_batch_begin(dd_ctx *ctx, dd_precision prec, const dd_solve_opts *opts);
 
 /* Admit ncol right-hand sides (b_dev: D, column-major n_dof x ncol, leading

@@ -155,6 +155,9 @@ struct dd_ctx {
     int state[kMaxLd] = {0}, its[kMaxLd] = {0}, steps[kMaxLd] = {0}, conv[kMaxLd] = {0};
     int stall[kMaxLd] = {0};
     double bn2[kMaxLd] = {0}, rn2[kMaxLd] = {0}, prev[kMaxLd] = {0}, stop2[kMaxLd] = {0};
+    // FP32 gathers (mixed): the direction is kept in pG by its own kernel and
+    // the FP32-data products gather FP32 copies of it and of w
+    bool g32 = false;
     int *d_mask = nullptr, *d_slots = nullptr;
   } batch;
   hipStream_t cap_stream = nullptr;   // capture only (the legacy default stream cannot capture)
@@ -1180,6 +1183,7 @@ void dd_default_opts(dd_solve_opts *o) {
   o->launch = DD_LAUNCH_AUTO;
   o->check_every = 0;
   o->verify = 1;
+  o->gather32 = -1;
 }
 
 const char *dd_last_error(const dd_ctx *ctx) {
@@ -1735,9 +1739,11 @@ dd_status batch_start_cg(dd_ctx *c, const int *mask, const double *rI, const dou
   gamma_apply(c, B.prec, plain(nullptr), w.wI, ld, rG, 0.0, -1.0, w.qG);
   std::vector<double> st2(B.stop2, B.stop2 + kMaxLd);
   HIPCHK(c, hipMemcpyAsync(c->st.stop2, st2.data(), kMaxLd * 8, hipMemcpyHostToDevice, c->stream));
+  // first direction: z itself when the direction kernel keeps it (FP32
+  // gathers), else none (formed as z + 0 p where it is gathered)
   if (c->n_gamma > 0)
-    launch_update(c, 2, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, B.o.precond, nullptr, 0,
-                  (const int *)B.d_mask, 0);
+    launch_update(c, 2, ld, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, B.o.precond, nullptr,
+                  B.g32 ? 1 : 0, (const int *)B.d_mask, 0);
   HIPCHK(c, hipGetLastError());
   return DD_OK;
 }
@@ -1759,6 +1765,7 @@ dd_status dd_batch_begin(dd_ctx *c, dd_precision prec, const dd_solve_opts *opts
   if (B.o.inner_tol < 0.0 || B.o.inner_tol >= 1.0) return fail(c, DD_EINVAL, "inner_tol not in [0,1)");
   if (B.o.inner_tol == 0.0) B.o.inner_tol = kInnerTol;
   B.prec = prec;
+  B.g32 = prec == DD_MIXED && B.o.gather32 == 1 && c->NI > 0 && c->n_gamma > 0;
   B.ld = 1;
   B.on = true;
   HIPCHK(c, hipMemsetAsync(c->st.active, 0, kMaxLd * sizeof(int), c->stream));
@@ -1827,7 +1834,27 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
   const int prec = B.prec;
   bool any = false;
   for (int j = 0; j < kMaxLd; ++j) any |= B.state[j] == DD_SLOT_RUNNING;
-  if (any && iters > 0 && c->n_gamma > 0) {
+  if (any && iters > 0 && c->n_gamma > 0 && B.g32) {
+    // direction kept in pG; its FP32 copy is refreshed here because the
+    // admissions and retirements in between change the column stride
+    hipLaunchKernelGGL(k_to_f32, dim3(grid1d((size_t)c->n_gamma * L)), dim3(256), 0, c->stream,
+                       (size_t)c->n_gamma * L, (const double *)w.pG, w.p32);
+    c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
+    struct ResetG32 { dd_ctx *c; ~ResetG32() { c->g32 = Gather32{}; } } reset_g32{c};
+    Src P = plain(w.pG);
+    P.x32 = w.p32;
+    const unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * L, kBlock));
+    for (int it = 0; it < iters; ++it) {
+      kig_apply(c, prec, P, L, nullptr, 1.0, w.yI);
+      interior_solve(c, prec, DD_APPLY_INV, w.yI, w.wI, L);          // also w in FP32
+      gamma_apply(c, prec, P, w.wI, L, nullptr, 1.0, -1.0, w.qG, 1, nullptr);
+      launch_update(c, 1, L, kMaxLd, op.dinv, w.dG, w.rG, w.zG, w.pG, w.qG, B.o.precond, nullptr, 0,
+                    nullptr, c->gamma_parts);
+      hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, L, w.zG,
+                         w.pG, c->st, w.p32);
+    }
+    HIPCHK(c, hipGetLastError());
+  } else if (any && iters > 0 && c->n_gamma > 0) {
     double *pA = w.pG, *pB = w.xG;
     for (int it = 0; it < iters; ++it) {
       Src P{nullptr, w.zG, pA, c->st.beta};
@@ -2024,7 +2051,8 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     }
   }
   if (c->force_cg3 >= 0) use_cg3 = c->force_cg3;
-  if (c->gather32) use_cg3 |= 2;
+  if (c->gather32 || o.gather32 == 1) use_cg3 |= 2;
+  if (o.gather32 == 0) use_cg3 &= 1;
   if (prec != DD_MIXED) use_cg3 &= 1;     // FP32 gathers serve FP32 data only
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
               o.check_every,

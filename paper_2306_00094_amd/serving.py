@@ -182,7 +182,9 @@ class Server:
                  hbm_budget: int | None = None, iters_per_step: int = 4):
         self.systems = systems                      # key -> DDProblem
         self.prec = prec
-        self.opts = opts if opts is not None else dd_default_opts(tol=1e-9)
+        # mixed precision: the FP32-data products gather FP32 vector copies
+        # (the serving batches are wide; FP64 solves ignore the option)
+        self.opts = opts if opts is not None else dd_default_opts(tol=1e-9, gather32=1)
         self.hbm_budget = hbm_budget
         self.iters_per_step = iters_per_step
         self.footprint = {k: dd_footprint(dd, prec, MAX_SLOTS) for k, dd in systems.items()}

@@ -83,6 +83,31 @@ def test_batch_api_matches_dd_solve(prec, monkeypatch):
     s.close()
 
 
+def test_batch_api_fp32_gathers_match_dd_solve(monkeypatch):
+    """Mixed batches with FP32 gathers keep the direction in memory (its own
+    kernel) and gather FP32 copies of it and of w; dd_solve forced to the
+    same four-launch iteration gives the same bits, and every column meets
+    the FP64 tolerance."""
+    dd = _dd()
+    wl, b, uref = system("2d")
+    print("case batch api fp32 gathers", flush=True)
+    monkeypatch.setenv("DD_CLASSIC_CG", "1")
+    monkeypatch.setenv("DD_DIRECTION_KERNEL", "1")
+    s = dd.Solver(wl.dd, max_nrhs=64)
+    s.factor(dd.DD_MIXED)
+    opts = dd.dd_default_opts(tol=1e-11, gather32=1)
+    ref = s.solve(dev(b), prec=dd.DD_MIXED, opts=opts).u.cpu().numpy()
+    plain = s.solve(dev(b), prec=dd.DD_MIXED, opts=dd.dd_default_opts(tol=1e-11, gather32=0))
+    assert not np.array_equal(ref, plain.u.cpu().numpy())       # the option took effect
+    out = run_batch(dd, s, b, [(0, 0, 0), (2, 1, 9), (3, 2, 2), (5, 3, 0)], dd.DD_MIXED, opts)
+    for col in range(b.shape[1]):
+        u, info = out[col]
+        assert info["converged"] == 1
+        assert np.array_equal(u, ref[col]), col
+        assert oracle.rel_err(u, uref[:, col]).max() <= 1e-8
+    s.close()
+
+
 def test_batch_rejects_solve_while_open():
     dd = _dd()
     wl, b, _ = system("1d")
@@ -104,7 +129,7 @@ def test_serving_mix_alone_equal_and_correct():
     from paper_2306_00094_amd import serving
     names = ["1d", "2d", "frac"]
     systems = {k: system(k)[0].dd for k in names}
-    opts = dd.dd_default_opts(tol=1e-11)
+    opts = dd.dd_default_opts(tol=1e-11, gather32=1)      # the serving default
     fps = {k: dd.dd_footprint(v, dd.DD_MIXED, 64) for k, v in systems.items()}
     budget = max(fps.values()) * 2           # at most two systems resident
     rng = np.random.default_rng(5)
