@@ -185,50 +185,67 @@ def cpu_baseline(wl, b, tol, budget_s):
                        f"{dt:.1f} s", threads_available=os.cpu_count())
 
 
-def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000, gather32: int = 1):
+def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000, gather32: int = 1,
+                chunk: int = 1000):
     """Continuous-batching serving run (paper_2306_00094_amd.serving) over
-    four resident systems: the 1D constant kernel, the benchmark system and
-    half-scale 2D constant and fractional systems.  Requests carry 1-16
-    seeded right-hand sides.  First all requests arrive at once (saturated
+    six resident systems: the 1D constant kernel at h = 1/1024 and 1/2048,
+    the 2D constant kernel at h = 1/64 and 1/128 (the benchmark system), and
+    the 2D fractional kernel at h = 1/48 and 1/96 (mesh sizes x0.5 to x2 of
+    the three base systems).  Requests carry 1-64 seeded right-hand sides.  First all requests arrive at once (saturated
     throughput), then Poisson arrivals at 0.8x that request rate (latency
-    under load).  Mixed precision, with FP32 gathers unless gather32 = 0."""
+    under load); more than `chunk` requests run as consecutive chunks of
+    that many.  Mixed precision, with FP32 gathers unless gather32 = 0."""
     import numpy as np
     from paper_2306_00094_amd import serving
     specs = {
         "1d-const h=1/1024": workloads.spec_1d(),
+        "1d-const h=1/2048": workloads.spec_1d(n=2048),
         "2d-const h=1/64": workloads.scaled(workloads.spec_2d_const, 0.5),
         "2d-frac h=1/48": workloads.scaled(workloads.spec_2d_frac, 0.5),
+        "2d-frac h=1/96": workloads.spec_2d_frac(),
     }
     systems = {k: workloads.build(sp).dd for k, sp in specs.items()}
     systems["2d-const h=1/128"] = wl_main.dd
     specs["2d-const h=1/128"] = wl_main.spec
     rng = np.random.default_rng(seed)
     keys = sorted(systems)
-    loads = {k: workloads.rhs(specs[k], nrhs=16, seed_base=seed + 100 * i) for i, k in enumerate(keys)}
+    loads = {k: workloads.rhs(specs[k], nrhs=64, seed_base=seed + 100 * i) for i, k in enumerate(keys)}
 
-    def requests(arrivals):
+    def requests(arrivals, base=0):
         out = []
         for i, t in enumerate(arrivals):
             k = keys[int(rng.integers(0, len(keys)))]
-            m = int(rng.integers(1, 17))
-            out.append(serving.Request(key=k, b=np.asfortranarray(loads[k][:, :m]), arrival=float(t), rid=i))
+            m = int(rng.integers(1, 65))
+            out.append(serving.Request(key=k, b=np.asfortranarray(loads[k][:, :m]), arrival=float(t),
+                                       rid=base + i))
         return out
+
+    # long runs go in chunks of `chunk` requests (each drains before the next
+    # starts); seconds add up over the chunks
+    def phase(name, arrivals):
+        done, secs = [], 0.0
+        for c0 in range(0, nreq, chunk):
+            n = min(chunk, nreq - c0)
+            t0 = time.perf_counter()
+            d = srv.run(requests(arrivals(n, c0), c0), timeout=600, keep_resident=True)
+            wall = time.perf_counter() - t0
+            secs += wall if name == "saturated" else serving.summarize(d)["seconds"]
+            done += d
+            if nreq > chunk:
+                log(f"bench: serving {name}: {c0 + n}/{nreq} requests, {secs:.1f} s")
+        return serving.summarize(done, wall=secs)
 
     opts = dd.dd_default_opts(tol=1e-9, gather32=gather32)
     srv = serving.Server(systems, prec=dd.DD_MIXED, opts=opts, iters_per_step=4)
     try:
         # every system resident (factors formed) before anything is timed
         srv.run(requests(np.zeros(len(keys) * 2)), timeout=300, keep_resident=True)
-        t0 = time.perf_counter()
-        done = srv.run(requests(np.zeros(nreq)), timeout=600, keep_resident=True)
-        burst = serving.summarize(done, wall=time.perf_counter() - t0)
+        burst = phase("saturated", lambda n, c0: np.zeros(n))
         rate = 0.8 * burst["requests"] / burst["seconds"]
-        done = srv.run(requests(serving.poisson_arrivals(nreq, rate=rate, seed=seed + 1)), timeout=600,
-                       keep_resident=True)
-        load = serving.summarize(done)
+        load = phase("load", lambda n, c0: serving.poisson_arrivals(n, rate=rate, seed=seed + 1 + c0))
     finally:
         srv.shutdown()
-    return dict(systems=keys, requests=nreq, rhs_per_request="1-16", rel_resid=1e-9, precision="mixed",
+    return dict(systems=keys, requests=nreq, rhs_per_request="1-64", rel_resid=1e-9, precision="mixed",
                 fp32_gathers=bool(gather32),
                 saturated_solves_per_s=burst["solves_per_s"], saturated_p50_ms=burst["p50_ms"],
                 saturated_p99_ms=burst["p99_ms"], offered_requests_per_s=rate,
