@@ -288,6 +288,84 @@ def wide_batch_leg(dd, workloads, torch, steps=3, warmup=1):
     return out
 
 
+# FP64 vector peak (256 CUs at 2.4 GHz) for the ALU-bound assembly kernel
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# FP64 operations per quadrature-point pair of the constant kernel (whose
+# value does not depend on the points): d_m (1 sub), the weight times the
+# kernel value times d_m (5 mul), and per vertex of the pair (6) d_n (1 sub)
+# and the accumulation (1 fma: 2)
+ASM_FLOPS_PER_QP = 24
+
+
+def interacting_pairs_per_row(spec) -> int:
+    """Ordered element pairs (E holding the node, F) that pass the barycentre
+    test, for a free node whose partners all lie on the mesh (the collar is
+    at least the search radius, so every free node has the same count)."""
+    import math
+    h = spec.h
+    r1 = int(math.ceil(spec.delta / h)) + 1
+    thr = math.floor((3.0 * spec.delta / h) ** 2)
+
+    def tri(a, b, t):
+        return [(a, b), (a + 1, b + t), (a + 1 - t, b + 1)]
+
+    m = (0, 0)
+    count = 0
+    for ca in (-1, 0):
+        for cb in (-1, 0):
+            for t in (0, 1):
+                E = tri(ca, cb, t)
+                if m not in E:
+                    continue
+                be = (sum(v[0] for v in E), sum(v[1] for v in E))
+                for fa in range(ca - r1, ca + r1 + 1):
+                    for fb in range(cb - r1, cb + r1 + 1):
+                        for tf in (0, 1):
+                            F = tri(fa, fb, tf)
+                            bf = (sum(v[0] for v in F), sum(v[1] for v in F))
+                            if (be[0] - bf[0]) ** 2 + (be[1] - bf[1]) ** 2 <= thr:
+                                count += 1
+    return count
+
+
+def assembly_leg(dd, workloads, torch, reps=5):
+    """Device assembly (dd_assemble_2d) of the benchmark system's stiffness
+    windows (2D constant kernel, h = 1/128, delta = 0.1, 16 129 rows of 31 x
+    31) against the CPU generator on the host's cores: time, agreement, and
+    the FP64 vector rate of the quadrature (ALU-bound)."""
+    import numpy as np
+    spec = workloads.spec_2d_const()
+    R = workloads.window_radius(spec)
+    W = 2 * R + 1
+    rows = (spec.n - 1) ** 2
+    win = torch.empty(rows * W * W, dtype=torch.float64, device="cuda")
+    args = (spec.n, spec.collar, spec.delta, spec.kernel, spec.phi, spec.s, R, win)
+    dd.dd_assemble_2d(*args)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dd.dd_assemble_2d(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    t0 = time.perf_counter()
+    ref = workloads.assemble_windows(spec)
+    cpu_ms = 1e3 * (time.perf_counter() - t0)
+    got = win.cpu().numpy().reshape(rows, -1)
+    ref = ref.reshape(rows, -1)
+    err = float((np.abs(got - ref) / np.abs(ref).max(axis=1, keepdims=True)).max())
+    pairs = interacting_pairs_per_row(spec) * rows
+    qp = pairs * 49
+    tflops = qp * ASM_FLOPS_PER_QP / (ms * 1e-3) / 1e12
+    return dict(system="2d-const h=1/128 delta=0.1", rows=rows, window=f"{W}x{W}", ms=ms,
+                cpu_generator_ms=cpu_ms, cpu_threads=workloads._nthreads(), speedup=cpu_ms / ms,
+                max_rel_diff_vs_generator=err, element_pairs=pairs, quad_pairs=qp,
+                roofline=dict(bound="alu", achieved=tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=tflops / FP64_VECTOR_PEAK_TFLOPS,
+                              flops_per_quad_pair=ASM_FLOPS_PER_QP))
+
+
 def jacobi_cg_leg(dd, workloads, wl, bt, b, tol, steps, warmup, torch, cpu_seconds):
     """The paper's baseline solver on the same system: CG on the whole matrix
     with diag(A) as preconditioner (section "Considered solver strategies"),
@@ -368,6 +446,8 @@ def main():
                     help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--no-wide-batch", action="store_true",
                     help="skip the mixed-vs-FP64 leg on the 32-column peridynamic batch")
+    ap.add_argument("--no-assembly", action="store_true",
+                    help="skip the device-assembly leg")
     ap.add_argument("--no-jacobi-cg", action="store_true",
                     help="skip the baseline leg (Jacobi-preconditioned CG on the whole system)")
     ap.add_argument("--launch", default="auto", choices=["auto", "kernels", "graph", "persistent"],
@@ -521,6 +601,11 @@ def main():
         "paper_context": "14.6x FETI vs Jacobi-CG solve time, fractional kernel, 48x48 subdomains, "
                          "16M dofs, 2304 Broadwell ranks (different method and machine)",
     }
+    if not args.no_assembly:
+        log("bench: device assembly leg (2D constant kernel, h = 1/128) ...")
+        line["assembly"] = assembly_leg(dd, workloads, torch)
+        log(f"bench: assembly {line['assembly']['ms']:.2f} ms on the device, "
+            f"{line['assembly']['cpu_generator_ms']:.0f} ms for the CPU generator")
     if not args.no_jacobi_cg:
         log("bench: baseline leg (Jacobi-preconditioned CG on the whole system) ...")
         jcg = jacobi_cg_leg(dd, workloads, wl, bt, b, tol, args.steps, args.warmup, torch,

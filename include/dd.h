@@ -292,6 +292,30 @@ const char *dd_last_error(const dd_ctx *ctx);
 /* Release every device and host resource of ctx (NULL is accepted). */
 void dd_destroy(dd_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Assembly of the nonlocal stiffness matrix on the device (the step before
+ * dd_setup), 2D: the unit square with n cells per side split into right
+ * triangles, plus an interaction collar of `collar` cells (Dirichlet volume
+ * constraint).  Entry (m, n') of the bilinear form of eq. bil1,
+ *   int int (psi_m(y) - psi_m(x)) (psi_n'(y) - psi_n'(x)) gamma(x, y) dy dx,
+ * for every free node m, with gamma = phi (kernel 0, eq. constantkernel),
+ * phi |x - y|^-(2 + 2s) (kernel 1, eq. fractionalkernel) or the peridynamic
+ * bond tensor phi (x-y)(x-y)^T / |x-y|^3 (kernel 2, eq. peridynamics; 2x2
+ * blocks), element pairs interacting when their barycentres are within delta
+ * (approximate interaction balls), 7-point degree-5 Gauss rules per triangle
+ * (fractional pairs sharing a vertex: mean of the 7x6- and 6x7-point rules).
+ *   win_dev (D, caller-owned): (n-1)^2 rows, free node (a, b) with a, b in
+ *   collar+1 .. collar+n-1 at row (b-collar-1)(n-1) + (a-collar-1); each row
+ *   a dense window of (2R+1)^2 doubles (4 (2R+1)^2 for kernel 2) for nodes
+ *   (a+da, b+db), |da|, |db| <= R, at (db+R)(2R+1) + (da+R) (kernel 2:
+ *   [row component][window][column component]).  Collar nodes are included.
+ * R >= ceil(delta n) + 2; the window of one row must fit in 64 KiB.
+ * Launched on hip_stream; returns without waiting.  The last bits of an
+ * entry may vary between runs (window entries are summed with atomics).
+ * Errors: DD_EINVAL (message from dd_last_error(NULL)), DD_EHIP. */
+dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel, double phi,
+                         double s, int32_t R, double *win_dev, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_ENOTSPD", 4: 
 EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solve",
             "dd_schur_apply", "dd_get_factor", "dd_get_schur_diag", "dd_autotune",
             "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
-            "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy"]
+            "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy",
+            "dd_assemble_2d"]
 DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
 DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE, DD_PHASE_LOOP = range(5)
 DD_NPHASES = 5
@@ -116,10 +117,12 @@ def load_library(path: str = LIB_PATH):
     lib.dd_last_error.restype = ctypes.c_char_p
     lib.dd_destroy.argtypes = [vp]
     lib.dd_destroy.restype = None
+    lib.dd_assemble_2d.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     for name in ("dd_footprint", "dd_setup", "dd_factor", "dd_solve", "dd_schur_apply",
                  "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
                  "dd_autotune", "dd_batch_begin", "dd_batch_admit", "dd_batch_step",
-                 "dd_batch_retire", "dd_batch_end"):
+                 "dd_batch_retire", "dd_batch_end", "dd_assemble_2d"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -288,6 +291,20 @@ def dd_batch_retire(ctx, slots, u, ld: int) -> list:
 def dd_batch_end(ctx) -> None:
     lib = load_library()
     _check(lib, lib.dd_batch_end(ctx), ctx)
+
+
+def dd_assemble_2d(n: int, collar: int, delta: float, kernel: int, phi: float, s: float, R: int,
+                   win, stream=None) -> None:
+    """Device assembly of the 2D nonlocal stiffness windows into `win` (a
+    float64 CUDA tensor of (n-1)^2 rows of (2R+1)^2 values, 4 (2R+1)^2 for the
+    peridynamic kernel); launched on `stream` (default: the current one)."""
+    lib = load_library()
+    W = 2 * R + 1
+    need = (n - 1) * (n - 1) * W * W * (4 if kernel == 2 else 1)
+    if win.dtype.itemsize != 8 or not win.is_cuda or not win.is_contiguous() or win.numel() != need:
+        raise ValueError(f"win must be a contiguous float64 CUDA tensor of {need} values")
+    _check(lib, lib.dd_assemble_2d(n, collar, delta, kernel, phi, s, R, ctypes.c_void_p(win.data_ptr()),
+                                   _stream_handle(stream)))
 
 
 def dd_set_timing(ctx, phase_mask: int, reset: bool = True) -> None:

@@ -19,6 +19,7 @@
 
 #include "dd.h"
 #include "dd_kernels.h"
+#include "dd_assemble.h"
 #include "dd_persistent.h"
 
 using namespace dd;
@@ -2209,6 +2210,50 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   }
   if (result == DD_ENOCONV) c->err = "tolerance not reached for at least one column";
   return result;
+}
+
+dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel, double phi, double s,
+                         int32_t R, double *win_dev, void *hip_stream) {
+  if (n < 2 || collar < 0 || !(delta > 0.0) || !win_dev)
+    return fail(nullptr, DD_EINVAL, "n < 2, collar < 0, delta <= 0 or win_dev NULL");
+  if (kernel != kKerConst && kernel != kKerFrac && kernel != kKerPD)
+    return fail(nullptr, DD_EINVAL, "unknown kernel");
+  AsmProblem P;
+  P.n = n;
+  P.c = collar;
+  P.N = n + 2 * collar;
+  P.kernel = kernel;
+  P.h = 1.0 / n;
+  P.phi = phi;
+  P.s = s;
+  P.R1 = (int)std::ceil(delta / P.h) + 1;
+  if (R < P.R1 + 1) return fail(nullptr, DD_EINVAL, "R < ceil(delta / h) + 2: the window misses partners");
+  P.R = R;
+  P.W = 2 * R + 1;
+  const double t = 3.0 * delta / P.h;
+  P.thr = (long long)std::floor(t * t);
+  const size_t lds = (size_t)P.W * P.W * (kernel == kKerPD ? 4 : 1) * sizeof(double);
+  if (lds > 65536) return fail(nullptr, DD_EINVAL, "window of more than 64 KiB per row");
+  hipStream_t st = (hipStream_t)hip_stream;
+  static double rules[13][4];             // static: the copy below may run after the return
+  static bool rules_set = false;
+  if (!rules_set) {
+    asm_rule_table(rules);
+    rules_set = true;
+  }
+  hipError_t ec = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_asm_rule), rules, sizeof(rules), 0,
+                                         hipMemcpyHostToDevice, st);
+  if (ec != hipSuccess) return fail(nullptr, DD_EHIP, std::string("quadrature rules: ") + hipGetErrorString(ec));
+  const dim3 grid((unsigned)((n - 1) * (n - 1))), block(kAsmBlock);
+  if (kernel == kKerConst)
+    hipLaunchKernelGGL(k_assemble_2d<kKerConst>, grid, block, lds, st, P, win_dev);
+  else if (kernel == kKerFrac)
+    hipLaunchKernelGGL(k_assemble_2d<kKerFrac>, grid, block, lds, st, P, win_dev);
+  else
+    hipLaunchKernelGGL(k_assemble_2d<kKerPD>, grid, block, lds, st, P, win_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, DD_EHIP, std::string("k_assemble_2d: ") + hipGetErrorString(e));
+  return DD_OK;
 }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ def lib():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dd_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(dd_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
@@ -104,6 +104,25 @@ def test_setup_rejects_bad_batch_width(lib, small):
         with pytest.raises(dd.DDError) as ei:
             dd.dd_setup(small, stream=0, max_nrhs=m)
         assert ei.value.status == dd.DD_EINVAL
+
+
+def test_assemble_rejects_bad_arguments(lib):
+    """Device assembly validates its arguments on the host (no device work):
+    unknown kernel, too few cells, a window that misses partners, a window
+    beyond 64 KiB per row."""
+    dd, L = lib
+    fake = ctypes.c_void_p(256)               # never dereferenced: every call fails validation
+    cases = [
+        ((32, 3, 0.1, 7, 1.0, 0.0, 8), "unknown kernel"),
+        ((1, 3, 0.1, 0, 1.0, 0.0, 8), "n < 2"),
+        ((32, 3, 0.1, 0, 1.0, 0.0, 5), "misses partners"),      # ceil(0.1 * 32) + 2 = 6
+        ((32, 3, 0.1, 0, 1.0, 0.0, 100), "64 KiB"),
+        ((32, 3, 0.1, 2, 1.0, 0.0, 50), "64 KiB"),
+    ]
+    for args, msg in cases:
+        st = L.dd_assemble_2d(*args, fake, None)
+        assert st == dd.DD_EINVAL, args
+        assert msg in L.dd_last_error(None).decode(), args
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -268,20 +268,48 @@ def _symmetrise_lower(A: sp.csr_matrix) -> sp.csr_matrix:
     return S
 
 
+def window_radius(spec: Spec) -> int:
+    """Half width R of the per-row assembly windows."""
+    return int(math.ceil(spec.delta / spec.h)) + 2
+
+
+def assemble_windows(spec: Spec) -> np.ndarray:
+    """The per-row assembly windows of a 2D spec (layout of nl_assemble_2d)."""
+    assert spec.dim == 2
+    lib = _load()
+    R = window_radius(spec)
+    W = 2 * R + 1
+    rowlen = W * W * (4 if spec.kernel == KER_PD else 1)
+    win = np.zeros((spec.n - 1) * (spec.n - 1) * rowlen, dtype=np.float64)
+    rc = lib.nl_assemble_2d(spec.n, spec.collar, spec.delta, spec.kernel, spec.phi, spec.s, R,
+                            _nthreads(), win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError(f"assembly failed ({rc})")
+    return win
+
+
+def windows_to_matrix(spec: Spec, win: np.ndarray, symmetrise: bool = True) -> sp.csr_matrix:
+    """The free-node stiffness matrix of a 2D spec from its assembly windows
+    (e.g. the device assembly's), as assemble() forms it."""
+    A = _window_to_csr(spec, np.ascontiguousarray(win, dtype=np.float64), window_radius(spec))[0]
+    if symmetrise:
+        A = _symmetrise_lower(A)
+    A.sort_indices()
+    return A
+
+
 def assemble(spec: Spec, symmetrise: bool = True) -> Assembled:
     lib = _load()
     n, c = spec.n, spec.collar
-    R = int(math.ceil(spec.delta / spec.h)) + 2
+    R = window_radius(spec)
     W = 2 * R + 1
     if spec.dim == 1:
         win = np.zeros((n - 1) * W, dtype=np.float64)
         rc = lib.nl_assemble_1d(n, c, spec.delta, spec.phi, R, _nthreads(),
                                 win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     else:
-        rowlen = W * W * (4 if spec.kernel == KER_PD else 1)
-        win = np.zeros((n - 1) * (n - 1) * rowlen, dtype=np.float64)
-        rc = lib.nl_assemble_2d(n, c, spec.delta, spec.kernel, spec.phi, spec.s, R,
-                                _nthreads(), win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        win = assemble_windows(spec)
+        rc = 0
     if rc != 0:
         raise RuntimeError(f"assembly failed ({rc})")
     A, Bd, coords, dcoords = _window_to_csr(spec, win, R)
