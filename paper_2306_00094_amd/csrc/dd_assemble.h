@@ -128,7 +128,7 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
       y0 = ly0 * Fx[0] + ly1 * Fx[1] + ly2 * Fx[2];
       y1 = ly0 * Fy[0] + ly1 * Fy[1] + ly2 * Fy[2];
     }
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < NE; ++q) {
       const double lx[3] = {c_asm_rule[QE + q][0], c_asm_rule[QE + q][1], c_asm_rule[QE + q][2]};
       const double dm = am - asm_sel(mE, lx[0], lx[1], lx[2]);
