@@ -290,7 +290,9 @@ __global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double 
     }
     const double wf = mF >= 0 ? 1.0 : 2.0;
     for (int j = 0; j < 3 * NC; ++j) esum[j] += wf * acc[j];           // E's vertices
-    for (int u = 3; u < nu; ++u) {                                      // F's other vertices
+#pragma unroll
+    for (int u = 3; u < 6; ++u) {                                       // F's other vertices
+      if (u >= nu) break;
       const int da = ua[u] - ma, db = ub[u] - mb;
       if (da < -P.R || da > P.R || db < -P.R || db > P.R) continue;
       double v[NC];
