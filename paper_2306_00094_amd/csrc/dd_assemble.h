@@ -108,13 +108,17 @@ __device__ __forceinline__ void asm_tri(int a, int b, int t, int va[3], int vb[3
 // The rule values are uniform (scalar operands).  F's points are the outer
 // loop, so the per-lane choice of F's coordinates happens once per point of
 // F; E's coordinates need no choice (vertex u of E is coordinate u) except
-// for the row's node.
+// for the row's node, chosen once per point of E.
 template <int KER, int QE, int NE, int QF, int NF>
 __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3], const double Ey[3],
                                          const double Fx[3], const double Fy[3], int mE, int mF, int nu,
                                          const int *inF, double scale, double *acc) {
   const double area = 0.5 * P.h * P.h;
   const double cst = area * area * scale * P.phi;
+  double bm[NE];                         // the row node's coordinate at E's points
+#pragma unroll
+  for (int q = 0; q < NE; ++q)
+    bm[q] = asm_sel(mE, c_asm_rule[QE + q][0], c_asm_rule[QE + q][1], c_asm_rule[QE + q][2]);
 #pragma unroll 1
   for (int p = 0; p < NF; ++p) {
     const double ly0 = c_asm_rule[QF + p][0], ly1 = c_asm_rule[QF + p][1], ly2 = c_asm_rule[QF + p][2];
@@ -131,7 +135,7 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const double lx[3] = {c_asm_rule[QE + q][0], c_asm_rule[QE + q][1], c_asm_rule[QE + q][2]};
-      const double dm = am - asm_sel(mE, lx[0], lx[1], lx[2]);
+      const double dm = am - bm[q];
       const double w = c_asm_rule[QE + q][3] * wp;
       double g = 0.0, s0 = 0.0, s1 = 0.0;
       if constexpr (KER == kKerConst) {
@@ -242,9 +246,10 @@ __global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double 
     if (fa0 < 0 || fb0 < 0 || fa0 >= P.N || fb0 >= P.N) continue;
     int fa[3], fb[3];
     asm_tri(fa0, fb0, tf, fa, fb);
-    const long long dA = (long long)(ea[0] + ea[1] + ea[2]) - (fa[0] + fa[1] + fa[2]);
-    const long long dB = (long long)(eb[0] + eb[1] + eb[2]) - (fb[0] + fb[1] + fb[2]);
-    if (dA * dA + dB * dB > P.thr) continue;
+    // (|dA|, |dB| <= 3 (2 R1 + 2): 32-bit products suffice)
+    const int dA = (ea[0] + ea[1] + ea[2]) - (fa[0] + fa[1] + fa[2]);
+    const int dB = (eb[0] + eb[1] + eb[2]) - (fb[0] + fb[1] + fb[2]);
+    if ((long long)(dA * dA + dB * dB) > P.thr) continue;
     // union of the vertices of E and F: E's three, then F's not in E
     int inF[6], ua[6], ub[6];
     for (int j = 3; j < 6; ++j) inF[j] = -1;
