@@ -171,3 +171,34 @@ def test_undecomposed_problem_passes_host_checks(lib):
     with pytest.raises(dd.DDError) as ei:
         dd.dd_setup(bad, stream=0, max_nrhs=1)
     assert ei.value.status == dd.DD_EINVAL and "not injective" in str(ei.value)
+
+
+def test_bench_assembly_work_count_brute_force():
+    """The element-pair count behind the assembly leg's roofline (one free
+    node's interacting pairs times the number of rows) equals a brute-force
+    count over every free node, every element holding it and every element
+    of the mesh, with the barycentre test written in real coordinates."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec_b = importlib.util.spec_from_file_location("bench_mod2", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec_b)
+    spec_b.loader.exec_module(bench)
+    for spec in (W.spec_2d_const(n=32, cuts=(2, 2)), W.spec_2d_frac(n=28, delta=0.15, cuts=(2, 2))):
+        n, c, h = spec.n, spec.collar, spec.h
+        N = n + 2 * c
+        # barycentres of all triangles of the mesh (with collar), real coordinates
+        a, b = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+        a, b = a.ravel(), b.ravel()
+        bary = np.concatenate([np.stack([(3 * a + 2) / 3, (3 * b + 1) / 3], 1),      # lower right
+                               np.stack([(3 * a + 1) / 3, (3 * b + 2) / 3], 1)]) * h  # upper left
+        total = 0
+        for mb in range(c + 1, c + n):
+            for ma in range(c + 1, c + n):
+                # the six triangles holding node (ma, mb)
+                es = [((ma - 1) + 2 / 3, (mb - 1) + 1 / 3), ((ma - 1) + 1 / 3, (mb - 1) + 2 / 3),
+                      (ma + 1 / 3, (mb - 1) + 2 / 3), ((ma - 1) + 2 / 3, mb + 1 / 3),
+                      (ma + 2 / 3, mb + 1 / 3), (ma + 1 / 3, mb + 2 / 3)]
+                for ex, ey in es:
+                    d2 = (bary[:, 0] - ex * h) ** 2 + (bary[:, 1] - ey * h) ** 2
+                    total += int(np.count_nonzero(d2 <= spec.delta ** 2 * (1 + 1e-12)))
+        assert bench.interacting_pairs_per_row(spec) * (n - 1) ** 2 == total
