@@ -147,7 +147,7 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
         // (r2 = 0 only where the points coincide, where d_m = 0 as well)
         if (r2 > 0.0) {
           if constexpr (KER == kKerPD) g = w * dm / (r2 * sqrt(r2));
-          else g = w * dm * pow(r2, -(1.0 + P.s));
+          else g = w * dm * exp2(-(1.0 + P.s) * log2(r2));   // |x - y|^-(2 + 2s); r2 > 0
         }
       }
 #pragma unroll
