@@ -137,7 +137,7 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
       const double lx[3] = {c_asm_rule[QE + q][0], c_asm_rule[QE + q][1], c_asm_rule[QE + q][2]};
       const double dm = am - bm[q];
       const double w = c_asm_rule[QE + q][3] * wp;
-      double g = 0.0, s0 = 0.0, s1 = 0.0;
+      double g = 0.0, s0 = 0.0, s1 = 0.0, b00 = 0.0, b01 = 0.0, b11 = 0.0;
       if constexpr (KER == kKerConst) {
         g = w * dm;
       } else {
@@ -149,22 +149,29 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
           if constexpr (KER == kKerPD) g = w * dm / (r2 * sqrt(r2));
           else g = w * dm * exp2(-(1.0 + P.s) * log2(r2));   // |x - y|^-(2 + 2s); r2 > 0
         }
+        if constexpr (KER == kKerPD) {
+          b00 = g * s0 * s0;
+          b01 = g * s0 * s1;
+          b11 = g * s1 * s1;
+        }
       }
 #pragma unroll
       for (int u = 0; u < 6; ++u) {
         if (u >= nu) break;
         const double dn = u < 3 ? au[u] - lx[u < 3 ? u : 0] : au[u];
-        if constexpr (KER == kKerPD) {
-          const double t = g * dn;
-          acc[4 * u + 0] += t * s0 * s0;
-          acc[4 * u + 1] += t * s0 * s1;
-          acc[4 * u + 2] += t * s0 * s1;
-          acc[4 * u + 3] += t * s1 * s1;
+        if constexpr (KER == kKerPD) {     // (the [1][0] entry is copied from [0][1] at the end)
+          acc[4 * u + 0] += dn * b00;
+          acc[4 * u + 1] += dn * b01;
+          acc[4 * u + 3] += dn * b11;
         } else {
           acc[u] += g * dn;
         }
       }
     }
+  }
+  if constexpr (KER == kKerPD) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) acc[4 * u + 2] = acc[4 * u + 1];
   }
 }
 
