@@ -125,6 +125,13 @@ typedef struct {
                             they multiply (half the gathered bytes; pays off for wide
                             batches): -1 = automatic (dd_solve: the autotuned schedule, else
                             off; batches: off), 0 = off, 1 = on */
+  int32_t tiles;         /* batches of 8 or more columns: coupling products on 16x16 tiles and
+                            interior solves on the matrix cores (the direction kept by its own
+                            kernel); a column's result then differs in rounding from the
+                            narrow-batch kernels but does not depend on the width among 8..64:
+                            -1 = automatic (the autotuned schedule, else off), 0 = off,
+                            1 = on (ignored below 8 columns, with the triangular-sweep apply,
+                            the persistent launch, or a context set up for fewer than 8) */
 } dd_solve_opts;
 
 typedef struct {
@@ -138,7 +145,7 @@ typedef struct {
 
 /* Fill opts with defaults: tol 1e-10, max_it 1000, precond 1, max_refine 8,
  * inner_tol 0 (automatic), fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1,
- * gather32 -1 (automatic). */
+ * gather32 -1 (automatic), tiles -1 (automatic). */
 void dd_default_opts(dd_solve_opts *opts);
 
 /* Device bytes a context for `prob` would hold (matrices, factors for
@@ -202,7 +209,9 @@ typedef struct {
                                 solve), clear: four (K_IG, interior solve, interface rows,
                                 update); bit 1 (DD_MIXED only): the FP32-data products
                                 gather FP32 copies of the vectors they multiply (half the
-                                gathered bytes; pays off for wide batches) */
+                                gathered bytes; pays off for wide batches); bit 2: the tiled
+                                matrix-core products of batches of 8 or more columns
+                                (dd_solve_opts.tiles) */
 } dd_tune_result;
 
 /* Autotuner: time every candidate schedule of the CG loop on this context and

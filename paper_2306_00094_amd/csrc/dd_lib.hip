@@ -19,6 +19,7 @@
 
 #include "dd.h"
 #include "dd_kernels.h"
+#include "dd_tiles.h"
 #include "dd_assemble.h"
 #include "dd_persistent.h"
 
@@ -42,6 +43,8 @@ struct Ops {
   void *g_val = nullptr;   // [K_GG | K_GI] values (T)
   double *diag = nullptr;  // diag(S)
   double *dinv = nullptr;  // 1 / diag(S)
+  void *tI_val = nullptr;  // 16x16 tiles of K_IG (T), wide batches
+  void *tG_val = nullptr;  // 16x16 tiles of [K_GG | K_GI] (T), wide batches
   bool ready = false;
 };
 
@@ -95,6 +98,18 @@ struct dd_ctx {
   long long *d_koff = nullptr;
   int *d_ig_ptr = nullptr, *d_ig_col = nullptr;
   int *d_g_ptr = nullptr, *d_g_split = nullptr, *d_g_col = nullptr;
+  // wide batches on the matrix cores (built when max_nrhs >= 8 and there are
+  // interiors): 16x16 tiles of K_IG over 16-row blocks of the interior rows, of
+  // [K_GG | K_GI] over 16-row blocks of the interface rows (tiles [ptr, split)
+  // multiply p, [split, ptr+1) multiply w), and the (subdomain, 16-row tile)
+  // work items of the interior solve
+  bool tiles = false;
+  int t_nrbI = 0, t_nrbG = 0, n_dit = 0;
+  size_t t_nI = 0, t_nG = 0;
+  int *d_tI_ptr = nullptr, *d_tI_col = nullptr;
+  int *d_tG_ptr = nullptr, *d_tG_split = nullptr, *d_tG_col = nullptr;
+  double *d_tI_val64 = nullptr, *d_tG_val64 = nullptr;
+  int2 *d_dit = nullptr;
   double *d_ig_val64 = nullptr, *d_g_val64 = nullptr, *d_kii64 = nullptr;
   Ops op[2];
   Work w{};
@@ -122,6 +137,7 @@ struct dd_ctx {
   int panel_potrf = 0;        // 1: Cholesky by two launches per 16-wide panel
   int flow_spin = kFlowSpin;  // bound of each wait in the single-launch Cholesky (sleeps)
   int gather32 = 0;           // 1: untuned mixed three-launch solves gather FP32 vector copies
+  int tune_persistent = 0;    // 1: the autotuner also times the cooperative persistent launch
   Gather32 g32{};             // FP32 gather copies of the three-launch iteration being launched
   int *d_flow = nullptr;      // single-launch Cholesky: ticket, timeout, done flags
   double *fac_x = nullptr, *fac_packed = nullptr, *fac_dloc = nullptr;   // factor work space
@@ -273,6 +289,105 @@ dd_status validate(const dd_problem *p) {
   return DD_OK;
 }
 
+// Block CSR of 16x16 tiles over 16-row blocks.  Row i's entries [ptr[i], mid)
+// (columns in [0, ncol1)) go to the first part of its block, entries
+// [mid, ptr[i+1]) (columns in [0, ncol2)) to the second, mid = split[i] (or
+// ptr[i+1] when split is null).  Within a part the tiles are in increasing
+// column-block order; values are placed in the A-operand order of the
+// 16x16x4 matrix instructions (dd_tiles.h), zeros elsewhere.
+struct TileSet {
+  std::vector<int> ptr, split, col;
+  std::vector<double> val;
+};
+constexpr int kTileMinLd = 8;     // narrowest batch served by the tiled products
+
+size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, const double *val,
+                   int ncol1, int ncol2, TileSet *ts) {
+  const int nrb = (nrows + kT - 1) / kT;
+  std::vector<int> slot1((ncol1 + kT - 1) / kT + 1, -1), slot2((ncol2 + kT - 1) / kT + 1, -1);
+  std::vector<int> cb1, cb2;
+  size_t ntiles = 0;
+  if (ts) {
+    ts->ptr.assign(nrb + 1, 0);
+    ts->split.assign(nrb, 0);
+    ts->col.clear();
+    ts->val.clear();
+  }
+  for (int rb = 0; rb < nrb; ++rb) {
+    const int i0 = rb * kT, i1 = std::min(nrows, i0 + kT);
+    cb1.clear();
+    cb2.clear();
+    for (int i = i0; i < i1; ++i) {
+      const int mid = split ? split[i] : ptr[i + 1];
+      for (int a = ptr[i]; a < mid; ++a) {
+        const int cb = col[a] / kT;
+        if (slot1[cb] < 0) { slot1[cb] = 0; cb1.push_back(cb); }
+      }
+      for (int a = mid; a < ptr[i + 1]; ++a) {
+        const int cb = col[a] / kT;
+        if (slot2[cb] < 0) { slot2[cb] = 0; cb2.push_back(cb); }
+      }
+    }
+    std::sort(cb1.begin(), cb1.end());
+    std::sort(cb2.begin(), cb2.end());
+    const size_t base = ntiles;
+    for (size_t t = 0; t < cb1.size(); ++t) slot1[cb1[t]] = (int)(base + t);
+    for (size_t t = 0; t < cb2.size(); ++t) slot2[cb2[t]] = (int)(base + cb1.size() + t);
+    ntiles += cb1.size() + cb2.size();
+    if (ts) {
+      for (int cb : cb1) ts->col.push_back(cb);
+      ts->split[rb] = (int)ts->col.size();
+      for (int cb : cb2) ts->col.push_back(cb);
+      ts->ptr[rb + 1] = (int)ts->col.size();
+      ts->val.resize(ntiles * 256, 0.0);
+      for (int i = i0; i < i1; ++i) {
+        const int mid = split ? split[i] : ptr[i + 1];
+        for (int a = ptr[i]; a < ptr[i + 1]; ++a) {
+          const int t = a < mid ? slot1[col[a] / kT] : slot2[col[a] / kT];
+          const int ii = i - i0, kk = col[a] % kT;
+          // T[ii][kk] is held by lane (kk % 4) * 16 + ii at step kk / 4
+          ts->val[(size_t)t * 256 + 4 * ((kk % 4) * kT + ii) + kk / 4] += val[a];
+        }
+      }
+    }
+    for (int cb : cb1) slot1[cb] = -1;
+    for (int cb : cb2) slot2[cb] = -1;
+  }
+  return ntiles;
+}
+
+// Tiles of a problem (interior rows x interface columns, interface rows x
+// [interface | interior] columns) counted from its CSR input.
+void count_problem_tiles(const dd_problem *p, size_t *nI, size_t *nG) {
+  std::vector<int> iptr(1, 0), icol;
+  int NI = 0;
+  for (int k = 0; k < p->n_sub; ++k) NI += p->sub[k].n_i;
+  iptr.reserve(NI + 1);
+  std::vector<std::vector<int>> gi(p->n_gamma);
+  int r = 0;
+  for (int k = 0; k < p->n_sub; ++k) {
+    const dd_subdomain &s = p->sub[k];
+    for (int i = 0; i < s.n_i; ++i, ++r) {
+      for (int a = s.kig_rowptr[i]; a < s.kig_rowptr[i + 1]; ++a) {
+        const int g = s.g_map[s.kig_col[a]];
+        icol.push_back(g);
+        gi[g].push_back(r);
+      }
+      iptr.push_back((int)icol.size());
+    }
+  }
+  *nI = build_tiles(NI, iptr.data(), nullptr, icol.data(), nullptr, p->n_gamma, 1, nullptr);
+  std::vector<int> gptr(1, 0), gsplit, gcol;
+  for (int j = 0; j < p->n_gamma; ++j) {
+    for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a) gcol.push_back(p->kgg_col[a]);
+    gsplit.push_back((int)gcol.size());
+    for (int v : gi[j]) gcol.push_back(v);
+    gptr.push_back((int)gcol.size());
+  }
+  *nG = build_tiles(p->n_gamma, gptr.data(), gsplit.data(), gcol.data(), nullptr, p->n_gamma,
+                    std::max(1, NI), nullptr);
+}
+
 size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   size_t NI = 0, kt = 0, nig = 0;
   for (int k = 0; k < p->n_sub; ++k) {
@@ -288,7 +403,17 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   b += kt * 8;                                                        // K_II
   size_t s = prec == DD_MIXED ? 4 : 8;
   b += 2 * kt * s + p->n_gamma * 16;                                  // L, K^-1, diag
-  if (prec == DD_MIXED) b += (nig + ngg + nig) * 4;                   // FP32 values
+  if (prec == DD_MIXED) {
+    b += (nig + ngg + nig) * 4;                                       // FP32 values
+    b += 2 * kt * 8 + p->n_gamma * 16;    // FP64 factors of the fallback (formed on first use)
+  }
+  if (max_nrhs >= kTileMinLd && p->n_sub > 0 && p->n_gamma > 0) {    // tiles of the wide batches
+    size_t tI = 0, tG = 0;
+    count_problem_tiles(p, &tI, &tG);
+    const size_t nrbI = (NI + kT - 1) / kT, nrbG = (p->n_gamma + kT - 1) / kT;
+    b += (tI + tG) * (4 + 256 * 8) + (nrbI + 1) * 4 + (2 * nrbG + 1) * 4 + NI * 8 / kT + 64;
+    if (prec == DD_MIXED) b += (tI + tG) * 256 * 4;
+  }
   b += (12 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                   // work vectors
   b += (4 * (size_t)p->n_gamma + NI) * ld * 4;                        // FP32 gather copies
   size_t chunks = std::max<size_t>((p->n_gamma + kGChunk - 1) / kGChunk,
@@ -522,6 +647,73 @@ void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const doub
     gamma_rows<float>(c, (const float *)c->op[1].g_val, p, z, ld, base, c1, c2, out, dot, pout, dinv, qd);
 }
 
+// ------------------------------------------------- tiled wide batches --
+// (batches of kTileMinLd or more columns; dd_tiles.h)
+template <typename VT, int NCB, bool DOT>
+void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const double *x1,
+                        const double *x2, int ld, const double *base, double c1, double c2,
+                        double *out) {
+  const int nrb = interface_rows ? c->t_nrbG : c->t_nrbI;
+  const int nrows = interface_rows ? c->n_gamma : c->NI;
+  if (nrb <= 0) return;
+  const dim3 g(grid_for(nrb, kWavesPerBlock)), b(kBlock);
+  const int *ptr = interface_rows ? c->d_tG_ptr : c->d_tI_ptr;
+  const int *split = interface_rows ? c->d_tG_split : nullptr;
+  const int *col = interface_rows ? c->d_tG_col : c->d_tI_col;
+  const int n2 = interface_rows ? c->NI : 0;
+  if (DOT) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums of p^T q
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
+    hipExtLaunchKernelGGL((k_tile_rows<VT, NCB, DOT>), g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr,
+                          split, col, val, x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
+  else
+    hipLaunchKernelGGL((k_tile_rows<VT, NCB, DOT>), g, b, 0, c->stream, nrb, nrows, ptr, split, col, val,
+                       x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
+}
+
+// out = base + c1 * (tiled K_IG or K_GG) x1 + c2 * (tiled K_GI) x2 with the
+// coupling values of `prec` (interface_rows: [K_GG | K_GI], else K_IG).
+template <bool DOT>
+void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const double *x2, int ld,
+               const double *base, double c1, double c2, double *out) {
+  // FP64 values straight from the setup copies: the FP64 residual of the mixed
+  // path runs on contexts whose FP64 operators were never formed
+  const void *v = prec == DD_FP64 ? (interface_rows ? (const void *)c->d_tG_val64 : (const void *)c->d_tI_val64)
+                                  : (interface_rows ? c->op[prec].tG_val : c->op[prec].tI_val);
+#define DD_TR(NCB)                                                                                     \
+  if (prec == DD_FP64)                                                                                 \
+    launch_tile_rows_t<double, NCB, DOT>(c, interface_rows, (const double *)v, x1, x2, ld, base, c1, c2, out); \
+  else                                                                                                 \
+    launch_tile_rows_t<float, NCB, DOT>(c, interface_rows, (const float *)v, x1, x2, ld, base, c1, c2, out)
+  if (ld <= 16) { DD_TR(1); }
+  else if (ld <= 32) { DD_TR(2); }
+  else { DD_TR(4); }
+#undef DD_TR
+}
+
+// w = base + sign * B y for the dense interior blocks B (kinv of `prec`, or the
+// FP64 blocks K_II themselves when kii is set).
+void dense_tiles(dd_ctx *c, int prec, bool kii, const double *y, int ld, const double *base, double sign,
+                 double *w) {
+  if (c->n_dit <= 0) return;
+  const dim3 g(grid_for(c->n_dit, kWavesPerBlock)), b(kBlock);
+#define DD_DT(MT, NCB, BLK)                                                                                \
+  hipLaunchKernelGGL((k_dense_tiles<MT, NCB>), g, b, 0, c->stream, c->n_dit, c->d_dit, (const MT *)(BLK),   \
+                     c->d_koff, c->d_ioff, c->d_ni, y, ld, base, sign, w)
+  if (kii || prec == DD_FP64) {
+    const void *blk = kii ? (const void *)c->d_kii64 : c->op[DD_FP64].kinv;
+    if (ld <= 16) DD_DT(double, 1, blk);
+    else if (ld <= 32) DD_DT(double, 2, blk);
+    else DD_DT(double, 4, blk);
+  } else {
+    const void *blk = c->op[DD_MIXED].kinv;
+    if (ld <= 16) DD_DT(float, 1, blk);
+    else if (ld <= 32) DD_DT(float, 2, blk);
+    else DD_DT(float, 4, blk);
+  }
+#undef DD_DT
+}
+
 // ------------------------------------------------ three-launch iteration --
 // Launches K1 and K2 of CG iteration k (see k_cg_kig): K2's state
 // workgroup, one workgroup per 64-row interface slice, then the row
@@ -728,6 +920,12 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                        (float *)o.ig_val);
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_g, c->d_g_val64,
                        (float *)o.g_val);
+    if (c->tiles) {
+      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nI * 256, c->d_tI_val64,
+                         (float *)o.tI_val);
+      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nG * 256, c->d_tG_val64,
+                         (float *)o.tG_val);
+    }
     HIPCHK(c, hipGetLastError());
   }
   if (c->n_gamma > 0 && !(c->n_sub > 0 && c->use_mfma))
@@ -774,9 +972,15 @@ dd_status ensure_ops(dd_ctx *c, int pi) {
   if (pi == DD_FP64) {
     o.ig_val = c->d_ig_val64;
     o.g_val = c->d_g_val64;
+    o.tI_val = c->d_tI_val64;
+    o.tG_val = c->d_tG_val64;
   } else {
     TRY(al(&o.ig_val, c->nnz_ig * 4));
     TRY(al(&o.g_val, c->nnz_g * 4));
+    if (c->tiles) {
+      TRY(al(&o.tI_val, c->t_nI * 256 * 4));
+      TRY(al(&o.tG_val, c->t_nG * 256 * 4));
+    }
   }
   return DD_OK;
 }
@@ -921,6 +1125,13 @@ dd_status launch_persistent(dd_ctx *c, int prec, int ld, int nrhs, int max_it, i
   }
 }
 
+// The tiled wide-batch products serve this solve: schedule bit 2, tiles built,
+// a batch of kTileMinLd or more columns, explicit inverses, no persistent launch.
+bool use_tiles(const dd_ctx *c, int sched, int ld, int apply, int launch) {
+  return (sched & 4) && c->tiles && ld >= kTileMinLd && apply != DD_APPLY_TRSM &&
+         launch != DD_LAUNCH_PERSISTENT && c->NI > 0 && c->n_gamma > 0;
+}
+
 // One substructuring solve on DD-layout data:
 //   g = bG - K_GI K_II^{-1} bI;  CG on S x = g until ||r_c||^2 <= stop2[c];
 //   uI = K_II^{-1} (bI - K_IG x);  uG = x.
@@ -930,20 +1141,29 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
                      double *uG, int ld, int nrhs, const CoreOpts &o) {
   Work &w = c->w;
   const Ops &op = c->op[prec];
+  // Wide batches on the matrix cores (schedule bit 2): tiled coupling products
+  // and interior solves, the direction kept in memory by its own kernel.
+  const bool tl = use_tiles(c, o.cg3, ld, o.apply, o.launch);
   // condensation (eq. subForcing summed over subdomains): r = bG - K_GI K_II^{-1} bI
-  interior_solve(c, prec, o.apply, bI, w.wI, ld);
-  gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
+  if (tl) {
+    dense_tiles(c, prec, false, bI, ld, nullptr, 1.0, w.wI);
+    tile_rows<false>(c, prec, true, nullptr, w.wI, ld, bG, 0.0, -1.0, w.rG);
+  } else {
+    interior_solve(c, prec, o.apply, bI, w.wI, ld);
+    gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
+  }
   // Three launches per iteration where the interiors exist and their inverse
   // is applied (k_cg_kig); otherwise four (K_IG, interior solve, interface
   // rows, update), which the persistent kernel also runs.
-  const bool cg3 = (o.cg3 & 1) && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
+  const bool cg3 = !tl && (o.cg3 & 1) && c->NI > 0 && c->n_gamma > 0 && o.apply != DD_APPLY_TRSM &&
                    o.launch != DD_LAUNCH_PERSISTENT && !c->classic_cg;
+  const int dkv = (c->direction_kernel || tl) ? 1 : 0;
   // FP32 gather copies for the FP32-data products (mixed): in the three-launch
   // iteration, or in the four-launch one with the direction kept by its kernel
-  const bool g32 = (o.cg3 & 2) && prec == DD_MIXED && c->NI > 0 && c->n_gamma > 0 &&
+  const bool g32 = !tl && (o.cg3 & 2) && prec == DD_MIXED && c->NI > 0 && c->n_gamma > 0 &&
                    o.apply != DD_APPLY_TRSM && o.launch != DD_LAUNCH_PERSISTENT &&
                    (cg3 || c->direction_kernel);
-  const int sched = (cg3 ? 1 : 0) | (g32 ? 2 : 0);
+  const int sched = (cg3 ? 1 : 0) | (g32 ? 2 : 0) | (tl ? 4 : 0);
   struct ResetG32 { dd_ctx *c; ~ResetG32() { c->g32 = Gather32{}; } } reset_g32{c};
   c->tev_cg3_ld = cg3 ? ld : 0;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
@@ -957,7 +1177,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // interior solve) also written in FP32 for the gathers of the loop below
     if (g32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
-                  c->direction_kernel, nullptr, 0);
+                  dkv, nullptr, 0);
   }
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
@@ -986,24 +1206,36 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // (active columns + 1) from the update kernel when non-null
   auto iteration = [&](double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
-    const bool dk = c->direction_kernel != 0;
+    const bool dk = dkv != 0;
     Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
     if (dk && g32) P.x32 = w.p32;
     // S p (eq. subSchurComplement, summed): y = K_IG p, w = K_II^{-1} y, q = K_GG p - K_GI w
     // (formed at the K_IG gathers, which also store it into pB for the rest of
     // the iteration; without interiors the interface rows form and store it)
     const bool p_at_gamma = !dk && c->NI == 0;
-    {
-      PhaseTimer t(c, DD_PHASE_KIG);
-      kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI, dk ? nullptr : pB_);
+    if (tl) {
+      {
+        PhaseTimer t(c, DD_PHASE_KIG);
+        tile_rows<false>(c, prec, false, pA_, nullptr, ld, nullptr, 1.0, 0.0, w.yI);
+      }
+      {
+        PhaseTimer t(c, DD_PHASE_INTERIOR);
+        dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, w.wI);
+      }
+      tile_rows<true>(c, prec, true, pA_, w.wI, ld, nullptr, 1.0, -1.0, w.qG);
+    } else {
+      {
+        PhaseTimer t(c, DD_PHASE_KIG);
+        kig_apply(c, prec, P, ld, nullptr, 1.0, w.yI, dk ? nullptr : pB_);
+      }
+      {
+        PhaseTimer t(c, DD_PHASE_INTERIOR);
+        interior_solve(c, prec, o.apply, w.yI, w.wI, ld);
+      }
+      // (timed, when asked, by events the launch itself records: kernel_events)
+      gamma_apply(c, prec, (dk || p_at_gamma) ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1,
+                  p_at_gamma ? pB_ : nullptr);
     }
-    {
-      PhaseTimer t(c, DD_PHASE_INTERIOR);
-      interior_solve(c, prec, o.apply, w.yI, w.wI, ld);
-    }
-    // (timed, when asked, by events the launch itself records: kernel_events)
-    gamma_apply(c, prec, (dk || p_at_gamma) ? P : plain(pB_), w.wI, ld, nullptr, 1.0, -1.0, w.qG, 1,
-                p_at_gamma ? pB_ : nullptr);
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
@@ -1033,7 +1265,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     hipGraphExec_t exec = nullptr;
     for (auto &g : c->graphs)
       if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
-          g.dk == c->direction_kernel && g.iters == G && g.x == uG && g.cg3 == sched)
+          g.dk == dkv && g.iters == G && g.x == uG && g.cg3 == sched)
         exec = g.exec;
     if (!exec) {
       if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1063,7 +1295,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       (void)hipGraphDestroy(graph);
       if (ee != hipSuccess)
         return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
-      c->graphs.push_back({prec, ld, o.apply, o.precond, c->direction_kernel, G, sched, uG, exec});
+      c->graphs.push_back({prec, ld, o.apply, o.precond, dkv, G, sched, uG, exec});
     }
     // replay; look at the result of launch n - 1 while launch n runs.  The
     // number of active columns only decreases, so a later value is as good.
@@ -1124,8 +1356,13 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   }
   c->g32 = Gather32{};
   // back substitution (eq. backwardSubstitution): uI = K_II^{-1} (bI - K_IG uG)
-  kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
-  interior_solve(c, prec, o.apply, w.yI, uI, ld);
+  if (tl) {
+    tile_rows<false>(c, prec, false, uG, nullptr, ld, bI, -1.0, 0.0, w.yI);
+    dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, uI);
+  } else {
+    kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
+    interior_solve(c, prec, o.apply, w.yI, uI, ld);
+  }
   HIPCHK(c, hipGetLastError());
   return DD_OK;
 }
@@ -1161,7 +1398,13 @@ dd_status fetch_state(dd_ctx *c, StateBlock *h) {
 // FP64 full-system residual in DD layout: rI = bI - K_II uI - K_IG uG,
 // rG = bG - K_GI uI - K_GG uG.
 void full_residual(dd_ctx *c, const double *bI, const double *bG, const double *uI,
-                   const double *uG, double *rI, double *rG, int ld) {
+                   const double *uG, double *rI, double *rG, int ld, bool tiles = false) {
+  if (tiles) {      // the tiled products (FP64 values); rI passes through y
+    tile_rows<false>(c, DD_FP64, false, uG, nullptr, ld, bI, -1.0, 0.0, c->w.yI);
+    dense_tiles(c, DD_FP64, true, uI, ld, c->w.yI, -1.0, rI);
+    tile_rows<false>(c, DD_FP64, true, uG, uI, ld, bG, -1.0, -1.0, rG);
+    return;
+  }
   dense_rows<double, double>(c, c->d_kii64, uI, ld, bI, -1.0, rI, c->d_ig_ptr, c->d_ig_col,
                              c->d_ig_val64, uG);
   gamma_rows<double>(c, c->d_g_val64, plain(uG), uI, ld, bG, -1.0, -1.0, rG, 0, nullptr);
@@ -1185,6 +1428,7 @@ void dd_default_opts(dd_solve_opts *o) {
   o->check_every = 0;
   o->verify = 1;
   o->gather32 = -1;
+  o->tiles = -1;
 }
 
 const char *dd_last_error(const dd_ctx *ctx) {
@@ -1242,6 +1486,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if (const char *e = getenv("DD_PANEL_POTRF")) c->panel_potrf = atoi(e) ? 1 : 0;
   if (const char *e = getenv("DD_FLOW_SPIN")) c->flow_spin = std::max(0, std::min(atoi(e), kFlowSpin));
   if (const char *e = getenv("DD_GATHER32")) c->gather32 = atoi(e) ? 1 : 0;
+  if (const char *e = getenv("DD_TUNE_PERSISTENT")) c->tune_persistent = atoi(e) ? 1 : 0;
   {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
@@ -1435,6 +1680,37 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   if ((s = upload(c, &c->d_g_split, gsplit.data(), c->n_gamma)) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_g_col, gcol.data(), gcol.size())) != DD_OK) return bail(s);
   if ((s = upload(c, &c->d_g_val64, gval.data(), gval.size())) != DD_OK) return bail(s);
+  // tiles of the wide-batch products (matrix cores)
+  if (c->ldmax >= kTileMinLd && c->n_sub > 0 && c->n_gamma > 0 && !getenv("DD_NO_TILES")) {
+    TileSet ti, tg;
+    c->t_nI = build_tiles(NI, igptr.data(), nullptr, igcol.data(), igval.data(), c->n_gamma, 1, &ti);
+    c->t_nG = build_tiles(c->n_gamma, gptr.data(), gsplit.data(), gcol.data(), gval.data(), c->n_gamma,
+                          std::max(1, NI), &tg);
+    c->t_nrbI = (NI + kT - 1) / kT;
+    c->t_nrbG = (c->n_gamma + kT - 1) / kT;
+    std::vector<int2> items;
+    std::vector<int> order(c->n_sub);
+    for (int k = 0; k < c->n_sub; ++k) order[k] = k;
+    // largest blocks first: their work items are the longest
+    std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return c->ni[a2] > c->ni[b2]; });
+    for (int k : order)
+      for (int I = 0; I < (c->ni[k] + kT - 1) / kT; ++I) items.push_back(make_int2(k, I));
+    c->n_dit = (int)items.size();
+    for (TileSet *t : {&ti, &tg})          // uploads need at least one element
+      if (t->col.empty()) {
+        t->col.push_back(0);
+        t->val.assign(256, 0.0);
+      }
+    if ((s = upload(c, &c->d_tI_ptr, ti.ptr.data(), ti.ptr.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tI_col, ti.col.data(), ti.col.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tI_val64, ti.val.data(), ti.val.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tG_ptr, tg.ptr.data(), tg.ptr.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tG_split, tg.split.data(), tg.split.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tG_col, tg.col.data(), tg.col.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_tG_val64, tg.val.data(), tg.val.size())) != DD_OK) return bail(s);
+    if ((s = upload(c, &c->d_dit, items.data(), items.size())) != DD_OK) return bail(s);
+    c->tiles = true;
+  }
   // work vectors
   size_t nG = (size_t)std::max(1, c->n_gamma) * c->ldmax, nI = (size_t)std::max(1, NI) * c->ldmax;
   Work &w = c->w;
@@ -1604,8 +1880,17 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 2});
     cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 2});
   }
+  // batches of kTileMinLd or more columns: the tiled matrix-core products
+  if (c->tiles && next_pow2(nrhs) >= kTileMinLd) {
+    cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 4});
+    cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 4});
+  }
   cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2, 0});
-  cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0, 0});
+  // The cooperative persistent launch is timed only on request
+  // (DD_TUNE_PERSISTENT=1): it has never won, and its first launch creates the
+  // runtime's cooperative-dispatch state, which then lives until the process
+  // exits.
+  if (c->tune_persistent) cands.push_back({DD_APPLY_INV, DD_LAUNCH_PERSISTENT, 0, 0, 0});
   const int saved_dk = c->direction_kernel;
   int lg = 0;
   while ((1 << lg) < next_pow2(nrhs)) ++lg;
@@ -2053,12 +2338,15 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   }
   if (c->force_cg3 >= 0) use_cg3 = c->force_cg3;
   if (c->gather32 || o.gather32 == 1) use_cg3 |= 2;
-  if (o.gather32 == 0) use_cg3 &= 1;
-  if (prec != DD_MIXED) use_cg3 &= 1;     // FP32 gathers serve FP32 data only
+  if (o.gather32 == 0) use_cg3 &= ~2;
+  if (prec != DD_MIXED) use_cg3 &= ~2;    // FP32 gathers serve FP32 data only
+  if (o.tiles == 1) use_cg3 |= 4;
+  if (o.tiles == 0) use_cg3 &= ~4;
   CoreOpts co{o.max_it, o.precond, o.apply == DD_APPLY_TRSM ? DD_APPLY_TRSM : DD_APPLY_INV,
               o.check_every,
               (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS,
               use_cg3};
+  const bool tl = use_tiles(c, co.cg3, L, co.apply, co.launch);
   Work &w = c->w;
   // gather b into the DD layout (both parts in one launch)
   const int n_all = c->NI + c->n_gamma;
@@ -2099,7 +2387,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     dd_status s = core_solve(c, DD_FP64, w.bI, w.bG, w.uI, w.uG, L, nrhs, co);
     if (s != DD_OK) return s;
     if (o.verify) {
-      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
     }
     scatter();
@@ -2129,7 +2417,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0);
     for (int j = nrhs; j < kMaxLd; ++j) done[j] = 1;
     for (int step = 1;; ++step) {
-      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
       TRY(fetch_state(c, &h));            // inner iterations, ||b||, ||r||: one wait per step
       bool any = false;
@@ -2182,7 +2470,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
       dd_status s = core_solve(c, DD_FP64, w.tI, w.tG, w.dI, w.dG, L, nrhs, co);
       if (s != DD_OK) return s;
       axpy(c->d_solve_mask);
-      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+      full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
       TRY(fetch_state(c, &h));
       for (int j = 0; j < nrhs; ++j) {
