@@ -148,22 +148,38 @@ typedef struct {
  * gather32 -1 (automatic), tiles -1 (automatic). */
 void dd_default_opts(dd_solve_opts *opts);
 
-/* Device bytes a context for `prob` would hold (matrices, factors for
- * `prec`, work vectors for max_nrhs right-hand sides).  Validates nothing
- * beyond the sizes. */
+/* Device bytes a context for `prob` would hold: the blocks of eq.
+ * subStiffnessMatrixSubBlocks as uploaded, the factors of eq.
+ * splittingBlockCholesky for `prec` (DD_MIXED also counts the FP64 factors its
+ * fallback forms on first use), the tiles of the wide-batch products when
+ * max_nrhs >= 8, and the work vectors for max_nrhs right-hand sides.  prob: H.
+ * Validates nothing beyond the sizes; DD_EINVAL on a NULL pointer or max_nrhs
+ * outside [1, 64].  (max_nrhs is an addition to the interface the method
+ * implies: it sizes the resident Krylov state of batched solves.) */
 dd_status dd_footprint(const dd_problem *prob, dd_precision prec, int32_t max_nrhs,
                        size_t *bytes);
 
-/* Validate `prob` (index ranges, CSR monotonicity, map injectivity, coverage
- * of every dof, no interior-interior coupling across subdomains), deep-copy it
- * to the current HIP device and bind the context to `hip_stream`.
- * max_nrhs in [1, 64]: largest batch dd_solve will accept.  *out is NULL on
- * error; the message of a failed setup is returned by dd_last_error(NULL). */
+/* Upload the partitioned system: per subdomain the blocks K_II^k and K_IG^k
+ * and the global K_GG (eqs. subStiffnessMatrix, subStiffnessMatrixSubBlocks;
+ * K_GG assembled once for all subdomains, whose subdomain blocks sum to it by
+ * the partition of unity of eq. zeta).  Validate `prob` (index ranges, CSR
+ * monotonicity, map injectivity, coverage of every dof, no interior-interior
+ * coupling across subdomains -- the requirement of eq. subRequirement that
+ * interiors interact only through the interface), deep-copy it to the current
+ * HIP device (prob: H, read during the call only) and bind the context to
+ * `hip_stream`.  max_nrhs in [1, 64]: largest batch dd_solve will accept (an
+ * addition to the interface the method implies).  *out is NULL on error
+ * (DD_EINVAL with the field named, DD_ENOMEM, DD_EHIP); the message of a
+ * failed setup is returned by dd_last_error(NULL). */
 dd_status dd_setup(const dd_problem *prob, void *hip_stream, int32_t max_nrhs,
                    dd_ctx **out);
 
-/* Factor every K_II^k (batched Cholesky), form the interior-solve operators
- * and the exact diag(S) preconditioner in precision `prec`.  May be called
+/* Factor every K_II^k = L_k L_k^T (batched Cholesky; the block factorisation of
+ * eq. splittingBlockCholesky needs K_II^k non-singular, which holds for every
+ * subdomain, floating ones included), form the interior-solve operators
+ * K_II^{-1} = L^{-T} L^{-1} and the exact diagonal of S (eq.
+ * subSchurComplement summed over k) for the Jacobi preconditioner, in
+ * precision `prec`.  May be called
  * again with the other precision; both sets of factors are then kept.
  * DD_ENOTSPD names the subdomain and column of the first failed pivot, or the
  * interface row whose diag(S) entry is not positive.  DD_EHIP also covers a
@@ -173,8 +189,15 @@ dd_status dd_setup(const dd_problem *prob, void *hip_stream, int32_t max_nrhs,
  * dd_footprint); later calls reuse it. */
 dd_status dd_factor(dd_ctx *ctx, dd_precision prec);
 
-/* Solve A u = b for nrhs columns.  b_dev and u_dev: D, column-major n_dof x
- * nrhs with leading dimension ld >= n_dof; they may not alias.  Uses the
+/* Solve A u = b for nrhs columns (the discrete system of the section "A
+ * discretized weak formulation"): condensation g = b_G - sum_k K_GI^k
+ * (K_II^k)^{-1} b_I^k (eq. subForcing summed over k), preconditioned CG on
+ * S u_G = g with S = sum_k R_k^T S_k R_k (eqs. subSchurComplement,
+ * SchurComplement), and back substitution of the interiors (eq.
+ * backwardSubstitution).  prec selects FP64 or mixed FP32/FP64 iterative
+ * refinement (an addition to the method, see dd_precision).  b_dev and u_dev:
+ * D, column-major n_dof x nrhs with leading dimension ld >= n_dof; they may
+ * not alias.  Uses the
  * factors of `prec` (dd_factor(prec) must have run; DD_MIXED falls back to
  * FP64 factors, computing them on first use, when opts->fp64_fallback).
  * info_host: H, nrhs entries (may be NULL).  Returns after the solution and

@@ -153,6 +153,77 @@ __device__ __forceinline__ void partials_sum2(const double *pa, const double *pb
   rb = wave_sum(sb);
 }
 
+// partials_sum / partials_sum2 for NC consecutive columns c0 .. c0+NC-1 at
+// once (columns >= c0 + nc read as zero): every column is summed exactly as the
+// one-column forms sum it (lane t adds partials t, t+64, ... in increasing order,
+// then the butterfly), only the loads of the columns overlap, so wide batches
+// pay one memory round trip per batch of kBatch partials instead of one per
+// column.
+// COH = false: plain loads, for partials written by an earlier launch (a
+// kernel boundary makes them visible; plain loads then hit in every XCD's L2
+// instead of all workgroups of the launch reading the same few lines from
+// memory).
+template <int NC, bool COH = true>
+__device__ __forceinline__ void partials_sum_cols(const double *part, int P, int ld, int c0, int nc,
+                                                  double (&out)[NC]) {
+  constexpr int B = 4;
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  for (int i0 = lane_id(); i0 < P; i0 += B * kWave) {
+    double v[B][NC];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = i0 + u * kWave;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double *a = part + (size_t)i * ld + c0 + c;
+        v[u][c] = (i < P && c < nc) ? (COH ? load_partial(a) : *a) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] += v[u][c];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = wave_sum(s[c]);
+}
+
+template <int NC>
+__device__ __forceinline__ void partials_sum2_cols(const double *pa, const double *pb, int P, int ld,
+                                                   int c0, int nc, double (&ra)[NC], double (&rb)[NC]) {
+  constexpr int B = 4;
+  double sa[NC], sb[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sa[c] = sb[c] = 0.0;
+  for (int i0 = lane_id(); i0 < P; i0 += B * kWave) {
+    double va[B][NC], vb[B][NC];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = i0 + u * kWave;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bool ok = i < P && c < nc;
+        va[u][c] = ok ? load_partial(pa + (size_t)i * ld + c0 + c) : 0.0;
+        vb[u][c] = ok ? load_partial(pb + (size_t)i * ld + c0 + c) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sa[c] += va[u][c];
+        sb[c] += vb[u][c];
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    ra[c] = wave_sum(sa[c]);
+    rb[c] = wave_sum(sb[c]);
+  }
+}
+
 // Last-workgroup election after every workgroup stored its partials (with
 // store_partial).  The counter is reset by the elected workgroup.
 __device__ __forceinline__ bool last_block(unsigned *counter, int *lds_flag) {
@@ -735,7 +806,13 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 // and, when host_nact is given, publishes (number of active columns + 1) to
 // host memory (a plain system-coherent store: the host reads only that value).
 // E = elements per thread (cpw * kRowsE * ld / kBlock, at least 1).
-template <int E>
+// GROUPED (wide batches of the tiled path, one chunk per workgroup): the
+// chunk partials of r.z and r.r are first summed per group of kPGroup
+// workgroups by the group's last workgroup (into red.part2: r.z group sums,
+// then r.r group sums), and the last group finishes the column state from the
+// group sums -- the load of the final sum spread over the groups instead of one
+// workgroup reducing every chunk of every column.
+template <int E, bool GROUPED = false>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
@@ -775,16 +852,23 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     }
   }
   if (mode == 1) {
-    for (int c = wv; c < ld; c += kWavesPerBlock) {
-      const int act0 = st.active[c];
-      const double rz0 = st.rz[c];
-      double pq = partials_sum(red.part3, npq, ld, c);
-      if (lane == 0) {
-        int act = act0;
+    // wave wv takes the columns c0 .. c0+7 of every group of 32 (the loads of a
+    // wave's columns overlap; each column's sum is that of partials_sum)
+    constexpr int NC = 8;
+    for (int c0 = wv * NC; c0 < ld; c0 += kWavesPerBlock * NC) {
+      const int nc = min(NC, ld - c0);
+      double pq[NC];
+      partials_sum_cols<NC, false>(red.part3, npq, ld, c0, nc, pq);   // written by the last launch
+      if (lane < nc) {
+        const int c = c0 + lane;
+        double pqc = pq[0];
+#pragma unroll
+        for (int u = 1; u < NC; ++u) if (lane == u) pqc = pq[u];
+        int act = st.active[c];
         double a = 0.0;
         if (act) {
-          if (!(pq > 0.0)) act = 0;
-          else a = rz0 / pq;
+          if (!(pqc > 0.0)) act = 0;
+          else a = st.rz[c] / pqc;
         }
         salpha[c] = a;
         sact[c] = act;
@@ -849,17 +933,49 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
                                       __HIP_MEMORY_SCOPE_AGENT);
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);   // both partial stores complete before the count
-  if (!last_block(&red.counter[1], &lflag)) return;
-  for (int c = wv; c < ld; c += kWavesPerBlock) {
-    // the column's state, loaded together with the partials
-    int active = st.active[c];
-    const double rzo = st.rz[c];
-    const int mk = mode == 2 ? mask[c] : 0;
-    const double s2 = st.stop2[c];
-    const int it0 = st.iters[c];
-    double rz, rr;
-    partials_sum2(red.part0, red.part1, nchunks, ld, c, rz, rr);
-    if (lane == 0) {
+  const double *fin0 = red.part0, *fin1 = red.part1;
+  int nfin = nchunks;
+  if constexpr (GROUPED) {
+    const int ngrp = ((int)gridDim.x + kPGroup - 1) / kPGroup;
+    const int grp = blockIdx.x / kPGroup;
+    const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
+    unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
+    if (!last_of(cnt, (unsigned)members, &lflag)) return;
+    double *gs0 = red.part2, *gs1 = red.part2 + (size_t)ngrp * ld;
+    for (int c = wv; c < ld; c += kWavesPerBlock) {
+      const double a0 = chunk_group_sum(red.part0, nchunks, ld, c, grp);
+      const double a1 = chunk_group_sum(red.part1, nchunks, ld, c, grp);
+      if (lane == 0) {
+        store_partial(gs0 + (size_t)grp * ld + c, a0);
+        store_partial(gs1 + (size_t)grp * ld + c, a1);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) reset_counter(cnt);
+    if (!last_of(&red.counter[1], (unsigned)ngrp, &lflag)) return;
+    fin0 = gs0;
+    fin1 = gs1;
+    nfin = ngrp;
+  } else {
+    if (!last_block(&red.counter[1], &lflag)) return;
+  }
+  constexpr int NC2 = 4;
+  for (int c0 = wv * NC2; c0 < ld; c0 += kWavesPerBlock * NC2) {
+    const int nc = min(NC2, ld - c0);
+    double rzv[NC2], rrv2[NC2];
+    partials_sum2_cols<NC2>(fin0, fin1, nfin, ld, c0, nc, rzv, rrv2);
+    // lane u < nc finishes column c0 + u
+    double rz = rzv[0], rr = rrv2[0];
+#pragma unroll
+    for (int u = 1; u < NC2; ++u)
+      if (lane == u) { rz = rzv[u]; rr = rrv2[u]; }
+    if (lane < nc) {
+      const int c = c0 + lane;
+      int active = st.active[c];
+      const double rzo = st.rz[c];
+      const int mk = mode == 2 ? mask[c] : 0;
+      const double s2 = st.stop2[c];
+      const int it0 = st.iters[c];
       if (mode == 0 || (mode == 2 && mk)) {
         st.rz[c] = rz;
         st.iters[c] = 0;

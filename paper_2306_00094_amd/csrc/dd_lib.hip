@@ -45,6 +45,7 @@ struct Ops {
   double *dinv = nullptr;  // 1 / diag(S)
   void *tI_val = nullptr;  // 16x16 tiles of K_IG (T), wide batches
   void *tG_val = nullptr;  // 16x16 tiles of [K_GG | K_GI] (T), wide batches
+  void *kinv_t = nullptr;  // K_II^{-1} packed into 16x16 tiles (T), wide batches
   bool ready = false;
 };
 
@@ -110,6 +111,9 @@ struct dd_ctx {
   int *d_tG_ptr = nullptr, *d_tG_split = nullptr, *d_tG_col = nullptr;
   double *d_tI_val64 = nullptr, *d_tG_val64 = nullptr;
   int2 *d_dit = nullptr;
+  long long t_kpack = 0;              // elements of the packed dense blocks (16x16 tiles)
+  long long *d_toff = nullptr;        // per subdomain offset of its packed tiles
+  double *d_kii_t = nullptr;          // K_II packed into tiles (FP64 residual of the mixed path)
   double *d_ig_val64 = nullptr, *d_g_val64 = nullptr, *d_kii64 = nullptr;
   Ops op[2];
   Work w{};
@@ -413,6 +417,13 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
     const size_t nrbI = (NI + kT - 1) / kT, nrbG = (p->n_gamma + kT - 1) / kT;
     b += (tI + tG) * (4 + 256 * 8) + (nrbI + 1) * 4 + (2 * nrbG + 1) * 4 + NI * 8 / kT + 64;
     if (prec == DD_MIXED) b += (tI + tG) * 256 * 4;
+    size_t kp = 0;                       // packed K_II (FP64) and K_II^{-1} (T)
+    for (int k = 0; k < p->n_sub; ++k) {
+      const size_t nt = (p->sub[k].n_i + kT - 1) / kT;
+      kp += nt * nt * 256;
+    }
+    b += kp * 8 + kp * s + (p->n_sub + 1) * 8;
+    if (prec == DD_MIXED) b += kp * 8;  // the FP64 fallback's packed inverse
   }
   b += (12 * (size_t)p->n_gamma + 6 * NI) * ld * 8;                   // work vectors
   b += (4 * (size_t)p->n_gamma + NI) * ld * 4;                        // FP32 gather copies
@@ -543,14 +554,19 @@ inline unsigned upd_grid(int n_gamma, int ld) {
 // CG update launch; the elements per thread follow from the batch width.
 void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, double *x, double *r,
                    double *z, double *p, const double *q, int precond, int *host_nact,
-                   int init_p_is_z, const int *mask, int npq) {
+                   int init_p_is_z, const int *mask, int npq, bool grouped = false) {
   if (c->n_gamma <= 0) return;
   const int cpw = upd_cpw(ld);
   const dim3 g(upd_grid(c->n_gamma, ld)), b(kBlock);
   const int E = std::max(1, cpw * kRowsE * ld / kBlock);
-#define DD_UPD(EE)                                                                              \
-  hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x, \
-                     r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p)
+  grouped = grouped && cpw == 1;
+#define DD_UPD(EE)                                                                                        \
+  if (grouped)                                                                                            \
+    hipLaunchKernelGGL((k_cg_update<EE, true>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,   \
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p); \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,         \
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p)
   switch (E) {
     case 1: DD_UPD(1); break;
     case 2: DD_UPD(2); break;
@@ -656,7 +672,7 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   const int nrb = interface_rows ? c->t_nrbG : c->t_nrbI;
   const int nrows = interface_rows ? c->n_gamma : c->NI;
   if (nrb <= 0) return;
-  const dim3 g(grid_for(nrb, kWavesPerBlock)), b(kBlock);
+  const dim3 g(nrb), b(kTW * kWave);
   const int *ptr = interface_rows ? c->d_tG_ptr : c->d_tI_ptr;
   const int *split = interface_rows ? c->d_tG_split : nullptr;
   const int *col = interface_rows ? c->d_tG_col : c->d_tI_col;
@@ -696,17 +712,17 @@ void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const
 void dense_tiles(dd_ctx *c, int prec, bool kii, const double *y, int ld, const double *base, double sign,
                  double *w) {
   if (c->n_dit <= 0) return;
-  const dim3 g(grid_for(c->n_dit, kWavesPerBlock)), b(kBlock);
+  const dim3 g(c->n_dit), b(kTW * kWave);
 #define DD_DT(MT, NCB, BLK)                                                                                \
-  hipLaunchKernelGGL((k_dense_tiles<MT, NCB>), g, b, 0, c->stream, c->n_dit, c->d_dit, (const MT *)(BLK),   \
-                     c->d_koff, c->d_ioff, c->d_ni, y, ld, base, sign, w)
+  hipLaunchKernelGGL((k_dense_tiles<MT, NCB>), g, b, 0, c->stream, c->NI, c->d_dit, (const MT *)(BLK),   \
+                     c->d_toff, c->d_ioff, c->d_ni, y, ld, base, sign, w)
   if (kii || prec == DD_FP64) {
-    const void *blk = kii ? (const void *)c->d_kii64 : c->op[DD_FP64].kinv;
+    const void *blk = kii ? (const void *)c->d_kii_t : c->op[DD_FP64].kinv_t;
     if (ld <= 16) DD_DT(double, 1, blk);
     else if (ld <= 32) DD_DT(double, 2, blk);
     else DD_DT(double, 4, blk);
   } else {
-    const void *blk = c->op[DD_MIXED].kinv;
+    const void *blk = c->op[DD_MIXED].kinv_t;
     if (ld <= 16) DD_DT(float, 1, blk);
     else if (ld <= 32) DD_DT(float, 2, blk);
     else DD_DT(float, 4, blk);
@@ -915,6 +931,11 @@ dd_status factor_impl(dd_ctx *c, int pi) {
                        c->d_koff, c->d_ni);
     HIPCHK(c, hipGetLastError());
   }
+  if (c->tiles && c->n_sub > 0) {   // K_II^{-1} in the tile order of the wide-batch interior solves
+    hipLaunchKernelGGL((k_pack_tiles<T>), dim3(64, c->n_sub), dim3(256), 0, c->stream, c->n_sub,
+                       (const T *)Kinv, c->d_koff, c->d_toff, c->d_ni, (T *)o.kinv_t);
+    HIPCHK(c, hipGetLastError());
+  }
   if (pi == DD_MIXED) {
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_ig, c->d_ig_val64,
                        (float *)o.ig_val);
@@ -969,6 +990,7 @@ dd_status ensure_ops(dd_ctx *c, int pi) {
   TRY(al(&o.kinv, c->ktot * s));
   TRY(al((void **)&o.diag, c->n_gamma * 8));
   TRY(al((void **)&o.dinv, c->n_gamma * 8));
+  if (c->tiles) TRY(al(&o.kinv_t, (size_t)c->t_kpack * s));
   if (pi == DD_FP64) {
     o.ig_val = c->d_ig_val64;
     o.g_val = c->d_g_val64;
@@ -1177,7 +1199,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // interior solve) also written in FP32 for the gathers of the loop below
     if (g32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
-                  dkv, nullptr, 0);
+                  dkv, nullptr, 0, tl);
   }
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
@@ -1239,7 +1261,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
-                    0, nullptr, c->gamma_parts);
+                    0, nullptr, c->gamma_parts, tl);
     }
     if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
@@ -1387,11 +1409,16 @@ inline double inner_stop2(double inner_tol, double tol, double rn2, double bn2) 
   return std::max(inner_tol * inner_tol * rn2, 0.25 * tol * tol * bn2);
 }
 
-dd_status fetch_state(dd_ctx *c, StateBlock *h) {
+// breakdown_fails = false (inner solves of the mixed refinement): a breakdown
+// of the FP32-operator CG (p^T S p <= 0 for an S that is positive definite
+// but ill-conditioned beyond FP32) is not an error; the refinement step then
+// fails to reduce the FP64 residual, and the column stalls and falls back to
+// the FP64 path.
+dd_status fetch_state(dd_ctx *c, StateBlock *h, bool breakdown_fails = true) {
   HIPCHK(c, hipMemcpyAsync(h, c->d_state, sizeof(StateBlock), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->tev_used) collect_timing(c, h);
-  if (h->flag[0]) return fail(c, DD_ENOTSPD, "CG breakdown: p^T S p <= 0");
+  if (h->flag[0] && breakdown_fails) return fail(c, DD_ENOTSPD, "CG breakdown: p^T S p <= 0");
   return DD_OK;
 }
 
@@ -1688,13 +1715,29 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
                           std::max(1, NI), &tg);
     c->t_nrbI = (NI + kT - 1) / kT;
     c->t_nrbG = (c->n_gamma + kT - 1) / kT;
-    std::vector<int2> items;
+    // Interior-solve work items (subdomain, 16-row tile).  Workgroup b runs on
+    // XCD b % 8: every subdomain's items go to one XCD (its slices of y are then
+    // cached in one L2), subdomains by decreasing work to the least loaded XCD,
+    // and the eight lists are interleaved (k = -1 pads a short list).
+    constexpr int kXcd = 8;
     std::vector<int> order(c->n_sub);
     for (int k = 0; k < c->n_sub; ++k) order[k] = k;
-    // largest blocks first: their work items are the longest
     std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return c->ni[a2] > c->ni[b2]; });
-    for (int k : order)
-      for (int I = 0; I < (c->ni[k] + kT - 1) / kT; ++I) items.push_back(make_int2(k, I));
+    std::vector<std::vector<int2>> bins(kXcd);
+    long long load[kXcd] = {0};
+    for (int k : order) {
+      int x = 0;
+      for (int y = 1; y < kXcd; ++y)
+        if (load[y] < load[x]) x = y;
+      const int nt = (c->ni[k] + kT - 1) / kT;
+      load[x] += (long long)nt * nt;
+      for (int I = 0; I < nt; ++I) bins[x].push_back(make_int2(k, I));
+    }
+    size_t blen = 0;
+    for (auto &bn : bins) blen = std::max(blen, bn.size());
+    std::vector<int2> items;
+    for (size_t i = 0; i < blen; ++i)
+      for (int x = 0; x < kXcd; ++x) items.push_back(i < bins[x].size() ? bins[x][i] : make_int2(-1, 0));
     c->n_dit = (int)items.size();
     for (TileSet *t : {&ti, &tg})          // uploads need at least one element
       if (t->col.empty()) {
@@ -1709,6 +1752,20 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     if ((s = upload(c, &c->d_tG_col, tg.col.data(), tg.col.size())) != DD_OK) return bail(s);
     if ((s = upload(c, &c->d_tG_val64, tg.val.data(), tg.val.size())) != DD_OK) return bail(s);
     if ((s = upload(c, &c->d_dit, items.data(), items.size())) != DD_OK) return bail(s);
+    std::vector<long long> toff(c->n_sub + 1, 0);
+    for (int k = 0; k < c->n_sub; ++k) {
+      const long long nt = (c->ni[k] + kT - 1) / kT;
+      toff[k + 1] = toff[k] + nt * nt * 256;
+    }
+    c->t_kpack = toff[c->n_sub];
+    if ((s = upload(c, &c->d_toff, toff.data(), toff.size())) != DD_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_kii_t, (size_t)c->t_kpack)) != DD_OK) return bail(s);
+    hipLaunchKernelGGL((k_pack_tiles<double>), dim3(64, c->n_sub), dim3(256), 0, c->stream, c->n_sub,
+                       c->d_kii64, c->d_koff, c->d_toff, c->d_ni, c->d_kii_t);
+    if (hipGetLastError() != hipSuccess) {
+      c->err = "packing of K_II failed";
+      return bail(DD_EHIP);
+    }
     c->tiles = true;
   }
   // work vectors
@@ -2158,7 +2215,7 @@ dd_status dd_batch_step(dd_ctx *c, int32_t iters, int32_t *state_host) {
     HIPCHK(c, hipGetLastError());
   }
   StateBlock &h = *c->h_state;
-  TRY(fetch_state(c, &h));
+  TRY(fetch_state(c, &h, prec == DD_FP64));   // mixed: an inner breakdown stalls the slot
   // slots whose CG finished: back substitution of the correction and update of u
   std::vector<int> fin(kMaxLd, 0);
   bool anyfin = false;
@@ -2419,7 +2476,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     for (int step = 1;; ++step) {
       full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
-      TRY(fetch_state(c, &h));            // inner iterations, ||b||, ||r||: one wait per step
+      TRY(fetch_state(c, &h, false));     // inner iterations, ||b||, ||r||: one wait per step
       bool any = false;
       for (int j = 0; j < nrhs; ++j) {
         if (mask[j]) {

@@ -50,116 +50,170 @@ template <> struct TileA<float> {
 
 // One 16-row slice of x (rows cb*16 .. cb*16+15, DD layout with leading
 // dimension ld) in the B-operand order: lane l takes row cb*16 + 4 s + l/16 and
-// column q*16 + l%16 for step s and column block q.  Rows >= n and columns >=
-// ld read as zero.
+// column q*16 + l%16 for step s and column block q.  Rows past the last row
+// n - 1 read row n - 1 (the tile entries they meet are zero); for ld = 8 the
+// lanes of columns 8..15 read columns 0..7 again (their products land in
+// output columns that are not stored).  The loads are unconditional, so the
+// compiler can count them when it waits for a buffer.
 template <int NCB>
 __device__ __forceinline__ void load_slice(const double *__restrict__ x, int n, int ld, int cb,
                                            double (&xv)[4][NCB]) {
   const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
+  const double *p = x + (l16 & (ld - 1));
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int row = cb * kT + 4 * s + g;
+    const int row = min(cb * kT + 4 * s + g, n - 1);
 #pragma unroll
-    for (int q = 0; q < NCB; ++q) {
-      const int col = q * kT + l16;
-      xv[s][q] = (row < n && col < ld) ? x[(size_t)row * ld + col] : 0.0;
-    }
+    for (int q = 0; q < NCB; ++q) xv[s][q] = p[(size_t)row * ld + q * kT];
   }
 }
 
-// acc[q] += T * X over the tiles [t0, t1) of one row block.  The next tile's
-// operands are loaded while the current tile's instructions run.
+template <int NCB>
+__device__ __forceinline__ void tile_mma(const double (&a)[4], const double (&xv)[4][NCB], dbl4 (&acc)[NCB]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], xv[s][q], acc[q]);
+}
+
+// acc[q] += T * X over the tiles t0, t0 + st, t0 + 2 st, ... (< t1) of one row
+// block, in that order (t0, t1, st uniform over the wave).  The tiles' column
+// blocks are fetched 64 at a time, one per lane, and broadcast by readlane; two
+// register buffers hold the operands of the next two tiles while a tile's
+// instructions run (the last loads of a wave repeat its last tile and are not
+// used).
 template <typename VT, int NCB>
-__device__ __forceinline__ void tile_row_acc(int t0, int t1, const int *__restrict__ tcol,
+__device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *__restrict__ tcol,
                                              const VT *__restrict__ tval, const double *__restrict__ x,
                                              int n, int ld, dbl4 (&acc)[NCB]) {
-  if (t0 >= t1) return;
+  const int cnt = t0 < t1 ? (t1 - t0 + st - 1) / st : 0;
   const int lane = lane_id();
-  double a[4], xv[4][NCB];
-  TileA<VT>::load(tval + (size_t)t0 * 256 + 4 * lane, a);
-  load_slice<NCB>(x, n, ld, tcol[t0], xv);
-  for (int t = t0; t < t1; ++t) {
-    double an[4], xn[4][NCB];
-    const bool more = t + 1 < t1;
-    if (more) {
-      TileA<VT>::load(tval + (size_t)(t + 1) * 256 + 4 * lane, an);
-      load_slice<NCB>(x, n, ld, tcol[t + 1], xn);
+  for (int base = 0; base < cnt; base += kWave) {
+    const int nb = min(kWave, cnt - base);
+    const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
+    const VT *tv = tval + (size_t)(t0 + base * st) * 256 + 4 * lane;
+    const size_t tstride = (size_t)st * 256;
+    double a0[4], x0[4][NCB], a1[4], x1[4][NCB];
+    TileA<VT>::load(tv, a0);
+    load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, 0), x0);
+    {
+      const int j1 = min(1, nb - 1);
+      TileA<VT>::load(tv + j1 * tstride, a1);
+      load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, j1), x1);
     }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], xv[s][q], acc[q]);
-    if (more) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        a[s] = an[s];
-#pragma unroll
-        for (int q = 0; q < NCB; ++q) xv[s][q] = xn[s][q];
+    for (int j = 0; j < nb; j += 2) {
+      tile_mma<NCB>(a0, x0, acc);
+      {
+        const int jn = min(j + 2, nb - 1);
+        TileA<VT>::load(tv + jn * tstride, a0);
+        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x0);
+      }
+      if (j + 1 < nb) tile_mma<NCB>(a1, x1, acc);
+      {
+        const int jn = min(j + 3, nb - 1);
+        TileA<VT>::load(tv + jn * tstride, a1);
+        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x1);
       }
     }
   }
 }
 
-// Row blocks of a tiled matrix, one wave per block of 16 rows, four per
-// workgroup:
-//   out = base + c1 * (tiles [ptr, split) applied to x1) + c2 * (tiles [split, ptr+1) applied to x2)
+// Workgroup b runs on XCD b % 8 (round-robin dispatch; each XCD has its own
+// L2).  Workgroup b takes item xcd_item(b, n) so that every XCD works through
+// one contiguous eighth of the items: neighbouring row blocks, which multiply
+// mostly the same vector slices, then share one L2.
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, i = b / kXcd, q = n / kXcd, r = n % kXcd;
+  return x * q + min(x, r) + i;
+}
+
+// Wave index as a uniform (scalar) value.
+__device__ __forceinline__ int wave_uniform() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
+// Waves per 16-row block: the block's tiles are dealt to them in turn and their
+// partial products summed in wave order through LDS.
+constexpr int kTW = 4;
+
+// One workgroup per block of 16 rows of a tiled matrix:
+//   out = base + sum over waves w of (c1 * (tiles [ptr, split) of wave w applied to x1)
+//                                     + c2 * (tiles [split, ptr+1) of wave w applied to x2))
 // (split == nullptr: one part, tiles [ptr, ptr+1) applied to x1; base may be
-// nullptr; a part whose coefficient is 0 is skipped).  x1 has n1
-// rows, x2 n2 rows, out nrows rows; all three DD layout with leading dimension ld.
-// With DOT the workgroup also writes its partial of x1^T out per column (its
-// 64 rows summed by one fixed butterfly) to red.part2, and the last of every
-// kPGroup consecutive workgroups the group sum to red.part3, which the update
-// kernel reduces (the step length of the CG iteration, p^T S p).
+// nullptr; a part whose coefficient is 0 is skipped).  x1 has n1 rows, x2 n2
+// rows, out nrows rows; all three DD layout with leading dimension ld.  Wave w
+// takes tiles b + w, b + w + kTW, ...; the wave sums are added in wave order.
+// With DOT the workgroup also writes x1^T out over its 16 rows (rows in order)
+// per column to red.part2, and the last of every kPGroup consecutive
+// workgroups the group sum to red.part3, which the update kernel reduces (the
+// step length of the CG iteration, from p^T S p).
 template <typename VT, int NCB, bool DOT>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kTW * kWave)
 k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
             const int *__restrict__ tcol, const VT *__restrict__ tval, const double *__restrict__ x1,
             int n1, const double *__restrict__ x2, int n2, int ld, const double *__restrict__ base,
             double c1, double c2, double *__restrict__ out, RedBuf red) {
-  const int wv = wave_id(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
-  const int rb = blockIdx.x * kWavesPerBlock + wv;
+  const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
+  const int rb = xcd_item(blockIdx.x, nrb);
   dbl4 acc1[NCB], acc2[NCB];
 #pragma unroll
   for (int q = 0; q < NCB; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc1[q][r] = acc2[q][r] = 0.0;
-  if (rb < nrb) {
-    const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
-    if (c1 != 0.0) tile_row_acc<VT, NCB>(b, s, tcol, tval, x1, n1, ld, acc1);
-    if (split && c2 != 0.0) tile_row_acc<VT, NCB>(s, e, tcol, tval, x2, n2, ld, acc2);
-  }
-  __shared__ double prod[kWavesPerBlock * kT * kMaxLd];
+  const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
+  if (c1 != 0.0) tile_row_acc<VT, NCB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, acc1);
+  if (split && c2 != 0.0) tile_row_acc<VT, NCB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, acc2);
+  __shared__ double part[kTW * kT * kMaxLd];
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
     const int col = q * kT + l16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int lr = g + 4 * r;                  // row of the tile held in register r
-      const int row = rb * kT + lr;
-      double v = 0.0;
-      if (rb < nrb && row < nrows && col < ld) {
+      if (col < ld) part[(wv * kT + lr) * ld + col] = c1 * acc1[q][r] + c2 * acc2[q][r];
+    }
+  }
+  __syncthreads();
+  const int nel = kT * ld;
+  double fin[kMaxLd * kT / (kTW * kWave)];       // this thread's elements (at most 4)
+#pragma unroll
+  for (int u = 0; u < kMaxLd * kT / (kTW * kWave); ++u) {
+    const int el = threadIdx.x + u * kTW * kWave;
+    fin[u] = 0.0;
+    if (el < nel) {
+      const int lr = el / ld, col = el - lr * ld, row = rb * kT + lr;
+      double v = part[el];
+#pragma unroll
+      for (int w = 1; w < kTW; ++w) v += part[w * nel + el];
+      if (row < nrows) {
         const size_t o = (size_t)row * ld + col;
-        v = (base ? base[o] : 0.0) + c1 * acc1[q][r] + c2 * acc2[q][r];
+        v += base ? base[o] : 0.0;
         out[o] = v;
-        if (DOT) v *= x1[(size_t)row * ld + col];
-      } else {
-        v = 0.0;
+        fin[u] = DOT ? v * x1[o] : 0.0;
       }
-      if (DOT && col < ld) prod[(wv * kT + lr) * ld + col] = v;
     }
   }
   if (!DOT) return;
-  __syncthreads();
-  for (int c = wv; c < ld; c += kWavesPerBlock) {
-    const double sm = chunk64_sum(prod, ld, c);
-    if (lane == 0) store_partial(red.part2 + (size_t)blockIdx.x * ld + c, sm);
+  __syncthreads();                               // every wave read its part: reuse it
+#pragma unroll
+  for (int u = 0; u < kMaxLd * kT / (kTW * kWave); ++u) {
+    const int el = threadIdx.x + u * kTW * kWave;
+    if (el < nel) part[el] = fin[u];
   }
-  const int grp = blockIdx.x / kPGroup;
+  __syncthreads();
+  if ((int)threadIdx.x < ld) {
+    const int c = threadIdx.x;
+    double sm = 0.0;
+    for (int lr = 0; lr < kT; ++lr) sm += part[lr * ld + c];
+    store_partial(red.part2 + (size_t)rb * ld + c, sm);
+  }
+  const int grp = rb / kPGroup;
   const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
   __shared__ int lflag;
   unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
   if (!last_of(cnt, (unsigned)members, &lflag)) return;
-  for (int c = wv; c < ld; c += kWavesPerBlock) {
+  for (int c = wv; c < ld; c += kTW) {
     const double gs = chunk_group_sum(red.part2, gridDim.x, ld, c, grp);
     if (lane == 0) store_partial(red.part3 + (size_t)grp * ld + c, gs);
   }
@@ -168,11 +222,16 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
 }
 
 // Interior solve w = base + sign * K_II^-1 y on the matrix cores (or, with the
-// blocks K_II themselves, the interior part of a residual): one wave per work item
-// (subdomain k, 16-row tile I of its block), the tiles of block row I of the
-// explicit inverse (column-major n x n at koff[k]) applied to y in column
-// order.  FP64 blocks: v_mfma_f64_16x16x4f64; FP32 blocks (mixed path):
-// v_mfma_f32_16x16x4f32 with FP32 operands and accumulation.
+// blocks K_II themselves, the interior part of a residual): one workgroup per
+// work item (subdomain k, 16-row tile I of its block; items[b] is the item of
+// workgroup b, arranged by the host so that all items of a subdomain run on one
+// XCD, and k = -1 pads).  The blocks are packed
+// by k_pack_tiles into 16x16 tiles in the A-operand order, block row I of
+// subdomain k at toff[k] + I * nt_k * 256 (nt_k = ceil(n_k / 16) tiles per
+// row, zero padded).  Wave w applies the tiles J = w, w + kTW, ... to the
+// 16-row slices of y; the wave sums are added in wave order.  FP64 blocks:
+// v_mfma_f64_16x16x4f64; FP32 blocks (mixed path): v_mfma_f32_16x16x4f32 with
+// FP32 operands and accumulation, the wave sums added in FP64.
 template <typename MT> struct DenseAcc;
 template <> struct DenseAcc<double> {
   typedef dbl4 acc_t;
@@ -183,56 +242,112 @@ template <> struct DenseAcc<float> {
   static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
 };
 
+template <typename MT> struct TileAT;
+template <> struct TileAT<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ void load(const double *p, double (&a)[4]) {
+    const v4 v = *(const v4 *)p;
+    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+  }
+};
+template <> struct TileAT<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ void load(const float *p, float (&a)[4]) {
+    const v4 v = *(const v4 *)p;
+    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+  }
+};
+
 template <typename MT, int NCB>
-__global__ void __launch_bounds__(kBlock)
-k_dense_tiles(int nitems, const int2 *__restrict__ items, const MT *__restrict__ blocks,
-              const long long *__restrict__ koff, const int *__restrict__ ioff,
+__global__ void __launch_bounds__(kTW * kWave)
+k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ packed,
+              const long long *__restrict__ toff, const int *__restrict__ ioff,
               const int *__restrict__ ni, const double *__restrict__ y, int ld,
               const double *__restrict__ base, double sign, double *__restrict__ w) {
-  const int it = blockIdx.x * kWavesPerBlock + wave_id();
-  if (it >= nitems) return;
-  const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
-  const int2 item = items[it];
+  const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
+  const int2 item = items[blockIdx.x];
+  if (item.x < 0) return;                        // padding of a short XCD list
   const int k = item.x, r0 = item.y * kT;
   const int n = ni[k], i0 = ioff[k];
-  const MT *A = blocks + koff[k];
-  const double *yb = y + (size_t)i0 * ld;
+  const int nt = (n + kT - 1) / kT;
+  const MT *A = packed + toff[k] + (size_t)item.y * nt * 256 + 4 * lane;
+  // y rows past the block (the next subdomain's, or the last row repeated at
+  // the end of y) meet the zero padding of the packed tiles
+  const double *yb = y + (l16 & (ld - 1));
   typedef typename DenseAcc<MT>::acc_t acc_t;
   acc_t acc[NCB];
 #pragma unroll
   for (int q = 0; q < NCB; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[q][r] = (MT)0;
-  const int ar = r0 + l16;                         // row of the A operand this lane loads
-  const int nt = (n + kT - 1) / kT;
-  for (int J = 0; J < nt; ++J) {
-    MT a[4], b[4][NCB];
+  auto load = [&](int J, MT (&a)[4], MT (&b)[4][NCB]) {
+    TileAT<MT>::load(A + (size_t)J * 256, a);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int col = J * kT + 4 * s + g;            // column of A = row of y
-      a[s] = (ar < n && col < n) ? A[(size_t)col * n + ar] : (MT)0;
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int q = 0; q < NCB; ++q) {
-        const int c = q * kT + l16;
-        b[s][q] = (col < n && c < ld) ? (MT)yb[(size_t)col * ld + c] : (MT)0;
-      }
-    }
+      for (int q = 0; q < NCB; ++q)
+        b[s][q] = (MT)yb[(size_t)min(i0 + J * kT + 4 * s + g, nall - 1) * ld + q * kT];
+  };
+  auto mma = [&](const MT (&a)[4], const MT (&b)[4][NCB]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], b[s][q], acc[q]);
+  };
+  // tiles J = wv, wv + kTW, ...: two register buffers in flight
+  const int cnt = wv < nt ? (nt - wv + kTW - 1) / kTW : 0;
+  if (cnt > 0) {
+    MT a0[4], b0[4][NCB], a1[4], b1[4][NCB];
+    load(wv, a0, b0);
+    load(wv + kTW * min(1, cnt - 1), a1, b1);
+    for (int j = 0; j < cnt; j += 2) {
+      mma(a0, b0);
+      load(wv + kTW * min(j + 2, cnt - 1), a0, b0);
+      if (j + 1 < cnt) mma(a1, b1);
+      load(wv + kTW * min(j + 3, cnt - 1), a1, b1);
+    }
   }
+  __shared__ double part[kTW * kT * kMaxLd];
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
     const int c = q * kT + l16;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = r0 + DenseAcc<MT>::row(g, r);
-      if (row < n && c < ld) {
-        const size_t o = (size_t)(i0 + row) * ld + c;
-        w[o] = (base ? base[o] : 0.0) + sign * (double)acc[q][r];
-      }
+    for (int r = 0; r < 4; ++r)
+      if (c < ld) part[(wv * kT + DenseAcc<MT>::row(g, r)) * ld + c] = (double)acc[q][r];
+  }
+  __syncthreads();
+  const int nel = kT * ld;
+  for (int el = threadIdx.x; el < nel; el += kTW * kWave) {
+    const int lr = el / ld, c = el - lr * ld, row = r0 + lr;
+    if (row < n) {
+      double v = part[el];
+#pragma unroll
+      for (int u = 1; u < kTW; ++u) v += part[u * nel + el];
+      const size_t o = (size_t)(i0 + row) * ld + c;
+      w[o] = (base ? base[o] : 0.0) + sign * v;
     }
+  }
+}
+
+// Packs column-major dense blocks (n_k x n_k at koff[k]) into the tile order
+// of k_dense_tiles: tile (I, J) of block k at toff[k] + (I * nt + J) * 256,
+// lane l holding B[16 I + l % 16][16 J + 4 s + l / 16] at position 4 l + s.
+template <typename T>
+__global__ void k_pack_tiles(int nsub, const T *__restrict__ blocks, const long long *__restrict__ koff,
+                             const long long *__restrict__ toff, const int *__restrict__ ni,
+                             T *__restrict__ packed) {
+  const int k = blockIdx.y;
+  if (k >= nsub) return;
+  const int n = ni[k], nt = (n + kT - 1) / kT;
+  const long long tot = (long long)nt * nt * 256;
+  const T *B = blocks + koff[k];
+  T *P = packed + toff[k];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(e / 256), pos = (int)(e % 256);
+    const int I = t / nt, J = t % nt, l = pos / 4, s = pos % 4;
+    const int i = I * kT + (l & 15), j = J * kT + 4 * s + (l >> 4);
+    P[e] = (i < n && j < n) ? B[(size_t)j * n + i] : (T)0;
   }
 }
 

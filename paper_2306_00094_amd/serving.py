@@ -10,7 +10,7 @@ different systems run concurrently on their own streams.  A system becomes
 resident only if its device footprint fits the HBM budget; idle systems are
 evicted least-recently-used first (their factors are then recomputed on the
 next request).  Stalled mixed-precision refinements are finished with FP64
-factors on a second context.
+factors on a second context, whose footprint is counted with the system's.
 
 All device work is done by the C ABI (paper_2306_00094_amd); this module only
 schedules it.  Latency = completion - arrival (host monotonic clock).
@@ -187,7 +187,14 @@ class Server:
         self.opts = opts if opts is not None else dd_default_opts(tol=1e-9, gather32=1)
         self.hbm_budget = hbm_budget
         self.iters_per_step = iters_per_step
-        self.footprint = {k: dd_footprint(dd, prec, MAX_SLOTS) for k, dd in systems.items()}
+        # device bytes held by a resident system: its context, and for mixed
+        # precision with the FP64 fallback also the second (FP64) context that
+        # finishes stalled requests, reserved up front so that admission by
+        # footprint never under-counts
+        fb = prec == DD_MIXED and self.opts.fp64_fallback != 0
+        self.footprint = {k: dd_footprint(dd, prec, MAX_SLOTS)
+                          + (dd_footprint(dd, DD_FP64, MAX_SLOTS) if fb else 0)
+                          for k, dd in systems.items()}
         self.resident = {}                          # key -> _System
         self.closing = set()                        # evicted systems still holding memory
         self.lock = threading.Lock()

@@ -1,7 +1,8 @@
 """GPU tests of the device assembly (dd_assemble_2d) against the CPU
 generator's assembly of the same nonlocal stiffness windows: constant,
 fractional (vertex-sharing pairs on the mean of the mixed rules) and
-peridynamic kernels at small sizes, and the benchmark system at full size.
+peridynamic kernels at small sizes, and the constant (h = 1/128), fractional
+(h = 1/96) and peridynamic (h = 1/160) benchmark systems at full size.
 
 The two sum the same pair integrals in different orders (the device adds the
 window entries with atomics), so an entry agrees to rounding of its sum:
@@ -21,6 +22,9 @@ CASES = {
     "2d-frac-28": lambda: workloads.spec_2d_frac(n=28, delta=0.15, cuts=(2, 2)),
     "2d-pd-40": lambda: workloads.spec_2d_pd(n=40, delta=0.1, cuts=(3, 3), jitter=0.2),
     "2d-const-128": lambda: workloads.spec_2d_const(),
+    # the fractional and peridynamic benchmark systems at full size
+    "2d-frac-96": lambda: workloads.spec_2d_frac(),
+    "2d-pd-160": lambda: workloads.spec_2d_pd(),
 }
 
 

@@ -65,6 +65,15 @@ def _load():
                                        ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int, dp]
         lib.nl_assemble_2d.restype = ctypes.c_int
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.nl_assemble_1d_sub.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, ctypes.c_int, u64p, ctypes.c_int, ip, ip, dp]
+        lib.nl_assemble_1d_sub.restype = ctypes.c_int
+        lib.nl_assemble_2d_sub.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           u64p, ctypes.c_int, ip, ip, dp]
+        lib.nl_assemble_2d_sub.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -410,6 +419,7 @@ class Partition:
     gamma_nodes: np.ndarray   # sorted free-node ids of the interface
     elem_member: np.ndarray   # (n_interior_elements x K) bool: E in hat-Omega_k
     cuts: tuple               # cut positions (cell units) per axis
+    node_free: np.ndarray = None   # (free nodes x K) bool: node of hat-Omega_k
 
 
 def partition(spec: Spec, rho: float | None = None) -> Partition:
@@ -437,7 +447,7 @@ def partition(spec: Spec, rho: float | None = None) -> Partition:
         cnt = node_in[free].sum(axis=1)
         gamma = np.nonzero(cnt >= 2)[0]                  # free-node ids (a-1)
         interior = [np.nonzero((cnt == 1) & node_in[free, k])[0] for k in range(K)]
-        return Partition(K, interior, gamma, member, (tuple(cx),))
+        return Partition(K, interior, gamma, member, (tuple(cx),), node_in[free])
     # 2D
     kx, ky = spec.cuts
     cx = _cut_positions(n, kx, spec.jitter, spec.jitter_seeds[0])
@@ -486,7 +496,7 @@ def partition(spec: Spec, rho: float | None = None) -> Partition:
     cnt = node_in[free_ext].sum(axis=1)
     gamma = np.nonzero(cnt >= 2)[0]
     interior = [np.nonzero((cnt == 1) & node_in[free_ext, k])[0] for k in range(K)]
-    return Partition(K, interior, gamma, member, (tuple(cx), tuple(cy)))
+    return Partition(K, interior, gamma, member, (tuple(cx), tuple(cy)), node_in[free_ext])
 
 
 # --------------------------------------------------------------------------
@@ -593,3 +603,294 @@ def scaled(spec_fn, scale: float, **kw) -> Spec:
     kw2 = dict(kw)
     kw2["n"] = n
     return spec_fn(**kw2)
+
+
+# --------------------------------------------------------------------------
+# Subdomain data of the dual method (section "FETI"): for every subdomain k its
+# copy Gamma_k of the interface (the interface dofs of hat-Omega_k), the
+# subdomain stiffness blocks of eq. subStiffnessMatrix assembled with the
+# zeta-weighted form of eq. bilinear-multi1, the floating flag (Gamma^D_k
+# empty, remark "floating") and the kernel of the subdomain operator.
+# --------------------------------------------------------------------------
+@dataclass
+class FetiProblem:
+    wl: "Workload"
+    g_sets: list          # per k: interface indices (dd's numbering) of Gamma_k, increasing
+    agg: list             # per k: CSR |G_k| x |G_k|, zeta-weighted A^k_GG
+    agi: list             # per k: CSR |G_k| x n_i, A^k_GI of the zeta-weighted assembly
+    kig: list             # per k: CSR n_i x |G_k|, A(I_k, Gamma_k) of the global matrix
+    floating: list        # per k: True if Gamma^D_k is empty
+    z: list               # per k: |G_k| x n_z kernel basis of S_k on Gamma_k (n_z = 0 if not floating)
+    member: np.ndarray    # (extended elements x K) bool: E in hat-Omega_k u Gamma^D_k
+    zeta_nodes: np.ndarray  # per interface dof: number of copies (zeta(x, x))
+
+    @property
+    def dd(self):
+        return self.wl.dd
+
+
+def _ext_membership(spec: Spec, part: Partition) -> np.ndarray:
+    """(extended elements x K) membership of hat-Omega_k u Gamma^D_k: elements
+    of (0,1)^d from the partition, collar elements within delta of
+    tilde-Omega_k (section "Building substructures": Gamma^D_k is the
+    interaction domain of tilde-Omega_k)."""
+    n, c, K = spec.n, spec.collar, part.K
+    N = n + 2 * c
+    dc = spec.delta * n                                  # delta in cell units
+    if spec.dim == 1:
+        member = np.zeros((N, K), dtype=bool)
+        member[c:c + n] = part.elem_member
+        cx = np.array(part.cuts[0])
+        e = np.arange(N) - c                              # element [e, e+1] in cell units
+        coll = (e < 0) | (e >= n)
+        for k in range(K):
+            d = np.maximum(0, np.maximum(cx[k] - (e + 1), e - cx[k + 1]))
+            member[coll, k] = d[coll] <= dc + 1e-12
+        return member
+    cx, cy = np.array(part.cuts[0]), np.array(part.cuts[1])
+    kx = len(cx) - 1
+    A_, B_ = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    A_ = A_.reshape(-1) - c
+    B_ = B_.reshape(-1) - c
+    tv = {0: ((0, 0), (1, 0), (1, 1)), 1: ((0, 0), (1, 1), (0, 1))}
+    vx = np.empty((2 * N * N, 3)); vy = np.empty((2 * N * N, 3))
+    for t in (0, 1):
+        vx[t::2] = np.stack([A_ + d[0] for d in tv[t]], axis=1)
+        vy[t::2] = np.stack([B_ + d[1] for d in tv[t]], axis=1)
+    cell_a = np.repeat(A_, 2)
+    cell_b = np.repeat(B_, 2)
+    inside = (cell_a >= 0) & (cell_a < n) & (cell_b >= 0) & (cell_b < n)
+    member = np.zeros((2 * N * N, K), dtype=bool)
+    # elements of (0,1)^2: element 2 (b n + a) + t of the partition
+    idx_in = 2 * (cell_b[inside] * n + cell_a[inside]) + np.tile([0, 1], N * N)[inside]
+    member[inside] = part.elem_member[idx_in]
+    for k in range(K):
+        i, j = k % kx, k // kx
+        x0, x1, y0, y1 = float(cx[i]), float(cx[i + 1]), float(cy[j]), float(cy[j + 1])
+        dxv = np.maximum(0.0, np.maximum(x0 - vx, vx - x1))
+        dyv = np.maximum(0.0, np.maximum(y0 - vy, vy - y1))
+        d2 = (dxv * dxv + dyv * dyv).min(axis=1)
+        for (px, py) in ((x0, y0), (x1, y0), (x1, y1), (x0, y1)):
+            for e0, e1 in ((0, 1), (1, 2), (2, 0)):
+                d2 = np.minimum(d2, _point_seg_dist2(px, py, vx[:, e0], vy[:, e0], vx[:, e1], vy[:, e1]))
+        member[~inside, k] = d2[~inside] <= dc * dc + 1e-9
+    return member
+
+
+def feti_problem(wl: Workload) -> FetiProblem:
+    spec, part, dd, A = wl.spec, wl.part, wl.dd, wl.asm.A.tocsr()
+    nc, K = spec.ncomp, part.K
+    n, c = spec.n, spec.collar
+    N = n + 2 * c
+    member = _ext_membership(spec, part)
+    if K > 64:
+        raise ValueError("at most 64 subdomains")
+    masks = (member.astype(np.uint64) << np.arange(K, dtype=np.uint64)[None, :]).sum(axis=1,
+                                                                                   dtype=np.uint64)
+    gidx = np.full(dd.n_dof, -1, dtype=np.int64)
+    gidx[dd.gamma_map] = np.arange(dd.n_gamma)
+    gnode_set = np.zeros(part.node_free.shape[0], dtype=bool)
+    gnode_set[part.gamma_nodes] = True
+    # rows: (interface node m of subdomain k) in subdomain order
+    rows_node, rows_sub, g_sets = [], [], []
+    for k in range(K):
+        nodes = np.nonzero(part.node_free[:, k] & gnode_set)[0]
+        g_sets.append(np.sort(gidx[(nodes[:, None] * nc + np.arange(nc)[None, :]).reshape(-1)]))
+        if spec.dim == 1:
+            ext = c + 1 + nodes
+        else:
+            fa, fb = nodes % (n - 1) + 1, nodes // (n - 1) + 1
+            ext = (fb + c) * (N + 1) + (fa + c)
+        rows_node.append(ext)
+        rows_sub.append(np.full(nodes.size, k))
+    rows_node = np.ascontiguousarray(np.concatenate(rows_node), dtype=np.int32)
+    rows_sub = np.ascontiguousarray(np.concatenate(rows_sub), dtype=np.int32)
+    P = rows_node.size
+    R = window_radius(spec)
+    Wd = 2 * R + 1
+    lib = _load()
+    ip = ctypes.POINTER(ctypes.c_int)
+    mp = np.ascontiguousarray(masks)
+    if spec.dim == 1:
+        win = np.zeros(P * Wd)
+        rc = lib.nl_assemble_1d_sub(n, c, spec.delta, spec.phi, R, _nthreads(),
+                                    mp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), P,
+                                    rows_node.ctypes.data_as(ip), rows_sub.ctypes.data_as(ip),
+                                    win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    else:
+        rowlen = Wd * Wd * (4 if spec.kernel == KER_PD else 1)
+        win = np.zeros(P * rowlen)
+        rc = lib.nl_assemble_2d_sub(n, c, spec.delta, spec.kernel, spec.phi, spec.s, R, _nthreads(),
+                                    mp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), P,
+                                    rows_node.ctypes.data_as(ip), rows_sub.ctypes.data_as(ip),
+                                    win.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise RuntimeError(f"subdomain assembly failed ({rc})")
+    # windows -> (row dof, column dof) entries over free dofs
+    if spec.dim == 1:
+        da = np.arange(-R, R + 1)
+        col_ext = rows_node[:, None] + da[None, :]
+        col_free = col_ext - c - 1
+        ok = (col_free >= 0) & (col_free < n - 1)
+        r = np.repeat(np.arange(P), Wd).reshape(P, Wd)[ok]
+        cfree = col_free[ok]
+        v = win.reshape(P, Wd)[ok]
+        row_dof = (rows_node - c - 1)[r]
+        col_dof = cfree
+    else:
+        dd_ = np.arange(-R, R + 1)
+        DB, DA = np.meshgrid(dd_, dd_, indexing="ij")
+        ra, rb = rows_node % (N + 1), rows_node // (N + 1)
+        ca_ = ra[:, None] + DA.reshape(-1)[None, :] - c
+        cb_ = rb[:, None] + DB.reshape(-1)[None, :] - c
+        okn = (ca_ > 0) & (ca_ < n) & (cb_ > 0) & (cb_ < n)
+        cfn = (cb_ - 1) * (n - 1) + (ca_ - 1)
+        rfn = (rb - c - 1) * (n - 1) + (ra - c - 1)
+        if nc == 1:
+            r = np.repeat(np.arange(P)[:, None], Wd * Wd, axis=1)[okn]
+            v = win.reshape(P, Wd * Wd)[okn]
+            row_dof = rfn[r]
+            col_dof = cfn[okn]
+        else:
+            wv = win.reshape(P, 2, Wd * Wd, 2)
+            rr, cc, vv, pp = [], [], [], []
+            for rcomp in range(2):
+                for ccomp in range(2):
+                    vals = wv[:, rcomp, :, ccomp][okn]
+                    pr = np.repeat(np.arange(P)[:, None], Wd * Wd, axis=1)[okn]
+                    rr.append(rfn[pr] * 2 + rcomp)
+                    cc.append(cfn[okn] * 2 + ccomp)
+                    vv.append(vals)
+                    pp.append(pr)
+            row_dof = np.concatenate(rr)
+            col_dof = np.concatenate(cc)
+            v = np.concatenate(vv)
+            r = np.concatenate(pp)
+    keep = v != 0.0
+    row_dof, col_dof, v, r = row_dof[keep], col_dof[keep], v[keep], r[keep]
+    sub_of = rows_sub[r]
+    owner = np.full(dd.n_dof, -1, dtype=np.int64)
+    iloc = np.full(dd.n_dof, -1, dtype=np.int64)
+    for k, I in enumerate(dd.i_maps):
+        owner[I] = k
+        iloc[I] = np.arange(I.size)
+    agg, agi, kig, floating, zs = [], [], [], [], []
+    zeta_nodes = np.zeros(dd.n_gamma, dtype=np.int64)
+    for k in range(K):
+        G = g_sets[k]
+        zeta_nodes[G] += 1
+        gl = np.full(dd.n_gamma, -1, dtype=np.int64)
+        gl[G] = np.arange(G.size)
+        sel = sub_of == k
+        rg = gl[gidx[row_dof[sel]]]
+        cg_all = gidx[col_dof[sel]]
+        vk = v[sel]
+        in_g = cg_all >= 0
+        cgl = np.where(in_g, gl[np.maximum(cg_all, 0)], -1)
+        okg = in_g & (cgl >= 0)
+        if np.any(rg < 0):
+            raise AssertionError("row outside Gamma_k")
+        agg.append(sp.csr_matrix((vk[okg], (rg[okg], cgl[okg])), shape=(G.size, G.size)))
+        # columns in interiors: must be subdomain k's own
+        cown = owner[col_dof[sel]]
+        oki = (~in_g) & (cown >= 0)
+        if np.any(cown[oki] != k):
+            raise AssertionError("subdomain row couples to another interior")
+        ni = dd.i_maps[k].size
+        agi.append(sp.csr_matrix((vk[oki], (rg[oki], iloc[col_dof[sel]][oki])), shape=(G.size, ni)))
+        kig.append(A[dd.i_maps[k]][:, dd.gamma_map[G]].tocsr())
+        fl = not member[:, k][_collar_elements(spec)].any()
+        floating.append(fl)
+        if not fl:
+            zs.append(np.zeros((G.size, 0)))
+        elif nc == 1:
+            zs.append(np.ones((G.size, 1)))
+        else:
+            nodes = dd.gamma_map[G] // 2
+            comp = dd.gamma_map[G] % 2
+            xy = wl.asm.coords[nodes]
+            Z = np.zeros((G.size, 3))
+            Z[comp == 0, 0] = 1.0
+            Z[comp == 1, 1] = 1.0
+            Z[:, 2] = np.where(comp == 0, -xy[:, 1], xy[:, 0])     # rotation (-y, x)
+            zs.append(Z)
+    for M in agg + agi + kig:
+        M.sort_indices()
+    return FetiProblem(wl, g_sets, agg, agi, kig, floating, zs, member, zeta_nodes)
+
+
+def _collar_elements(spec: Spec) -> np.ndarray:
+    """Mask of the collar (Dirichlet) elements of the extended mesh."""
+    n, c = spec.n, spec.collar
+    N = n + 2 * c
+    if spec.dim == 1:
+        e = np.arange(N) - c
+        return (e < 0) | (e >= n)
+    A_, B_ = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    a = np.repeat(A_.reshape(-1) - c, 2)
+    b = np.repeat(B_.reshape(-1) - c, 2)
+    return ~((a >= 0) & (a < n) & (b >= 0) & (b < n))
+
+
+def feti_loads(fp: FetiProblem, nrhs: int | None = None, seed_base: int | None = None) -> list:
+    """Per subdomain the interface part of the load of eq. bilinear-multi5,
+    int_{hat-Omega_k} f psi_m zeta(x,x)^-1 dx, for the nodal values of rhs()
+    (P1 f_h, zero off the free nodes): per k an array |G_k| x nrhs."""
+    wl = fp.wl
+    spec, dd = wl.spec, wl.dd
+    nrhs = spec.nrhs if nrhs is None else nrhs
+    seed_base = spec.seed_base if seed_base is None else seed_base
+    nfree = dd.n_dof
+    F = np.empty((nfree, nrhs))
+    for r in range(nrhs):
+        F[:, r] = splitmix64_uniform_fast(seed_base + r, nfree)
+    n, c, nc = spec.n, spec.collar, spec.ncomp
+    N = n + 2 * c
+    member = fp.member
+    zeta_e = member.sum(axis=1)
+    out = []
+    gidx = np.full(dd.n_dof, -1, dtype=np.int64)
+    gidx[dd.gamma_map] = np.arange(dd.n_gamma)
+    for k in range(len(fp.g_sets)):
+        G = fp.g_sets[k]
+        gl = np.full(dd.n_gamma, -1, dtype=np.int64)
+        gl[G] = np.arange(G.size)
+        fk = np.zeros((G.size, nrhs))
+        if spec.dim == 1:
+            h = spec.h
+            loc = h / 6.0 * np.array([[2.0, 1.0], [1.0, 2.0]])
+            for e in np.nonzero(member[:, k] & ~_collar_elements(spec))[0]:
+                verts = [e, e + 1]                               # extended node ids
+                fr = [v - c - 1 for v in verts]                  # free node ids
+                for i in range(2):
+                    if not (0 <= fr[i] < n - 1):
+                        continue
+                    gi = gidx[fr[i]]
+                    if gi < 0 or gl[gi] < 0:
+                        continue
+                    for j in range(2):
+                        if 0 <= fr[j] < n - 1:
+                            fk[gl[gi]] += loc[i, j] * F[fr[j]] / zeta_e[e]
+        else:
+            area = 0.5 * spec.h ** 2
+            loc = area / 12.0 * (np.ones((3, 3)) + np.eye(3))
+            tv = {0: ((0, 0), (1, 0), (1, 1)), 1: ((0, 0), (1, 1), (0, 1))}
+            for e in np.nonzero(member[:, k] & ~_collar_elements(spec))[0]:
+                cell, t = e // 2, e % 2
+                ca, cb = cell % N - c, cell // N - c
+                fr = []
+                for d in tv[t]:
+                    a, b = ca + d[0], cb + d[1]
+                    fr.append((b - 1) * (n - 1) + (a - 1) if (0 < a < n and 0 < b < n) else -1)
+                for i in range(3):
+                    if fr[i] < 0:
+                        continue
+                    for comp in range(nc):
+                        gi = gidx[fr[i] * nc + comp]
+                        if gi < 0 or gl[gi] < 0:
+                            continue
+                        for j in range(3):
+                            if fr[j] >= 0:
+                                fk[gl[gi]] += loc[i, j] * F[fr[j] * nc + comp] / zeta_e[e]
+        out.append(fk)
+    return out

@@ -65,8 +65,18 @@ static int clip_poly(double (*p)[2], int n, double sx, double sy, double c,
  * Row of free node am (extended index) for the 1D constant kernel phi on the
  * band |x-y| <= delta.  Nodes x_a = (a - c) h, a = 0..N.  win has 2R+1 slots.
  */
+/* member (optional): per element e of the extended mesh a bit mask of the
+ * subdomains k whose hat-Omega_k u Gamma^D_k holds it; then only pairs (e, f)
+ * that both lie in subdomain `sub` count, weighted by 1 / zeta(e, f) with zeta
+ * the number of subdomains holding both (eqs. zeta, bilinear-multi1). */
+static int popcount64(uint64_t v) {
+  int n = 0;
+  while (v) { v &= v - 1; ++n; }
+  return n;
+}
+
 static void row_1d(int am, int N, int c, double h, double delta, double phi,
-                   int R, double *win) {
+                   int R, double *win, const uint64_t *member, int sub) {
   int R1 = (int)ceil(delta / h) + 1;
   for (int ei = 0; ei < 2; ++ei) {
     int e = am - 1 + ei;                 /* element [e, e+1] holds am */
@@ -82,6 +92,11 @@ static void row_1d(int am, int N, int c, double h, double delta, double phi,
       int n2 = clip_poly(t1, n1, 1.0, -1.0, delta, t2);  /* x - y <= delta */
       if (n2 < 3) continue;
       double wf = (am == f || am == f + 1) ? 1.0 : 2.0;
+      if (member) {
+        const uint64_t both = member[e] & member[f];
+        if (!((both >> sub) & 1u)) continue;
+        wf /= (double)popcount64(both);
+      }
       int verts[4] = {e, e + 1, f, f + 1};
       double acc[4] = {0, 0, 0, 0};
       for (int k = 1; k + 1 < n2; ++k) {
@@ -136,7 +151,23 @@ int nl_assemble_1d(int n, int c, double delta, double phi, int R, int nthreads,
   memset(win, 0, sizeof(double) * (size_t)(n - 1) * (2 * R + 1));
 #pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
   for (int i = 0; i < n - 1; ++i)
-    row_1d(c + 1 + i, N, c, h, delta, phi, R, win + (size_t)i * (2 * R + 1));
+    row_1d(c + 1 + i, N, c, h, delta, phi, R, win + (size_t)i * (2 * R + 1), NULL, 0);
+  return 0;
+}
+
+/* Rows of the subdomain matrices A^k of eq. subStiffnessMatrix (the form of
+ * eq. bilinear-multi1): row p is node row_node[p] (extended index a) of
+ * subdomain row_sub[p]; member[e] (e = 0..N-1) as for row_1d. */
+int nl_assemble_1d_sub(int n, int c, double delta, double phi, int R, int nthreads,
+                       const uint64_t *member, int P, const int *row_node, const int *row_sub,
+                       double *win /* P x (2R+1) */) {
+  double h = 1.0 / n;
+  int N = n + 2 * c;
+  if (R < (int)ceil(delta / h) + 2) return -1;
+  memset(win, 0, sizeof(double) * (size_t)P * (2 * R + 1));
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+  for (int p = 0; p < P; ++p)
+    row_1d(row_node[p], N, c, h, delta, phi, R, win + (size_t)p * (2 * R + 1), member, row_sub[p]);
   return 0;
 }
 
@@ -271,7 +302,11 @@ static void pair_2d(const prob2d_t *P, const int ea[3], const int eb[3],
   }
 }
 
-static void row_2d(const prob2d_t *P, int ma, int mb, double *win) {
+/* member (optional): per element of the extended mesh (index 2 (cb N + ca) + t)
+ * the bit mask of the subdomains holding it; then only pairs that both lie in
+ * subdomain `sub` count, weighted by 1 / zeta(E, F) (eqs. zeta,
+ * bilinear-multi1). */
+static void row_2d(const prob2d_t *P, int ma, int mb, double *win, const uint64_t *member, int sub) {
   int R1 = (int)ceil(P->delta / P->h) + 1;
   int vec = (P->kernel == KER_PD);
   int W = P->W;
@@ -295,6 +330,12 @@ static void row_2d(const prob2d_t *P, int ma, int mb, double *win) {
               long BFa = fa[0] + fa[1] + fa[2], BFb = fb[0] + fb[1] + fb[2];
               long D = (BEa - BFa) * (BEa - BFa) + (BEb - BFb) * (BEb - BFb);
               if (D > P->thr) continue;
+              double zw = 1.0;
+              if (member) {
+                const uint64_t both = member[2 * (cb * P->N + ca) + t] & member[2 * (fb0 * P->N + fa0) + tf];
+                if (!((both >> sub) & 1u)) continue;
+                zw = 1.0 / (double)popcount64(both);
+              }
               /* union vertex list */
               int uva[6], uvb[6], nu = 0;
               for (int k = 0; k < 3; ++k) { uva[nu] = ea[k]; uvb[nu] = eb[k]; ++nu; }
@@ -306,7 +347,7 @@ static void row_2d(const prob2d_t *P, int ma, int mb, double *win) {
                 if (fa[k] == ma && fb[k] == mb) mInF = 1;
                 if (!dup) { uva[nu] = fa[k]; uvb[nu] = fb[k]; ++nu; }
               }
-              double wf = mInF ? 1.0 : 2.0;
+              double wf = (mInF ? 1.0 : 2.0) * zw;
               double acc[24];
               memset(acc, 0, sizeof(acc));
               if (P->kernel == KER_FRAC && touching) {
@@ -354,7 +395,31 @@ int nl_assemble_2d(int n, int c, double delta, int kernel, double phi,
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
   for (long i = 0; i < (long)nrow; ++i) {
     int ia = (int)(i % (n - 1)), ib = (int)(i / (n - 1));
-    row_2d(&P, c + 1 + ia, c + 1 + ib, win + (size_t)i * rowlen);
+    row_2d(&P, c + 1 + ia, c + 1 + ib, win + (size_t)i * rowlen, NULL, 0);
+  }
+  return 0;
+}
+
+/* Rows of the subdomain matrices A^k (eq. subStiffnessMatrix with the form of
+ * eq. bilinear-multi1): row p is extended node row_node[p] = b (N+1) + a of
+ * subdomain row_sub[p], in the window layout of nl_assemble_2d. */
+int nl_assemble_2d_sub(int n, int c, double delta, int kernel, double phi, double s, int R,
+                       int nthreads, const uint64_t *member, int P, const int *row_node,
+                       const int *row_sub, double *win) {
+  init_rules();
+  prob2d_t Q;
+  Q.kernel = kernel; Q.phi = phi; Q.s = s;
+  Q.h = 1.0 / n; Q.delta = delta; Q.c = c; Q.N = n + 2 * c;
+  double t = 3.0 * delta / Q.h;
+  Q.thr = (long)floor(t * t);
+  Q.R = R; Q.W = 2 * R + 1;
+  if (R < (int)ceil(delta / Q.h) + 2) return -1;
+  size_t rowlen = (size_t)Q.W * Q.W * (kernel == KER_PD ? 4 : 1);
+  memset(win, 0, sizeof(double) * rowlen * (size_t)P);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+  for (long p = 0; p < (long)P; ++p) {
+    int a = row_node[p] % (Q.N + 1), b = row_node[p] / (Q.N + 1);
+    row_2d(&Q, a, b, win + (size_t)p * rowlen, member, row_sub[p]);
   }
   return 0;
 }
