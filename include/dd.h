@@ -348,6 +348,67 @@ void dd_destroy(dd_ctx *ctx);
 dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel, double phi,
                          double s, int32_t R, double *win_dev, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * One-level FETI (section "FETI", Algorithm 1): the dual method on the same
+ * reduced multi-domain problem (eq. discreteSubNonlocal).  Every subdomain k
+ * keeps its own copy Gamma_k of the interface dofs of hat-Omega_k; the
+ * copies are tied by Lagrange multipliers lambda, one per pair of consecutive
+ * copies of a dof (B: one +1 and one -1 per row), and the projected
+ * preconditioned CG runs on P F lambda = P d (eq. FETIproblem) with
+ * F = B S^+ B^T, the natural coarse space G = B Z of the floating subdomains'
+ * kernels (eq. P), lambda_0 = G (G^T G)^-1 e, and the scaled Dirichlet
+ * preconditioner B_D S B_D^T (eq. preconditioner).  S_k^+ comes from the
+ * Cholesky factor of A^k with pinned dofs for floating subdomains (section
+ * "Pseudoinverse and Cholesky decomposition"), the pins chosen where the
+ * kernel basis is best conditioned; alpha and u by eqs. forAlpha and forU,
+ * then the interiors by eq. backwardSubstitution. */
+typedef struct dd_feti_ctx dd_feti_ctx;
+
+/* The FETI data of one subdomain, HOST pointers (read during dd_feti_setup). */
+typedef struct {
+  int32_t n_g;                /* dofs of Gamma_k (the interface dofs of hat-Omega_k) */
+  const int32_t *g_map;       /* n_g: copy dof -> interface index of the problem, increasing */
+  const int32_t *agg_rowptr;  /* n_g+1: CSR of A^k_GG (eq. subStiffnessMatrixSubBlocks assembled */
+  const int32_t *agg_col;     /*   with the zeta-weighted form of eq. bilinear-multi1), n_g x n_g */
+  const double *agg_val;
+  const int32_t *kig_rowptr;  /* n_i+1: CSR of A^k_IG = A(I_k, Gamma_k), columns in [0, n_g) */
+  const int32_t *kig_col;
+  const double *kig_val;
+  int32_t n_z;                /* 0 if Gamma^D_k is non-empty, else the dimension of ker A^k
+                                 (1 for scalar kernels, 3 for peridynamics; at most 8) */
+  const double *z;            /* n_g x n_z column-major: that kernel on Gamma_k */
+} dd_feti_sub;
+
+/* Set up FETI for `prob` (whose subdomains give K_II^k and the interior maps;
+ * prob is validated as by dd_setup) and the copies fsub[0 .. prob->n_sub).
+ * Forms B, B_D, Z, G and (G^T G)^-1 (host), and factors and inverts the
+ * pinned subdomain matrices on the device (dense, n_i + n_g rows each) to
+ * keep the interface blocks that give S_k^+.  Loads b_G are split evenly over
+ * the copies of a dof (the constrained problem sees only their sum, so the
+ * solution does not depend on the split).  max_nrhs in [1, 64].  Errors:
+ * DD_EINVAL (field named; message by dd_feti_last_error(NULL)), DD_ENOMEM,
+ * DD_ENOTSPD (a pinned subdomain matrix or G^T G not positive definite),
+ * DD_EHIP. */
+dd_status dd_feti_setup(const dd_problem *prob, const dd_feti_sub *fsub, void *hip_stream,
+                        int32_t max_nrhs, dd_feti_ctx **out);
+
+/* Factor the interior blocks K_II^k (the Dirichlet solves of S_k in the
+ * preconditioner, the reduced forcing of eq. subForcing and the back
+ * substitution), FP64. */
+dd_status dd_feti_factor(dd_feti_ctx *ctx);
+
+/* Solve A u = b (b_dev, u_dev: D, column-major n_dof x nrhs, leading
+ * dimension ld >= n_dof, no aliasing).  Column c stops when the projected
+ * residual ||P r_c||_2 <= tol ||P r_c^0||_2 or after max_it iterations.
+ * info_host (H, nrhs entries, may be NULL): iterations, converged, and the
+ * FP64 full-system relative residual ||b - A u|| / ||b||.  DD_ENOCONV if a
+ * column missed the tolerance, DD_ENOTSPD on p^T F p <= 0. */
+dd_status dd_feti_solve(dd_feti_ctx *ctx, const double *b_dev, double *u_dev, int32_t nrhs, int32_t ld,
+                        double tol, int32_t max_it, dd_solve_info *info_host);
+
+const char *dd_feti_last_error(const dd_feti_ctx *ctx);
+void dd_feti_destroy(dd_feti_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

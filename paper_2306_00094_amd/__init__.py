@@ -30,7 +30,8 @@ EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solv
             "dd_schur_apply", "dd_get_factor", "dd_get_schur_diag", "dd_autotune",
             "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
             "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy",
-            "dd_assemble_2d"]
+            "dd_assemble_2d", "dd_feti_setup", "dd_feti_factor", "dd_feti_solve", "dd_feti_last_error",
+            "dd_feti_destroy"]
 DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
 DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE, DD_PHASE_LOOP = range(5)
 DD_NPHASES = 5
@@ -72,6 +73,12 @@ class dd_tune_result(ctypes.Structure):
                 ("direction_kernel", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("ms_per_solve", ctypes.c_double), ("candidates", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("three_launch", ctypes.c_int32)]
+
+
+class dd_feti_sub(ctypes.Structure):
+    _fields_ = [("n_g", ctypes.c_int32), ("g_map", _i32p), ("agg_rowptr", _i32p), ("agg_col", _i32p),
+                ("agg_val", _f64p), ("kig_rowptr", _i32p), ("kig_col", _i32p), ("kig_val", _f64p),
+                ("n_z", ctypes.c_int32), ("z", _f64p)]
 
 
 class DDError(RuntimeError):
@@ -119,6 +126,17 @@ def load_library(path: str = LIB_PATH):
     lib.dd_destroy.restype = None
     lib.dd_assemble_2d.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
+    lib.dd_feti_setup.argtypes = [ctypes.POINTER(dd_problem), ctypes.POINTER(dd_feti_sub), vp, ctypes.c_int32,
+                                  ctypes.POINTER(vp)]
+    lib.dd_feti_factor.argtypes = [vp]
+    lib.dd_feti_solve.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.POINTER(dd_solve_info)]
+    lib.dd_feti_last_error.argtypes = [vp]
+    lib.dd_feti_last_error.restype = ctypes.c_char_p
+    lib.dd_feti_destroy.argtypes = [vp]
+    lib.dd_feti_destroy.restype = None
+    for name in ("dd_feti_setup", "dd_feti_factor", "dd_feti_solve"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("dd_footprint", "dd_setup", "dd_factor", "dd_solve", "dd_schur_apply",
                  "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
                  "dd_autotune", "dd_batch_begin", "dd_batch_admit", "dd_batch_step",
@@ -387,6 +405,112 @@ class Solver:
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None:
             dd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- one-level FETI
+def _feti_check(lib, status: int, ctx=None):
+    if status != DD_OK:
+        msg = lib.dd_feti_last_error(ctx)
+        raise DDError(status, msg.decode() if msg else "")
+
+
+class _FetiSubs:
+    """ctypes view of the per-subdomain FETI data (keeps the arrays alive).
+    fp: workloads.FetiProblem-like object with g_sets, agg, kig and, per
+    floating subdomain, z (empty for the others)."""
+
+    def __init__(self, fp):
+        self.keep = []
+
+        def i32(a):
+            a = np.ascontiguousarray(a, dtype=np.int32)
+            self.keep.append(a)
+            return a.ctypes.data_as(_i32p)
+
+        def f64(a):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self.keep.append(a)
+            return a.ctypes.data_as(_f64p)
+
+        K = len(fp.g_sets)
+        self.subs = (dd_feti_sub * K)()
+        for k in range(K):
+            agg = fp.agg[k].tocsr()
+            kig = fp.kig[k].tocsr()
+            z = np.asarray(fp.z[k], dtype=np.float64)
+            s = self.subs[k]
+            s.n_g = int(len(fp.g_sets[k]))
+            s.g_map = i32(fp.g_sets[k])
+            s.agg_rowptr, s.agg_col, s.agg_val = i32(agg.indptr), i32(agg.indices), f64(agg.data)
+            s.kig_rowptr, s.kig_col, s.kig_val = i32(kig.indptr), i32(kig.indices), f64(kig.data)
+            s.n_z = int(z.shape[1]) if fp.floating[k] else 0
+            s.z = f64(z.ravel(order="F")) if s.n_z else None
+
+
+def dd_feti_setup(dd, fp, stream=None, max_nrhs: int = 1):
+    lib = load_library()
+    pb = _Problem(dd)
+    fs = _FetiSubs(fp)
+    ctx = ctypes.c_void_p()
+    st = lib.dd_feti_setup(ctypes.byref(pb.p), fs.subs, _stream_handle(stream), max_nrhs, ctypes.byref(ctx))
+    _feti_check(lib, st, None)
+    return ctx
+
+
+def dd_feti_factor(ctx) -> None:
+    lib = load_library()
+    _feti_check(lib, lib.dd_feti_factor(ctx), ctx)
+
+
+def dd_feti_solve(ctx, b, u, nrhs: int, ld: int, tol: float, max_it: int, raise_on_noconv: bool = True):
+    lib = load_library()
+    info = (dd_solve_info * nrhs)()
+    st = lib.dd_feti_solve(ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()), nrhs, ld, tol,
+                           max_it, info)
+    if st != DD_OK and not (st == DD_ENOCONV and not raise_on_noconv):
+        _feti_check(lib, st, ctx)
+    return st, [dict(iters=i.iters, converged=i.converged, rel_resid=i.rel_resid) for i in info]
+
+
+def dd_feti_destroy(ctx) -> None:
+    if ctx is not None and ctx.value:
+        load_library().dd_feti_destroy(ctx)
+
+
+class FetiSolver:
+    """One-level FETI context (dd_feti_*) bound to a torch stream."""
+
+    def __init__(self, dd, fp, max_nrhs: int = 1, stream=None):
+        import torch
+        self.torch = torch
+        self.n_dof = int(dd.n_dof)
+        self.max_nrhs = max_nrhs
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = dd_feti_setup(dd, fp, self.stream, max_nrhs)
+
+    def factor(self) -> None:
+        dd_feti_factor(self.ctx)
+
+    def solve(self, b, tol: float = 1e-10, max_it: int = 1000, raise_on_noconv: bool = True) -> SolveResult:
+        torch = self.torch
+        nrhs = int(b.shape[0])
+        ld = int(b.stride(0)) if nrhs > 1 else int(b.shape[1])
+        if b.dtype != torch.float64 or not b.is_cuda or (b.shape[1] > 1 and b.stride(1) != 1):
+            raise ValueError("b must be a CUDA float64 tensor with unit inner stride")
+        u = torch.empty((nrhs, ld), dtype=torch.float64, device=b.device)
+        st, info = dd_feti_solve(self.ctx, b, u, nrhs, ld, tol, max_it, raise_on_noconv)
+        return SolveResult(u[:, :self.n_dof], st, info)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None:
+            dd_feti_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

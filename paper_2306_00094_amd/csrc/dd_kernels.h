@@ -251,6 +251,33 @@ __device__ __forceinline__ bool last_of(unsigned *counter, unsigned members, int
   return *lds_flag != 0;
 }
 
+// Group sums (as chunk_group_sum) of every column c < ld, written to
+// out[g * ld + c] by device-coherent stores: wave wv of nw takes 8 columns per
+// pass, issues all their loads before the butterflies and all stores before a
+// single wait for completion (one memory round trip per pass, not one load and
+// one store round trip per column).
+__device__ __forceinline__ void group_sums_store(const double *part, int P, int ld, int g,
+                                                 double *out, int wv, int nw) {
+  constexpr int NC = 8;
+  const int m = g * kPGroup + lane_id();
+  for (int c0 = wv * NC; c0 < ld; c0 += nw * NC) {
+    double v[NC];
+#pragma unroll
+    for (int u = 0; u < NC; ++u)
+      v[u] = (c0 + u < ld && m < P) ? __hip_atomic_load(part + (size_t)m * ld + c0 + u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0.0;
+#pragma unroll
+    for (int u = 0; u < NC; ++u) v[u] = wave_sum(v[u]);
+    if (lane_id() == 0)
+#pragma unroll
+      for (int u = 0; u < NC; ++u)
+        if (c0 + u < ld)
+          __hip_atomic_store(out + (size_t)g * ld + c0 + u, v[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the group sums are stored
+}
+
 // Sum of chunk partials g*kPGroup .. g*kPGroup+63 (those < P) of column c.
 __device__ __forceinline__ double chunk_group_sum(const double *part, int P, int ld, int c, int g) {
   const int m = g * kPGroup + lane_id();
@@ -763,10 +790,7 @@ __device__ __forceinline__ void gamma_rows_body(int nrows, const int *__restrict
   __shared__ int lflag;
   unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
   if (!last_of(cnt, (unsigned)members, &lflag)) return;
-  for (int c = wv; c < ld; c += NW) {
-    double g = chunk_group_sum(red.part2, gridDim.x, ld, c, grp);
-    if (lane == 0) store_partial(red.part3 + (size_t)grp * ld + c, g);
-  }
+  group_sums_store(red.part2, gridDim.x, ld, grp, red.part3, wv, NW);
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(cnt);
 }
@@ -942,14 +966,8 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
     if (!last_of(cnt, (unsigned)members, &lflag)) return;
     double *gs0 = red.part2, *gs1 = red.part2 + (size_t)ngrp * ld;
-    for (int c = wv; c < ld; c += kWavesPerBlock) {
-      const double a0 = chunk_group_sum(red.part0, nchunks, ld, c, grp);
-      const double a1 = chunk_group_sum(red.part1, nchunks, ld, c, grp);
-      if (lane == 0) {
-        store_partial(gs0 + (size_t)grp * ld + c, a0);
-        store_partial(gs1 + (size_t)grp * ld + c, a1);
-      }
-    }
+    group_sums_store(red.part0, nchunks, ld, grp, gs0, wv, kWavesPerBlock);
+    group_sums_store(red.part1, nchunks, ld, grp, gs1, wv, kWavesPerBlock);
     __syncthreads();
     if (threadIdx.x == 0) reset_counter(cnt);
     if (!last_of(&red.counter[1], (unsigned)ngrp, &lflag)) return;

@@ -1437,6 +1437,30 @@ void full_residual(dd_ctx *c, const double *bI, const double *bG, const double *
   gamma_rows<double>(c, c->d_g_val64, plain(uG), uI, ld, bG, -1.0, -1.0, rG, 0, nullptr);
 }
 
+// ||b_c - A u_c||_2 / ||b_c||_2 of caller-layout columns (column-major n_dof x
+// nrhs, leading dimension ld) with the FP64 blocks of the context.
+dd_status residual_cols(dd_ctx *c, const double *b, const double *u, int nrhs, int ld, double *rel) {
+  const int L = next_pow2(nrhs);
+  Work &w = c->w;
+  const int n_all = c->NI + c->n_gamma;
+  const unsigned g = std::min(4096u, grid_for((size_t)n_all * L, 256));
+  hipLaunchKernelGGL(k_gather2, dim3(g), dim3(256), 0, c->stream, c->NI, c->n_gamma, c->d_imap, c->d_gmap, b,
+                     ld, nrhs, L, w.bI, w.bG);
+  hipLaunchKernelGGL(k_gather2, dim3(g), dim3(256), 0, c->stream, c->NI, c->n_gamma, c->d_imap, c->d_gmap, u,
+                     ld, nrhs, L, w.uI, w.uG);
+  full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L);
+  hipLaunchKernelGGL(k_norm2, dim3(grid_for((size_t)n_all, kRowsE)), dim3(kBlock), 0, c->stream, c->NI,
+                     c->n_gamma, L, w.bI, w.bG, c->red, w.bnrm2, 0.0, (double *)nullptr);
+  hipLaunchKernelGGL(k_norm2, dim3(grid_for((size_t)n_all, kRowsE)), dim3(kBlock), 0, c->stream, c->NI,
+                     c->n_gamma, L, w.tI, w.tG, c->red, w.rnrm2, 0.0, (double *)nullptr);
+  HIPCHK(c, hipGetLastError());
+  StateBlock &h = *c->h_state;
+  TRY(fetch_state(c, &h, false));
+  for (int j = 0; j < nrhs; ++j)
+    rel[j] = h.bnrm2[j] > 0.0 ? std::sqrt(h.rnrm2[j] / h.bnrm2[j]) : std::sqrt(h.rnrm2[j]);
+  return DD_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI ==
@@ -2602,3 +2626,6 @@ dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel
 }
 
 }  // extern "C"
+
+#include "dd_feti.h"
+

@@ -213,10 +213,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
   __shared__ int lflag;
   unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
   if (!last_of(cnt, (unsigned)members, &lflag)) return;
-  for (int c = wv; c < ld; c += kTW) {
-    const double gs = chunk_group_sum(red.part2, gridDim.x, ld, c, grp);
-    if (lane == 0) store_partial(red.part3 + (size_t)grp * ld + c, gs);
-  }
+  group_sums_store(red.part2, gridDim.x, ld, grp, red.part3, wv, kTW);
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(cnt);
 }

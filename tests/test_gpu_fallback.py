@@ -10,7 +10,7 @@
 
 The modified systems are built on the CPU from a generated one: a diagonal
 shift of the whole matrix (A - sigma I, still positive definite, condition
-number about 1e7) or of the interface block only (K_GG - sigma I with
+number about 3e7) or of the interface block only (K_GG - sigma I with
 lambda_min(S) < sigma < min diag(S): diag(S) stays positive, S becomes
 indefinite)."""
 import copy
@@ -74,11 +74,11 @@ def full_matrix(dd):
 def ill_conditioned():
     spec, wl, b = base()
     ev = np.linalg.eigvalsh(wl.asm.A.toarray())
-    sigma = ev[0] - ev[-1] / 1e7                 # lambda_min(A - sigma I) = lambda_max / 1e7
+    sigma = ev[0] - ev[-1] / 3e7                 # lambda_min(A - sigma I) = lambda_max / 3e7
     d2 = shifted(wl.dd, sigma)
     A2 = full_matrix(d2)
     e2 = np.linalg.eigvalsh(A2.toarray())
-    assert 5e6 < e2[-1] / e2[0] < 2e7
+    assert 1e7 < e2[-1] / e2[0] < 1e8
     return d2, A2, b, e2[-1] / e2[0]
 
 
@@ -105,16 +105,17 @@ def test_fallback_forced_by_step_cap():
 
 
 def test_fallback_on_stalled_refinement():
-    """Condition number 1e7: FP32 operators cannot reduce the FP64 residual
-    by 1/2 per step, the refinement stalls and the FP64 path finishes every
-    column to the tolerance."""
+    """Condition number 3e7: FP32 operators (relative error about kappa u_32 > 1)
+    cannot reduce the FP64 residual by 1/2 per step, the refinement stalls and
+    the FP64 path finishes every column to the tolerance (1e-8: the FP64
+    floor of the relative residual is about kappa u_64 = 7e-9)."""
     dd = _dd()
     d2, A2, b, kappa = ill_conditioned()
     print(f"case fallback stall kappa={kappa:.2e}", flush=True)
     uref = oracle.monolithic_solve(A2, b)
     s = dd.Solver(d2, max_nrhs=b.shape[1])
     s.factor(dd.DD_MIXED)
-    tol = 1e-12
+    tol = 1e-8
     r = s.solve(dev(b), prec=dd.DD_MIXED, opts=dd.dd_default_opts(tol=tol, max_it=5000))
     u = r.u.cpu().numpy().T
     print(f"  info {r.info}", flush=True)
@@ -134,7 +135,7 @@ def test_serving_fallback_slots():
     from paper_2306_00094_amd import serving
     d2, A2, b, kappa = ill_conditioned()
     print("case serving fallback", flush=True)
-    tol = 1e-11
+    tol = 1e-8
     srv = serving.Server({"ill": d2}, prec=dd.DD_MIXED,
                          opts=dd.dd_default_opts(tol=tol, max_it=5000, gather32=1))
     reqs = [serving.Request("ill", b[:, j:j + 1].copy(), arrival=0.0, rid=j) for j in range(b.shape[1])]
