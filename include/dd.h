@@ -211,6 +211,18 @@ dd_status dd_solve(dd_ctx *ctx, dd_precision prec, const double *b_dev, double *
 dd_status dd_schur_apply(dd_ctx *ctx, dd_precision prec, const double *p_dev,
                          double *q_dev, int32_t nrhs, int32_t ld);
 
+/* The same product without any device allocation, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid it); dd_schur_apply allocates an index map per call.
+ * Its work vectors -- (2 n_gamma + 2 n_I) * next_pow2(nrhs) doubles -- live in
+ * a static device array of 4 Mi doubles (32 MiB) that every device the library
+ * runs on holds until the process ends; larger work is rejected with
+ * DD_EINVAL.  The context's device must be the current device.  All calls on
+ * one device share that array: calls that overlap on one GPU (several streams
+ * or host threads) race.  Same arguments, layout and errors as dd_schur_apply. */
+dd_status dd_schur_apply_noalloc(dd_ctx *ctx, dd_precision prec, const double *p_dev,
+                                 double *q_dev, int32_t nrhs, int32_t ld);
+
 /* Copy the lower Cholesky factor of subdomain k (n_i x n_i column-major,
  * upper triangle zero) to host memory `out` as doubles (diagnostic entry). */
 dd_status dd_get_factor(dd_ctx *ctx, dd_precision prec, int32_t k, double *out);

@@ -31,7 +31,7 @@ EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solv
             "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
             "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy",
             "dd_assemble_2d", "dd_feti_setup", "dd_feti_factor", "dd_feti_solve", "dd_feti_last_error",
-            "dd_feti_destroy"]
+            "dd_feti_destroy", "dd_schur_apply_noalloc"]
 DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
 DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE, DD_PHASE_LOOP = range(5)
 DD_NPHASES = 5
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.dd_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_int32,
                              ctypes.POINTER(dd_solve_opts), ctypes.POINTER(dd_solve_info)]
     lib.dd_schur_apply.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_int32]
+    lib.dd_schur_apply_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_int32]
     lib.dd_get_factor.argtypes = [vp, ctypes.c_int, ctypes.c_int32, _f64p]
     lib.dd_get_schur_diag.argtypes = [vp, ctypes.c_int, _f64p]
     lib.dd_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(dd_solve_opts),
@@ -138,7 +139,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("dd_feti_setup", "dd_feti_factor", "dd_feti_solve"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("dd_footprint", "dd_setup", "dd_factor", "dd_solve", "dd_schur_apply",
-                 "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
+                 "dd_schur_apply_noalloc", "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
                  "dd_autotune", "dd_batch_begin", "dd_batch_admit", "dd_batch_step",
                  "dd_batch_retire", "dd_batch_end", "dd_assemble_2d"):
         getattr(lib, name).restype = ctypes.c_int
@@ -248,6 +249,13 @@ def dd_solve(ctx, prec: int, b, u, nrhs: int, ld: int, opts: dd_solve_opts | Non
 def dd_schur_apply(ctx, prec: int, p, q, nrhs: int, ld: int) -> None:
     lib = load_library()
     _check(lib, lib.dd_schur_apply(ctx, prec, _dev_ptr(p), _dev_ptr(q), nrhs, ld), ctx)
+
+
+def dd_schur_apply_noalloc(ctx, prec: int, p, q, nrhs: int, ld: int) -> None:
+    """dd_schur_apply without any device allocation (work vectors in the
+    library's static device array; at most 4 Mi doubles of them)."""
+    lib = load_library()
+    _check(lib, lib.dd_schur_apply_noalloc(ctx, prec, _dev_ptr(p), _dev_ptr(q), nrhs, ld), ctx)
 
 
 def dd_get_factor(ctx, prec: int, k: int, n: int) -> np.ndarray:

@@ -2628,4 +2628,5 @@ dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel
 }  // extern "C"
 
 #include "dd_feti.h"
+#include "dd_noalloc.h"
 
