@@ -144,14 +144,24 @@ def test_bench_traffic_needs_matching_kernel_source():
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    saved = dict(bench.MEASURED_TRAFFIC)
+    import copy
+    saved = copy.deepcopy(bench.MEASURED_TRAFFIC)
     try:
-        bench.MEASURED_TRAFFIC["src_sha256"] = "0" * 16
-        assert bench.measured_traffic("k_gamma_rows<double>", saved["workload"]) is None
+        for key, m in saved.items():
+            bench.MEASURED_TRAFFIC[key] = dict(m, sha="0" * 16)
+            assert bench.measured_traffic(key, m["workload"]) is None
+            assert bench.measured_traffic(key, "another workload") is None
+            # with the sha of the file as it stands the stored figure is reported
+            import hashlib
+            src = os.path.join(root, "paper_2306_00094_amd", "csrc", m["src"])
+            with open(src, "rb") as f:
+                bench.MEASURED_TRAFFIC[key] = dict(m, sha=hashlib.sha256(f.read()).hexdigest()[:16])
+            v = bench.measured_traffic(key, m["workload"])
+            assert v == 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
     finally:
         bench.MEASURED_TRAFFIC.clear()
         bench.MEASURED_TRAFFIC.update(saved)
-    assert bench.measured_traffic("k_gamma_rows<double>", "another workload") is None
+    assert bench.measured_traffic("no such kernel", "cfg4") is None
 
 
 def test_undecomposed_problem_passes_host_checks(lib):
