@@ -37,6 +37,14 @@ tolerance and no multi-RHS scheme):
     of the full system;
   * Jacobi preconditioner with the exact diagonal of S.
 
+Two further solvers of the same discrete system, each in its own module and
+pinned by its own tests:
+* ``feti_oracle.FETIOracle`` -- the paper's one-level FETI (section "FETI",
+  Algorithm 1) on zeta-weighted subdomain matrices (tests/test_feti_oracle.py);
+* ``bdd_oracle.BDDOracle`` -- the primal interface problem with the balancing
+  Neumann-Neumann preconditioner built from the same pinned pseudoinverses
+  (tests/test_bdd_oracle.py).
+
 Pins of this oracle (tests/test_oracle.py): brute-force dense inverses on
 tiny systems, explicit dense Schur complements, DD-vs-monolithic agreement,
 CG termination in at most n_G steps, symmetry of S; for jacobi_pcg: the
