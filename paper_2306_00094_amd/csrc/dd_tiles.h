@@ -81,7 +81,10 @@ __device__ __forceinline__ void tile_mma(const double (&a)[4], const double (&xv
 // blocks are fetched 64 at a time, one per lane, and broadcast by readlane; two
 // register buffers hold the operands of the next two tiles while a tile's
 // instructions run (the last loads of a wave repeat its last tile and are not
-// used).
+// used).  Scheduling barriers keep every group of loads in program order --
+// buffer 0 before buffer 1 in the prologue as in the loop -- so that the
+// instructions of one buffer wait only for that buffer's loads, the other
+// buffer's staying in flight.
 template <typename VT, int NCB>
 __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *__restrict__ tcol,
                                              const VT *__restrict__ tval, const double *__restrict__ x,
@@ -96,24 +99,30 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
     double a0[4], x0[4][NCB], a1[4], x1[4][NCB];
     TileA<VT>::load(tv, a0);
     load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, 0), x0);
+    __builtin_amdgcn_sched_barrier(0);
     {
       const int j1 = min(1, nb - 1);
       TileA<VT>::load(tv + j1 * tstride, a1);
       load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, j1), x1);
     }
+    __builtin_amdgcn_sched_barrier(0);
     for (int j = 0; j < nb; j += 2) {
       tile_mma<NCB>(a0, x0, acc);
+      __builtin_amdgcn_sched_barrier(0);
       {
         const int jn = min(j + 2, nb - 1);
         TileA<VT>::load(tv + jn * tstride, a0);
         load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x0);
       }
+      __builtin_amdgcn_sched_barrier(0);
       if (j + 1 < nb) tile_mma<NCB>(a1, x1, acc);
+      __builtin_amdgcn_sched_barrier(0);
       {
         const int jn = min(j + 3, nb - 1);
         TileA<VT>::load(tv + jn * tstride, a1);
         load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x1);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -291,17 +300,24 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
 #pragma unroll
       for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], b[s][q], acc[q]);
   };
-  // tiles J = wv, wv + kTW, ...: two register buffers in flight
+  // tiles J = wv, wv + kTW, ...: two register buffers in flight, each group of
+  // loads kept in program order (see tile_row_acc)
   const int cnt = wv < nt ? (nt - wv + kTW - 1) / kTW : 0;
   if (cnt > 0) {
     MT a0[4], b0[4][NCB], a1[4], b1[4][NCB];
     load(wv, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     load(wv + kTW * min(1, cnt - 1), a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     for (int j = 0; j < cnt; j += 2) {
       mma(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
       load(wv + kTW * min(j + 2, cnt - 1), a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
       if (j + 1 < cnt) mma(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
       load(wv + kTW * min(j + 3, cnt - 1), a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   __shared__ double part[kTW * kT * kMaxLd];
