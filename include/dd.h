@@ -418,6 +418,47 @@ dd_status dd_feti_factor(dd_feti_ctx *ctx);
 dd_status dd_feti_solve(dd_feti_ctx *ctx, const double *b_dev, double *u_dev, int32_t nrhs, int32_t ld,
                         double tol, int32_t max_it, dd_solve_info *info_host);
 
+/* The primal interface problem S u_G = g (eq. SchurComplement summed over
+ * subdomains, eq. subForcing) by CG with the balancing Neumann-Neumann
+ * preconditioner, the primal counterpart of the scaled Dirichlet
+ * preconditioner of eq. preconditioner (section "Preconditioning"):
+ *   M^-1 = P_0 + (I - P_0 S) M_NN (I - S P_0),  M_NN = sum_k R_k^T D_k S_k^+ D_k R_k,
+ * D_k = 1 / zeta on Gamma_k, S_k^+ the pseudoinverse of the zeta-weighted
+ * subdomain Schur complement (the S^+ blocks of the FETI context), and the
+ * coarse space N = [R_k^T D_k Z_k] of the floating subdomains, P_0 = N (N^T S N)^-1 N^T
+ * (formed by the first call: S N through the primal product, N^T S N inverted
+ * on the host).  Same stopping rule as dd_solve (||r_c|| <= tol ||b_c||, x0 = 0),
+ * then eq. backwardSubstitution.  Arguments, layout and info as dd_feti_solve;
+ * DD_ENOCONV if a column missed the tolerance, DD_ENOTSPD on p^T S p <= 0 or a
+ * coarse matrix that is not positive definite. */
+dd_status dd_bdd_solve(dd_feti_ctx *ctx, const double *b_dev, double *u_dev, int32_t nrhs, int32_t ld,
+                       double tol, int32_t max_it, dd_solve_info *info_host);
+
+/* Solvers of the same system that share one FETI context. */
+typedef enum {
+  DD_METHOD_AUTO = 0,    /* the method chosen by dd_method_autotune (tuned on first use) */
+  DD_METHOD_FETI = 1,    /* dd_feti_solve: one-level FETI (Algorithm 1) */
+  DD_METHOD_BDD = 2,     /* dd_bdd_solve: primal interface CG, balancing Neumann-Neumann */
+  DD_METHOD_JACOBI = 3   /* dd_solve (FP64) on the primal context: primal CG, exact diag(S) */
+} dd_method;
+
+/* Time the three methods on a seeded batch of nrhs columns (values in [-1, 1))
+ * at tolerance tol -- the primal context first autotunes its own schedule --
+ * and keep the fastest for DD_METHOD_AUTO.  A method that misses the
+ * tolerance within max_it loses.  method (H, may be NULL): the choice; ms (H,
+ * 3 entries, may be NULL): ms per batch of FETI, BDD and Jacobi (1e300 for a
+ * method that failed to converge).  Allocates two n_dof x nrhs device buffers
+ * for the duration of the call. */
+dd_status dd_method_autotune(dd_feti_ctx *ctx, int32_t nrhs, double tol, int32_t max_it, int32_t *method,
+                             double *ms);
+
+/* Solve with `method` (dd_method); arguments as dd_feti_solve.  Note that the
+ * methods stop on their own residuals (FETI: the projected multiplier
+ * residual; BDD and Jacobi: the interface residual relative to ||b||); info
+ * always reports the full-system relative residual. */
+dd_status dd_method_solve(dd_feti_ctx *ctx, int32_t method, const double *b_dev, double *u_dev, int32_t nrhs,
+                          int32_t ld, double tol, int32_t max_it, dd_solve_info *info_host);
+
 const char *dd_feti_last_error(const dd_feti_ctx *ctx);
 void dd_feti_destroy(dd_feti_ctx *ctx);
 

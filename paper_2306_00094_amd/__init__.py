@@ -31,7 +31,9 @@ EXPORTED = ["dd_default_opts", "dd_footprint", "dd_setup", "dd_factor", "dd_solv
             "dd_set_timing", "dd_get_timing", "dd_batch_begin", "dd_batch_admit",
             "dd_batch_step", "dd_batch_retire", "dd_batch_end", "dd_last_error", "dd_destroy",
             "dd_assemble_2d", "dd_feti_setup", "dd_feti_factor", "dd_feti_solve", "dd_feti_last_error",
-            "dd_feti_destroy", "dd_schur_apply_noalloc"]
+            "dd_feti_destroy", "dd_schur_apply_noalloc", "dd_bdd_solve", "dd_method_autotune",
+            "dd_method_solve"]
+DD_METHOD_AUTO, DD_METHOD_FETI, DD_METHOD_BDD, DD_METHOD_JACOBI = range(4)
 DD_SLOT_FREE, DD_SLOT_RUNNING, DD_SLOT_DONE, DD_SLOT_FALLBACK = range(4)
 DD_PHASE_KIG, DD_PHASE_INTERIOR, DD_PHASE_GAMMA, DD_PHASE_UPDATE, DD_PHASE_LOOP = range(5)
 DD_NPHASES = 5
@@ -132,11 +134,17 @@ def load_library(path: str = LIB_PATH):
     lib.dd_feti_factor.argtypes = [vp]
     lib.dd_feti_solve.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                   ctypes.POINTER(dd_solve_info)]
+    lib.dd_bdd_solve.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.POINTER(dd_solve_info)]
+    lib.dd_method_solve.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.POINTER(dd_solve_info)]
+    lib.dd_method_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _i32p, _f64p]
     lib.dd_feti_last_error.argtypes = [vp]
     lib.dd_feti_last_error.restype = ctypes.c_char_p
     lib.dd_feti_destroy.argtypes = [vp]
     lib.dd_feti_destroy.restype = None
-    for name in ("dd_feti_setup", "dd_feti_factor", "dd_feti_solve"):
+    for name in ("dd_feti_setup", "dd_feti_factor", "dd_feti_solve", "dd_bdd_solve", "dd_method_solve",
+                 "dd_method_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("dd_footprint", "dd_setup", "dd_factor", "dd_solve", "dd_schur_apply",
                  "dd_schur_apply_noalloc", "dd_get_factor", "dd_get_schur_diag", "dd_set_timing", "dd_get_timing",
@@ -487,6 +495,37 @@ def dd_feti_solve(ctx, b, u, nrhs: int, ld: int, tol: float, max_it: int, raise_
     return st, [dict(iters=i.iters, converged=i.converged, rel_resid=i.rel_resid) for i in info]
 
 
+def dd_bdd_solve(ctx, b, u, nrhs: int, ld: int, tol: float, max_it: int, raise_on_noconv: bool = True):
+    lib = load_library()
+    info = (dd_solve_info * nrhs)()
+    st = lib.dd_bdd_solve(ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()), nrhs, ld, tol,
+                          max_it, info)
+    if st != DD_OK and not (st == DD_ENOCONV and not raise_on_noconv):
+        _feti_check(lib, st, ctx)
+    return st, [dict(iters=i.iters, converged=i.converged, rel_resid=i.rel_resid) for i in info]
+
+
+def dd_method_solve(ctx, method: int, b, u, nrhs: int, ld: int, tol: float, max_it: int,
+                    raise_on_noconv: bool = True):
+    lib = load_library()
+    info = (dd_solve_info * nrhs)()
+    st = lib.dd_method_solve(ctx, method, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(u.data_ptr()), nrhs,
+                             ld, tol, max_it, info)
+    if st != DD_OK and not (st == DD_ENOCONV and not raise_on_noconv):
+        _feti_check(lib, st, ctx)
+    return st, [dict(iters=i.iters, converged=i.converged, rel_resid=i.rel_resid) for i in info]
+
+
+def dd_method_autotune(ctx, nrhs: int, tol: float, max_it: int = 1000) -> dict:
+    """Time FETI, BDD and Jacobi on a seeded batch; the fastest serves DD_METHOD_AUTO."""
+    lib = load_library()
+    m = ctypes.c_int32(0)
+    ms = (ctypes.c_double * 3)()
+    _feti_check(lib, lib.dd_method_autotune(ctx, nrhs, tol, max_it, ctypes.byref(m),
+                                            ctypes.cast(ms, _f64p)), ctx)
+    return dict(method=int(m.value), ms_feti=ms[0], ms_bdd=ms[1], ms_jacobi=ms[2])
+
+
 def dd_feti_destroy(ctx) -> None:
     if ctx is not None and ctx.value:
         load_library().dd_feti_destroy(ctx)
@@ -515,6 +554,29 @@ class FetiSolver:
         u = torch.empty((nrhs, ld), dtype=torch.float64, device=b.device)
         st, info = dd_feti_solve(self.ctx, b, u, nrhs, ld, tol, max_it, raise_on_noconv)
         return SolveResult(u[:, :self.n_dof], st, info)
+
+    def _out(self, b):
+        torch = self.torch
+        nrhs = int(b.shape[0])
+        ld = int(b.stride(0)) if nrhs > 1 else int(b.shape[1])
+        if b.dtype != torch.float64 or not b.is_cuda or (b.shape[1] > 1 and b.stride(1) != 1):
+            raise ValueError("b must be a CUDA float64 tensor with unit inner stride")
+        return nrhs, ld, torch.empty((nrhs, ld), dtype=torch.float64, device=b.device)
+
+    def solve_bdd(self, b, tol: float = 1e-10, max_it: int = 1000, raise_on_noconv: bool = True) -> SolveResult:
+        """Primal interface CG with the balancing Neumann-Neumann preconditioner."""
+        nrhs, ld, u = self._out(b)
+        st, info = dd_bdd_solve(self.ctx, b, u, nrhs, ld, tol, max_it, raise_on_noconv)
+        return SolveResult(u[:, :self.n_dof], st, info)
+
+    def solve_method(self, b, method: int = DD_METHOD_AUTO, tol: float = 1e-10, max_it: int = 1000,
+                     raise_on_noconv: bool = True) -> SolveResult:
+        nrhs, ld, u = self._out(b)
+        st, info = dd_method_solve(self.ctx, method, b, u, nrhs, ld, tol, max_it, raise_on_noconv)
+        return SolveResult(u[:, :self.n_dof], st, info)
+
+    def autotune(self, nrhs: int, tol: float = 1e-10, max_it: int = 1000) -> dict:
+        return dd_method_autotune(self.ctx, nrhs, tol, max_it)
 
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None:

@@ -140,6 +140,21 @@ __global__ void k_pack_sub(int nsub, const T *__restrict__ blocks, const long lo
   }
 }
 
+// Seeded test right-hand side of the method autotuner: b[c * ld + i] in
+// [-1, 1) from a 64-bit mix of (i, c) (the finaliser of SplitMix64).
+__global__ void k_feti_pattern(int n, int nrhs, int ld, double *__restrict__ b) {
+  const size_t tot = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / n), i = (int)(e % n);
+    unsigned long long z = (unsigned long long)e * 0x9E3779B97F4A7C15ull + 0x1234567ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    b[(size_t)c * ld + i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
 }  // namespace dd
 
 namespace {
@@ -201,6 +216,19 @@ struct dd_feti_ctx {
   double *h_dots = nullptr;                      // pinned
   dd::ColCoef coef{};                            // coefficients of the next axpy / xpay
   bool factored = false;
+  // balancing Neumann-Neumann preconditioner of the primal interface problem:
+  // scaled restriction R_D (U x Gamma, entries 1 / zeta), its transpose, the
+  // coarse space N = R_D^T Z, S N and the inverse of S_0 = N^T S N (formed by
+  // the first BDD solve), interface vectors of the primal PCG
+  DCsr Rd, Rdt, Nm, Nt, SNm, SNt, S0i;
+  std::vector<int> hN_ptr, hN_col;
+  std::vector<double> hN_val;
+  bool bdd_ready = false;
+  double *gx = nullptr, *gr = nullptr, *gz = nullptr, *gp = nullptr, *gq = nullptr, *gt = nullptr,
+         *gu = nullptr, *cz3 = nullptr;
+  // method chosen by dd_method_autotune (0: not tuned) and its timings
+  int method = 0, tuned_nrhs = 0;
+  double tune_ms[3] = {0.0, 0.0, 0.0};
   std::string err;
 };
 
@@ -269,8 +297,54 @@ std::vector<int> choose_pins(const double *z, int n, int nz) {
   return pins;
 }
 
+// Inverse of a symmetric positive definite n x n matrix (row-major) by
+// Cholesky; false if a pivot is not positive.  The result as a dense CSR.
+bool spd_inverse_csr(const std::vector<double> &M, int n, HCsr &out) {
+  std::vector<double> L((size_t)n * n, 0.0), Li((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = M[(size_t)j * n + j];
+    for (int q = 0; q < j; ++q) s -= L[(size_t)j * n + q] * L[(size_t)j * n + q];
+    if (!(s > 0.0)) return false;
+    L[(size_t)j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = M[(size_t)i * n + j];
+      for (int q = 0; q < j; ++q) t -= L[(size_t)i * n + q] * L[(size_t)j * n + q];
+      L[(size_t)i * n + j] = t / L[(size_t)j * n + j];
+    }
+  }
+  for (int col = 0; col < n; ++col) {       // (L L^T)^-1 e_col
+    std::vector<double> v(n, 0.0);
+    v[col] = 1.0;
+    for (int i = 0; i < n; ++i) {
+      double t = v[i];
+      for (int q = 0; q < i; ++q) t -= L[(size_t)i * n + q] * v[q];
+      v[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = v[i];
+      for (int q = i + 1; q < n; ++q) t -= L[(size_t)q * n + i] * v[q];
+      v[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) Li[(size_t)i * n + col] = v[i];
+  }
+  out = HCsr();
+  out.ncols = n;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      out.col.push_back(j);
+      out.val.push_back(Li[(size_t)i * n + j]);
+    }
+    out.row_end();
+  }
+  return true;
+}
+
 // Dot products of the ncols columns of x and y (n rows, ld): into f->h_dots.
 dd_status dots(dd_feti_ctx *f, int n, int ld, const double *x, const double *y) {
+  if (n <= 0) {
+    for (int c = 0; c < ld; ++c) f->h_dots[c] = 0.0;
+    return DD_OK;
+  }
   const unsigned nb = grid_for(std::max(1, n), kRowsE);
   hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(kBlock), 0, f->stream, n, ld, x, y, f->dpart);
   hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kMaxLd), 0, f->stream, (int)nb, ld, f->dpart, f->dout);
@@ -346,6 +420,88 @@ void precond(dd_feti_ctx *f, const double *x, double *out, int ld) {
   csr_apply(f, f->BDt, x, ld, nullptr, 1.0, f->sU);
   sapply(f, f->sU, f->fU, ld);
   csr_apply(f, f->BD, f->fU, ld, nullptr, 1.0, out);
+}
+
+// ---------------------------------------------------- balancing Neumann-Neumann --
+// q = S x on the interface of the primal context (eq. subSchurComplement summed
+// over subdomains): the same three products as one CG iteration of dd_solve.
+void primal_schur(dd_feti_ctx *f, const double *x, double *q, int ld) {
+  dd_ctx *c = f->P;
+  kig_apply(c, DD_FP64, plain(x), ld, nullptr, 1.0, c->w.yI);
+  interior_solve(c, DD_FP64, DD_APPLY_INV, c->w.yI, c->w.wI, ld);
+  gamma_apply(c, DD_FP64, plain(x), c->w.wI, ld, nullptr, 1.0, -1.0, q);
+}
+
+// S N (dense, n_gamma x nc, by columns through the primal Schur product) and
+// the inverse of S_0 = N^T S N, once per context.
+dd_status bdd_prepare(dd_feti_ctx *f) {
+  if (f->bdd_ready) return DD_OK;
+  const int nG = f->n_gamma, nc = f->nc, L = f->ldmax;
+  if (nc > 0) {
+    std::vector<double> Nd((size_t)nG * nc, 0.0), SNd((size_t)nG * nc, 0.0), chunk((size_t)nG * L);
+    for (int g = 0; g < nG; ++g)
+      for (int a = f->hN_ptr[g]; a < f->hN_ptr[g + 1]; ++a) Nd[(size_t)g * nc + f->hN_col[a]] = f->hN_val[a];
+    for (int c0 = 0; c0 < nc; c0 += L) {
+      const int m = std::min(L, nc - c0);
+      for (int g = 0; g < nG; ++g)
+        for (int j = 0; j < L; ++j) chunk[(size_t)g * L + j] = j < m ? Nd[(size_t)g * nc + c0 + j] : 0.0;
+      FHIP(hipMemcpyAsync(f->gt, chunk.data(), chunk.size() * sizeof(double), hipMemcpyHostToDevice, f->stream));
+      primal_schur(f, f->gt, f->gq, L);
+      FHIP(hipMemcpyAsync(chunk.data(), f->gq, chunk.size() * sizeof(double), hipMemcpyDeviceToHost, f->stream));
+      FHIP(hipStreamSynchronize(f->stream));
+      for (int g = 0; g < nG; ++g)
+        for (int j = 0; j < m; ++j) SNd[(size_t)g * nc + c0 + j] = chunk[(size_t)g * L + j];
+    }
+    std::vector<double> S0((size_t)nc * nc, 0.0);
+    for (int g = 0; g < nG; ++g)
+      for (int a = f->hN_ptr[g]; a < f->hN_ptr[g + 1]; ++a) {
+        const int i = f->hN_col[a];
+        const double v = f->hN_val[a];
+        for (int j = 0; j < nc; ++j) S0[(size_t)i * nc + j] += v * SNd[(size_t)g * nc + j];
+      }
+    for (int i = 0; i < nc; ++i)          // symmetric up to rounding: take the mean
+      for (int j = 0; j < i; ++j) S0[(size_t)i * nc + j] = S0[(size_t)j * nc + i] =
+          0.5 * (S0[(size_t)i * nc + j] + S0[(size_t)j * nc + i]);
+    HCsr S0i, SN, SNt;
+    if (!spd_inverse_csr(S0, nc, S0i)) return ffail(f, DD_ENOTSPD, "coarse matrix N^T S N not positive definite");
+    SN.ncols = nc;
+    for (int g = 0; g < nG; ++g) {
+      for (int j = 0; j < nc; ++j) {
+        SN.col.push_back(j);
+        SN.val.push_back(SNd[(size_t)g * nc + j]);
+      }
+      SN.row_end();
+    }
+    SNt = SN.transpose();
+    dd_status st;
+    if ((st = up_csr(f, S0i, f->S0i)) != DD_OK || (st = up_csr(f, SN, f->SNm)) != DD_OK ||
+        (st = up_csr(f, SNt, f->SNt)) != DD_OK)
+      return ffail(f, st, "uploading the coarse space: " + f->D->err);
+  }
+  f->bdd_ready = true;
+  return DD_OK;
+}
+
+// z = M^-1 r = P_0 r + (I - P_0 S) M_NN (I - S P_0) r with P_0 = N S_0^-1 N^T and
+// M_NN = R_D^T S^+ R_D (S^+ blockwise over the copies).
+void bdd_minv(dd_feti_ctx *f, const double *r, double *z, int ld) {
+  const double *t = r;
+  if (f->nc > 0) {            // c2 = S_0^-1 N^T r;  t = r - S N c2 (balanced)
+    csr_apply(f, f->Nt, r, ld, nullptr, 1.0, f->cz);
+    csr_apply(f, f->S0i, f->cz, ld, nullptr, 1.0, f->cz2);
+    csr_apply(f, f->SNm, f->cz2, ld, r, -1.0, f->gt);
+    t = f->gt;
+  }
+  csr_apply(f, f->Rd, t, ld, nullptr, 1.0, f->sU);
+  spinv(f, f->sU, f->fU, ld);
+  if (f->nc > 0) {            // z = u + N (c2 - S_0^-1 (S N)^T u)
+    csr_apply(f, f->Rdt, f->fU, ld, nullptr, 1.0, f->gu);
+    csr_apply(f, f->SNt, f->gu, ld, nullptr, 1.0, f->cz3);
+    csr_apply(f, f->S0i, f->cz3, ld, f->cz2, -1.0, f->cz);
+    csr_apply(f, f->Nm, f->cz, ld, f->gu, 1.0, z);
+  } else {
+    csr_apply(f, f->Rdt, f->fU, ld, nullptr, 1.0, z);
+  }
 }
 
 }  // namespace
@@ -556,41 +712,11 @@ dd_status dd_feti_setup(const dd_problem *prob, const dd_feti_sub *fs, void *hip
   GtGi.ncols = nc;
   if (nc > 0) {
     // G^T G (dense, nc x nc) and its inverse by Cholesky (the coarse problem)
-    std::vector<double> M((size_t)nc * nc, 0.0), Li((size_t)nc * nc, 0.0);
+    std::vector<double> M((size_t)nc * nc, 0.0);
     for (int r = 0; r < G.nrows; ++r)
       for (int a = G.ptr[r]; a < G.ptr[r + 1]; ++a)
         for (int b2 = G.ptr[r]; b2 < G.ptr[r + 1]; ++b2) M[(size_t)G.col[a] * nc + G.col[b2]] += G.val[a] * G.val[b2];
-    std::vector<double> L((size_t)nc * nc, 0.0);
-    for (int j = 0; j < nc; ++j) {
-      double s = M[(size_t)j * nc + j];
-      for (int q2 = 0; q2 < j; ++q2) s -= L[(size_t)j * nc + q2] * L[(size_t)j * nc + q2];
-      if (!(s > 0.0)) { f->err = "G^T G not positive definite"; return bail(DD_ENOTSPD); }
-      L[(size_t)j * nc + j] = std::sqrt(s);
-      for (int i = j + 1; i < nc; ++i) {
-        double t = M[(size_t)i * nc + j];
-        for (int q2 = 0; q2 < j; ++q2) t -= L[(size_t)i * nc + q2] * L[(size_t)j * nc + q2];
-        L[(size_t)i * nc + j] = t / L[(size_t)j * nc + j];
-      }
-    }
-    for (int col = 0; col < nc; ++col) {       // (L L^T)^-1 e_col
-      std::vector<double> v(nc, 0.0);
-      v[col] = 1.0;
-      for (int i = 0; i < nc; ++i) {
-        double t = v[i];
-        for (int q2 = 0; q2 < i; ++q2) t -= L[(size_t)i * nc + q2] * v[q2];
-        v[i] = t / L[(size_t)i * nc + i];
-      }
-      for (int i = nc - 1; i >= 0; --i) {
-        double t = v[i];
-        for (int q2 = i + 1; q2 < nc; ++q2) t -= L[(size_t)q2 * nc + i] * v[q2];
-        v[i] = t / L[(size_t)i * nc + i];
-      }
-      for (int i = 0; i < nc; ++i) Li[(size_t)i * nc + col] = v[i];
-    }
-    for (int i = 0; i < nc; ++i) {
-      for (int j = 0; j < nc; ++j) { GtGi.col.push_back(j); GtGi.val.push_back(Li[(size_t)i * nc + j]); }
-      GtGi.row_end();
-    }
+    if (!spd_inverse_csr(M, nc, GtGi)) { f->err = "G^T G not positive definite"; return bail(DD_ENOTSPD); }
   }
   f->err.clear();
   if ((st = up_csr(f, B, f->B)) != DD_OK) return bail(st);
@@ -604,6 +730,36 @@ dd_status dd_feti_setup(const dd_problem *prob, const dd_feti_sub *fs, void *hip
   if ((st = up_csr(f, Q.transpose(), f->Qt)) != DD_OK) return bail(st);
   if ((st = up_csr(f, Z, f->Zm)) != DD_OK) return bail(st);
   if ((st = up_csr(f, Z.transpose(), f->Zt)) != DD_OK) return bail(st);
+  {
+    // balancing Neumann-Neumann: R_D (row u: the interface dof of copy u,
+    // weight 1 / zeta), R_D^T (per dof its copies in subdomain order) and the
+    // coarse space N = R_D^T Z (column (k, m): z_k[:, m] / zeta on Gamma_k)
+    HCsr Rd;
+    Rd.ncols = nG;
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < fs[k].n_g; ++j) {
+        const int gi = fs[k].g_map[j];
+        Rd.col.push_back(gi);
+        Rd.val.push_back(1.0 / (double)copies[gi].size());
+        Rd.row_end();
+      }
+    HCsr Rdt = Rd.transpose(), N;
+    N.ncols = nc;
+    for (int g = 0; g < nG; ++g) {
+      for (int a = Rdt.ptr[g]; a < Rdt.ptr[g + 1]; ++a)
+        for (int b2 = Z.ptr[Rdt.col[a]]; b2 < Z.ptr[Rdt.col[a] + 1]; ++b2) {
+          N.col.push_back(Z.col[b2]);
+          N.val.push_back(Rdt.val[a] * Z.val[b2]);
+        }
+      N.row_end();
+    }
+    if ((st = up_csr(f, Rd, f->Rd)) != DD_OK || (st = up_csr(f, Rdt, f->Rdt)) != DD_OK ||
+        (st = up_csr(f, N, f->Nm)) != DD_OK || (st = up_csr(f, N.transpose(), f->Nt)) != DD_OK)
+      return bail(st);
+    f->hN_ptr = N.ptr;
+    f->hN_col = N.col;
+    f->hN_val = N.val;
+  }
   // --- the Neumann context: pinned subdomain matrices, factored and inverted ----------
   {
     std::vector<std::vector<double>> blocks(K);
@@ -739,9 +895,13 @@ dd_status dd_feti_setup(const dd_problem *prob, const dd_feti_sub *fs, void *hip
   double **uv[] = {&f->tU, &f->sU, &f->fU};
   for (double **v : uv)
     if ((st = dalloc(c, v, (size_t)NU * L)) != DD_OK) return bail(st);
+  double **gv[] = {&f->gx, &f->gr, &f->gz, &f->gp, &f->gq, &f->gt, &f->gu};
+  for (double **v : gv)
+    if ((st = dalloc(c, v, (size_t)std::max(1, nG) * L)) != DD_OK) return bail(st);
+  if ((st = dalloc(c, &f->cz3, (size_t)std::max(1, f->nc) * L)) != DD_OK) return bail(st);
   if ((st = dalloc(c, &f->cz, (size_t)std::max(1, nc) * L)) != DD_OK ||
       (st = dalloc(c, &f->cz2, (size_t)std::max(1, nc) * L)) != DD_OK ||
-      (st = dalloc(c, &f->dpart, (size_t)(grid_for(std::max(f->nlam, NU), kRowsE) + 1) * kMaxLd)) != DD_OK ||
+      (st = dalloc(c, &f->dpart, (size_t)(grid_for(std::max(std::max(f->nlam, NU), NI), kRowsE) + 1) * kMaxLd)) != DD_OK ||
       (st = dalloc(c, &f->dout, kMaxLd)) != DD_OK)
     return bail(st);
   if (hipHostMalloc((void **)&f->h_dots, kMaxLd * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -887,6 +1047,193 @@ dd_status dd_feti_solve(dd_feti_ctx *f, const double *b_dev, double *u_dev, int3
   }
   if (result == DD_ENOCONV) f->err = "tolerance not reached for at least one column";
   return result;
+}
+
+dd_status dd_bdd_solve(dd_feti_ctx *f, const double *b_dev, double *u_dev, int32_t nrhs, int32_t ld, double tol,
+                       int32_t max_it, dd_solve_info *info) {
+  if (!f) return ffail(nullptr, DD_EINVAL, "ctx is NULL");
+  f->err.clear();
+  if (!f->factored) return ffail(f, DD_ESTATE, "dd_feti_factor has not run");
+  if (nrhs < 1 || nrhs > f->max_nrhs) return ffail(f, DD_EINVAL, "nrhs out of [1, max_nrhs]");
+  if (ld < f->n_dof || !b_dev || !u_dev || b_dev == u_dev) return ffail(f, DD_EINVAL, "bad b/u or ld < n_dof");
+  if (!(tol > 0.0) || max_it < 1) return ffail(f, DD_EINVAL, "tol <= 0 or max_it < 1");
+  FTRY(bdd_prepare(f));
+  dd_ctx *c = f->P;
+  Work &w = c->w;
+  const int L = next_pow2(nrhs), nG = f->n_gamma;
+  const size_t ng = (size_t)nG;
+  // b in the primal DD layout; reduced forcing g = b_G - K_GI K_II^-1 b_I (eq. subForcing)
+  const int n_all = c->NI + nG;
+  hipLaunchKernelGGL(k_gather2, dim3(std::min(4096u, grid_for((size_t)n_all * L, 256))), dim3(256), 0, f->stream,
+                     c->NI, nG, c->d_imap, c->d_gmap, b_dev, ld, nrhs, L, w.bI, w.bG);
+  interior_solve(c, DD_FP64, DD_APPLY_INV, w.bI, w.wI, L);
+  gamma_apply(c, DD_FP64, plain(nullptr), w.wI, L, w.bG, 0.0, -1.0, f->gr);      // r = g (x = 0)
+  FHIP(hipMemsetAsync(f->gx, 0, ng * L * sizeof(double), f->stream));
+  // stop column c when ||r_c|| <= tol ||b_c|| (the stopping rule of dd_solve)
+  std::vector<double> stop2(L, 0.0), rz(L, 0.0), a(L, 0.0);
+  FTRY(dots(f, c->NI, L, w.bI, w.bI));
+  for (int col = 0; col < L; ++col) stop2[col] = f->h_dots[col];
+  FTRY(dots(f, nG, L, w.bG, w.bG));
+  for (int col = 0; col < L; ++col) stop2[col] = tol * tol * (stop2[col] + f->h_dots[col]);
+  FTRY(dots(f, nG, L, f->gr, f->gr));
+  std::vector<int> active(L, 0), its(L, 0);
+  bool any = false;
+  for (int col = 0; col < L; ++col) {
+    active[col] = col < nrhs && f->h_dots[col] > stop2[col];
+    any |= active[col] != 0;
+  }
+  if (any) {
+    bdd_minv(f, f->gr, f->gz, L);
+    FHIP(hipMemcpyAsync(f->gp, f->gz, ng * L * sizeof(double), hipMemcpyDeviceToDevice, f->stream));
+    FTRY(dots(f, nG, L, f->gr, f->gz));
+    for (int col = 0; col < L; ++col) rz[col] = f->h_dots[col];
+  }
+  int it = 0;
+  while (any && it < max_it) {
+    primal_schur(f, f->gp, f->gq, L);                       // q = S p
+    FTRY(dots(f, nG, L, f->gp, f->gq));
+    for (int col = 0; col < L; ++col) {
+      const double pq = f->h_dots[col];
+      if (active[col] && !(pq > 0.0)) return ffail(f, DD_ENOTSPD, "BDD breakdown: p^T S p <= 0");
+      a[col] = active[col] ? rz[col] / pq : 0.0;
+    }
+    set_coef(f, a, L);
+    axpy(f, ng, L, f->gp, f->gx);                           // x += alpha p
+    for (int col = 0; col < L; ++col) a[col] = -a[col];
+    set_coef(f, a, L);
+    axpy(f, ng, L, f->gq, f->gr);                           // r -= alpha q
+    FTRY(dots(f, nG, L, f->gr, f->gr));
+    ++it;
+    any = false;
+    for (int col = 0; col < L; ++col)
+      if (active[col]) {
+        its[col] = it;
+        if (f->h_dots[col] <= stop2[col]) active[col] = 0;
+        any |= active[col] != 0;
+      }
+    if (!any) break;
+    bdd_minv(f, f->gr, f->gz, L);                           // z = M^-1 r
+    FTRY(dots(f, nG, L, f->gr, f->gz));
+    for (int col = 0; col < L; ++col) {
+      a[col] = active[col] ? f->h_dots[col] / rz[col] : 0.0;
+      if (active[col]) rz[col] = f->h_dots[col];
+    }
+    set_coef(f, a, L);
+    xpay(f, ng, L, f->gz, f->gp);                           // p = z + beta p
+  }
+  // interiors by eq. backwardSubstitution, then the solution in the caller's layout
+  kig_apply(c, DD_FP64, plain(f->gx), L, w.bI, -1.0, w.yI);
+  interior_solve(c, DD_FP64, DD_APPLY_INV, w.yI, w.uI, L);
+  hipLaunchKernelGGL(k_scatter2, dim3(std::min(4096u, grid_for((size_t)n_all * nrhs, 256))), dim3(256), 0,
+                     f->stream, c->NI, nG, c->d_imap, c->d_gmap, w.uI, f->gx, L, nrhs, u_dev, ld);
+  FHIP(hipGetLastError());
+  FHIP(hipStreamSynchronize(f->stream));
+  dd_status result = DD_OK;
+  for (int col = 0; col < nrhs; ++col)
+    if (active[col]) result = DD_ENOCONV;
+  if (info) {
+    std::vector<double> rel(nrhs);
+    dd_status rs = residual_cols(c, b_dev, u_dev, nrhs, ld, rel.data());
+    if (rs != DD_OK) return ffail(f, rs, "residual: " + c->err);
+    for (int col = 0; col < nrhs; ++col) {
+      info[col].iters = its[col];
+      info[col].refine_steps = 0;
+      info[col].used_fallback = 0;
+      info[col].converged = !active[col];
+      info[col].rel_resid = rel[col];
+    }
+  }
+  if (result == DD_ENOCONV) f->err = "tolerance not reached for at least one column";
+  return result;
+}
+
+dd_status dd_method_solve(dd_feti_ctx *f, int32_t method, const double *b_dev, double *u_dev, int32_t nrhs,
+                          int32_t ld, double tol, int32_t max_it, dd_solve_info *info);
+
+dd_status dd_method_autotune(dd_feti_ctx *f, int32_t nrhs, double tol, int32_t max_it, int32_t *method,
+                             double *ms) {
+  if (!f) return ffail(nullptr, DD_EINVAL, "ctx is NULL");
+  f->err.clear();
+  if (!f->factored) return ffail(f, DD_ESTATE, "dd_feti_factor has not run");
+  if (nrhs < 1 || nrhs > f->max_nrhs) return ffail(f, DD_EINVAL, "nrhs out of [1, max_nrhs]");
+  if (!(tol > 0.0) || max_it < 1) return ffail(f, DD_EINVAL, "tol <= 0 or max_it < 1");
+  // the primal context's own schedule for the Jacobi-preconditioned method
+  {
+    dd_solve_opts o;
+    dd_default_opts(&o);
+    o.tol = tol;
+    o.max_it = max_it;
+    dd_tune_result tr;
+    dd_status st = dd_autotune(f->P, DD_FP64, nrhs, &o, &tr);
+    if (st != DD_OK) return ffail(f, st, "primal schedule: " + f->P->err);
+  }
+  double *b = nullptr, *u = nullptr;
+  const size_t n = (size_t)f->n_dof * nrhs;
+  if (hipMalloc(&b, n * sizeof(double)) != hipSuccess) return ffail(f, DD_ENOMEM, "autotune right-hand side");
+  if (hipMalloc(&u, n * sizeof(double)) != hipSuccess) {
+    (void)hipFree(b);
+    return ffail(f, DD_ENOMEM, "autotune solution");
+  }
+  hipLaunchKernelGGL(k_feti_pattern, dim3(std::min(4096u, grid_for(n, 256))), dim3(256), 0, f->stream, f->n_dof,
+                     nrhs, f->n_dof, b);
+  double best = 1e300;
+  int choice = DD_METHOD_FETI;
+  double t3[3] = {0.0, 0.0, 0.0};
+  dd_status result = DD_OK;
+  for (int m = DD_METHOD_FETI; m <= DD_METHOD_JACOBI && result == DD_OK; ++m) {
+    double tm = 1e300;
+    for (int rep = 0; rep < 3; ++rep) {        // the first run is a warm-up
+      if (hipStreamSynchronize(f->stream) != hipSuccess) { result = ffail(f, DD_EHIP, "autotune sync"); break; }
+      const auto t0 = std::chrono::steady_clock::now();
+      dd_status st = dd_method_solve(f, m, b, u, nrhs, f->n_dof, tol, max_it, nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (st == DD_ENOCONV) { tm = 1e300; break; }        // a method that misses the tolerance loses
+      if (st != DD_OK) { result = st; break; }
+      if (rep > 0) tm = std::min(tm, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    t3[m - 1] = tm;
+    if (tm < best) { best = tm; choice = m; }
+  }
+  (void)hipFree(b);
+  (void)hipFree(u);
+  if (result != DD_OK) return result;
+  f->err.clear();
+  f->method = choice;
+  f->tuned_nrhs = nrhs;
+  for (int i = 0; i < 3; ++i) f->tune_ms[i] = t3[i];
+  if (method) *method = choice;
+  if (ms)
+    for (int i = 0; i < 3; ++i) ms[i] = t3[i];
+  return DD_OK;
+}
+
+dd_status dd_method_solve(dd_feti_ctx *f, int32_t method, const double *b_dev, double *u_dev, int32_t nrhs,
+                          int32_t ld, double tol, int32_t max_it, dd_solve_info *info) {
+  if (!f) return ffail(nullptr, DD_EINVAL, "ctx is NULL");
+  if (method == DD_METHOD_AUTO) {
+    if (!f->method) {
+      dd_status st = dd_method_autotune(f, nrhs, tol, max_it, nullptr, nullptr);
+      if (st != DD_OK) return st;
+    }
+    method = f->method;
+  }
+  switch (method) {
+    case DD_METHOD_FETI: return dd_feti_solve(f, b_dev, u_dev, nrhs, ld, tol, max_it, info);
+    case DD_METHOD_BDD: return dd_bdd_solve(f, b_dev, u_dev, nrhs, ld, tol, max_it, info);
+    case DD_METHOD_JACOBI: {
+      f->err.clear();
+      if (!f->factored) return ffail(f, DD_ESTATE, "dd_feti_factor has not run");
+      dd_solve_opts o;
+      dd_default_opts(&o);
+      o.tol = tol;
+      o.max_it = max_it;
+      std::vector<dd_solve_info> tmp(std::max(1, (int)nrhs));
+      dd_status st = dd_solve(f->P, DD_FP64, b_dev, u_dev, nrhs, ld, &o, info ? info : tmp.data());
+      if (st != DD_OK) f->err = f->P->err;
+      return st;
+    }
+    default: return ffail(f, DD_EINVAL, "unknown method");
+  }
 }
 
 const char *dd_feti_last_error(const dd_feti_ctx *f) { return f ? f->err.c_str() : g_setup_error.c_str(); }
