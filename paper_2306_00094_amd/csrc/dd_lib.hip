@@ -679,11 +679,13 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   const int n2 = interface_rows ? c->NI : 0;
   if (DOT) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums of p^T q
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // two tiles in flight per wave: three or four measured slower on the
+  // peridynamic 32-column batch (148, 155, 166 us per interface launch)
   if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
-    hipExtLaunchKernelGGL((k_tile_rows<VT, NCB, DOT>), g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr,
+    hipExtLaunchKernelGGL((k_tile_rows<VT, NCB, DOT, 2>), g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr,
                           split, col, val, x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
   else
-    hipLaunchKernelGGL((k_tile_rows<VT, NCB, DOT>), g, b, 0, c->stream, nrb, nrows, ptr, split, col, val,
+    hipLaunchKernelGGL((k_tile_rows<VT, NCB, DOT, 2>), g, b, 0, c->stream, nrb, nrows, ptr, split, col, val,
                        x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
 }
 

@@ -78,14 +78,13 @@ __device__ __forceinline__ void tile_mma(const double (&a)[4], const double (&xv
 
 // acc[q] += T * X over the tiles t0, t0 + st, t0 + 2 st, ... (< t1) of one row
 // block, in that order (t0, t1, st uniform over the wave).  The tiles' column
-// blocks are fetched 64 at a time, one per lane, and broadcast by readlane; two
-// register buffers hold the operands of the next two tiles while a tile's
+// blocks are fetched 64 at a time, one per lane, and broadcast by readlane; D
+// register buffers hold the operands of the next D tiles while a tile's
 // instructions run (the last loads of a wave repeat its last tile and are not
-// used).  Scheduling barriers keep every group of loads in program order --
-// buffer 0 before buffer 1 in the prologue as in the loop -- so that the
-// instructions of one buffer wait only for that buffer's loads, the other
-// buffer's staying in flight.
-template <typename VT, int NCB>
+// used).  Scheduling barriers keep every group of loads in program order, so
+// that the instructions of one buffer wait only for that buffer's loads, the
+// other buffers' staying in flight.
+template <typename VT, int NCB, int D>
 __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *__restrict__ tcol,
                                              const VT *__restrict__ tval, const double *__restrict__ x,
                                              int n, int ld, dbl4 (&acc)[NCB]) {
@@ -96,33 +95,24 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
     const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
     const VT *tv = tval + (size_t)(t0 + base * st) * 256 + 4 * lane;
     const size_t tstride = (size_t)st * 256;
-    double a0[4], x0[4][NCB], a1[4], x1[4][NCB];
-    TileA<VT>::load(tv, a0);
-    load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, 0), x0);
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      const int j1 = min(1, nb - 1);
-      TileA<VT>::load(tv + j1 * tstride, a1);
-      load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, j1), x1);
+    double a[D][4], xs[D][4][NCB];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int jd = min(d, nb - 1);
+      TileA<VT>::load(tv + jd * tstride, a[d]);
+      load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jd), xs[d]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    for (int j = 0; j < nb; j += 2) {
-      tile_mma<NCB>(a0, x0, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      {
-        const int jn = min(j + 2, nb - 1);
-        TileA<VT>::load(tv + jn * tstride, a0);
-        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x0);
+    for (int j = 0; j < nb; j += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        if (j + d < nb) tile_mma<NCB>(a[d], xs[d], acc);
+        __builtin_amdgcn_sched_barrier(0);
+        const int jn = min(j + d + D, nb - 1);
+        TileA<VT>::load(tv + jn * tstride, a[d]);
+        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), xs[d]);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __builtin_amdgcn_sched_barrier(0);
-      if (j + 1 < nb) tile_mma<NCB>(a1, x1, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      {
-        const int jn = min(j + 3, nb - 1);
-        TileA<VT>::load(tv + jn * tstride, a1);
-        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), x1);
-      }
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -157,7 +147,7 @@ constexpr int kTW = 4;
 // per column to red.part2, and the last of every kPGroup consecutive
 // workgroups the group sum to red.part3, which the update kernel reduces (the
 // step length of the CG iteration, from p^T S p).
-template <typename VT, int NCB, bool DOT>
+template <typename VT, int NCB, bool DOT, int D = 2>
 __global__ void __launch_bounds__(kTW * kWave)
 k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
             const int *__restrict__ tcol, const VT *__restrict__ tval, const double *__restrict__ x1,
@@ -171,9 +161,9 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc1[q][r] = acc2[q][r] = 0.0;
   const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
-  if (c1 != 0.0) tile_row_acc<VT, NCB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, acc1);
-  if (split && c2 != 0.0) tile_row_acc<VT, NCB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, acc2);
-  __shared__ double part[kTW * kT * kMaxLd];
+  if (c1 != 0.0) tile_row_acc<VT, NCB, D>(b + wv, s, kTW, tcol, tval, x1, n1, ld, acc1);
+  if (split && c2 != 0.0) tile_row_acc<VT, NCB, D>(s + wv, e, kTW, tcol, tval, x2, n2, ld, acc2);
+  __shared__ double part[kTW * kT * kT * NCB];   // ld <= 16 NCB
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
     const int col = q * kT + l16;
@@ -320,7 +310,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  __shared__ double part[kTW * kT * kMaxLd];
+  __shared__ double part[kTW * kT * kT * NCB];   // ld <= 16 NCB
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
     const int c = q * kT + l16;
