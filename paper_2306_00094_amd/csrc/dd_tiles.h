@@ -48,23 +48,43 @@ template <> struct TileA<float> {
   }
 };
 
+// Columns of the vector slices: with NCB column blocks of 16 (ld = 16 NCB for
+// NCB >= 2) lane l holds the NCB consecutive columns NCB (l % 16) + q, q < NCB,
+// of each row it reads, so that one 16- or 32-byte load brings all of them
+// (the q-th matrix instruction then computes the columns NCB j + q, j < 16).
+// For NCB = 1 lane l holds column l % 16; at ld = 8 the lanes of columns
+// 8..15 read columns 0..7 again (their products land in output columns that
+// are not stored).
+template <int NCB>
+__device__ __forceinline__ int slice_col0(int l16, int ld) {
+  return NCB == 1 ? (l16 & (ld - 1)) : NCB * l16;
+}
+template <int NCB>
+__device__ __forceinline__ void slice_row(const double *__restrict__ p, double (&v)[NCB]) {
+  if constexpr (NCB == 1) {
+    v[0] = p[0];
+  } else {
+    typedef double vt __attribute__((ext_vector_type(NCB)));
+    const vt w = *(const vt *)p;
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) v[q] = w[q];
+  }
+}
+
 // One 16-row slice of x (rows cb*16 .. cb*16+15, DD layout with leading
-// dimension ld) in the B-operand order: lane l takes row cb*16 + 4 s + l/16 and
-// column q*16 + l%16 for step s and column block q.  Rows past the last row
-// n - 1 read row n - 1 (the tile entries they meet are zero); for ld = 8 the
-// lanes of columns 8..15 read columns 0..7 again (their products land in
-// output columns that are not stored).  The loads are unconditional, so the
+// dimension ld) in the B-operand order: lane l takes row cb*16 + 4 s + l/16 for
+// step s, its columns as above.  Rows past the last row n - 1 read row n - 1
+// (the tile entries they meet are zero).  The loads are unconditional, so the
 // compiler can count them when it waits for a buffer.
 template <int NCB>
 __device__ __forceinline__ void load_slice(const double *__restrict__ x, int n, int ld, int cb,
                                            double (&xv)[4][NCB]) {
   const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
-  const double *p = x + (l16 & (ld - 1));
+  const double *p = x + slice_col0<NCB>(l16, ld);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int row = min(cb * kT + 4 * s + g, n - 1);
-#pragma unroll
-    for (int q = 0; q < NCB; ++q) xv[s][q] = p[(size_t)row * ld + q * kT];
+    slice_row<NCB>(p + (size_t)row * ld, xv[s]);
   }
 }
 
@@ -166,7 +186,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
   __shared__ double part[kTW * kT * kT * NCB];   // ld <= 16 NCB
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
-    const int col = q * kT + l16;
+    const int col = NCB * l16 + q;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int lr = g + 4 * r;                  // row of the tile held in register r
@@ -269,7 +289,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
   const MT *A = packed + toff[k] + (size_t)item.y * nt * 256 + 4 * lane;
   // y rows past the block (the next subdomain's, or the last row repeated at
   // the end of y) meet the zero padding of the packed tiles
-  const double *yb = y + (l16 & (ld - 1));
+  const double *yb = y + slice_col0<NCB>(l16, ld);
   typedef typename DenseAcc<MT>::acc_t acc_t;
   acc_t acc[NCB];
 #pragma unroll
@@ -279,10 +299,12 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
   auto load = [&](int J, MT (&a)[4], MT (&b)[4][NCB]) {
     TileAT<MT>::load(A + (size_t)J * 256, a);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+      double v[NCB];
+      slice_row<NCB>(yb + (size_t)min(i0 + J * kT + 4 * s + g, nall - 1) * ld, v);
 #pragma unroll
-      for (int q = 0; q < NCB; ++q)
-        b[s][q] = (MT)yb[(size_t)min(i0 + J * kT + 4 * s + g, nall - 1) * ld + q * kT];
+      for (int q = 0; q < NCB; ++q) b[s][q] = (MT)v[q];
+    }
   };
   auto mma = [&](const MT (&a)[4], const MT (&b)[4][NCB]) {
 #pragma unroll
@@ -313,7 +335,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
   __shared__ double part[kTW * kT * kT * NCB];   // ld <= 16 NCB
 #pragma unroll
   for (int q = 0; q < NCB; ++q) {
-    const int c = q * kT + l16;
+    const int c = NCB * l16 + q;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (c < ld) part[(wv * kT + DenseAcc<MT>::row(g, r)) * ld + c] = (double)acc[q][r];
