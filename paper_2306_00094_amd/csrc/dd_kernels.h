@@ -72,6 +72,11 @@ struct ColState {
   double *rz2;      // 2 x kMaxLd
   int *act2;        // 2 x kMaxLd
   int *bd;          // kMaxLd
+  // split update of the tiled iteration: the state a step started from and
+  // its breakdown marks (written by the update, read by the direction launch)
+  double *rz_prev;  // kMaxLd
+  int *act_prev;    // kMaxLd
+  int *brk;         // kMaxLd
 };
 
 // Partial-sum buffers and completion counters of the reductions.
@@ -830,13 +835,17 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 // and, when host_nact is given, publishes (number of active columns + 1) to
 // host memory (a plain system-coherent store: the host reads only that value).
 // E = elements per thread (cpw * kRowsE * ld / kBlock, at least 1).
-// GROUPED (wide batches of the tiled path, one chunk per workgroup): the
-// chunk partials of r.z and r.r are first summed per group of kPGroup
-// workgroups by the group's last workgroup (into red.part2: r.z group sums,
-// then r.r group sums), and the last group finishes the column state from the
-// group sums -- the load of the final sum spread over the groups instead of one
-// workgroup reducing every chunk of every column.
-template <int E, bool GROUPED = false>
+// RED = 1 (grouped; one chunk per workgroup): the chunk partials of r.z and
+// r.r are first summed per group of kPGroup workgroups by the group's last
+// workgroup (into red.part2: r.z group sums, then r.r group sums), and the last
+// group finishes the column state from the group sums -- the load of the final
+// sum spread over the groups instead of one workgroup reducing every chunk of
+// every column.
+// RED = 2 (split; mode 1 only): as RED = 1, but the launch ends with the group
+// sums; k_cg_direction_state reduces them and finishes the column state.
+// Workgroup 0 records the state this step started from (r.z, active) and its
+// step length and breakdown marks for it.
+template <int E, int RED = 0>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ dinv,
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
@@ -896,6 +905,12 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         }
         salpha[c] = a;
         sact[c] = act;
+        if (RED == 2 && blockIdx.x == 0) {
+          st.rz_prev[c] = st.rz[c];
+          st.act_prev[c] = st.active[c];
+          st.brk[c] = st.active[c] && !act;
+          st.alpha[c] = a;
+        }
       }
     }
     __syncthreads();
@@ -959,7 +974,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
   __builtin_amdgcn_s_waitcnt(0x0F70);   // both partial stores complete before the count
   const double *fin0 = red.part0, *fin1 = red.part1;
   int nfin = nchunks;
-  if constexpr (GROUPED) {
+  if constexpr (RED >= 1) {
     const int ngrp = ((int)gridDim.x + kPGroup - 1) / kPGroup;
     const int grp = blockIdx.x / kPGroup;
     const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
@@ -970,6 +985,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     group_sums_store(red.part1, nchunks, ld, grp, gs1, wv, kWavesPerBlock);
     __syncthreads();
     if (threadIdx.x == 0) reset_counter(cnt);
+    if constexpr (RED == 2) return;
     if (!last_of(&red.counter[1], (unsigned)ngrp, &lflag)) return;
     fin0 = gs0;
     fin1 = gs1;
@@ -1607,6 +1623,73 @@ k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restri
       const double pn = fma(st.beta[c], p[e], z[e]);
       p[e] = pn;
       if (p32) p32[e] = (float)pn;      // copy gathered by the FP32-data products
+    }
+  }
+}
+
+// End of a CG step after the split update (k_cg_update<E, 2>): every workgroup
+// reduces the ngrp group sums of r.z and r.r per column in the same fixed
+// order, decides the column's state from them and from the state the step
+// started from (rz_prev, act_prev, brk, recorded by the update's workgroup 0;
+// the state itself is written here by workgroup 0 and read by no other
+// workgroup of this launch), and forms p = z + beta p for the columns still
+// iterating.  Workgroup 0 also writes the column state (as the last workgroup
+// of the grouped update does) and publishes (active columns + 1) to host_nact.
+__global__ void __launch_bounds__(kBlock)
+k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
+                     ColState st, int ngrp, int *__restrict__ host_nact, float *__restrict__ p32 = nullptr) {
+  __shared__ double sbeta[kMaxLd];
+  __shared__ int sact[kMaxLd];
+  const int wv = wave_id(), lane = lane_id();
+  const double *gs0 = red.part2, *gs1 = red.part2 + (size_t)ngrp * ld;
+  // wave w: columns 16 w .. 16 w + 15, one lane each (lanes 16.. idle)
+  {
+    const int c = wv * 16 + lane;
+    if (lane < 16 && c < ld) {
+      double rz = 0.0, rr = 0.0;
+      for (int g = 0; g < ngrp; ++g) {
+        rz += gs0[(size_t)g * ld + c];
+        rr += gs1[(size_t)g * ld + c];
+      }
+      const int act0 = st.act_prev[c], brk = st.brk[c];
+      int act = 0;
+      double beta = 0.0;
+      if (act0 && !brk) {
+        beta = rz / st.rz_prev[c];
+        act = rr > st.stop2[c] ? 1 : 0;
+      }
+      sbeta[c] = beta;
+      sact[c] = act;
+      if (blockIdx.x == 0) {
+        if (act0 && brk) st.flag[0] = 1;          // breakdown: p^T q <= 0
+        if (act0 && !brk) {
+          st.iters[c] += 1;
+          st.beta[c] = beta;
+          st.rz[c] = rz;
+        }
+        st.active[c] = act;
+        st.nrm2[c] = rr;
+      }
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && wv == 0) {
+    int na = lane < ld ? sact[lane] : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
+    if (lane == 0) {
+      if (st.flag[0]) na = 0;            // breakdown ends the loop
+      st.flag[1] = na > 0 ? 1 : 0;
+      if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+  const size_t n = (size_t)nrows * ld;
+  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
+    const int c = (int)(e % ld);
+    if (sact[c]) {
+      const double pn = fma(sbeta[c], p[e], z[e]);
+      p[e] = pn;
+      if (p32) p32[e] = (float)pn;
     }
   }
 }

@@ -53,9 +53,9 @@ struct Ops {
 struct StateBlock {
   double rz[kMaxLd], alpha[kMaxLd], beta[kMaxLd], stop2[kMaxLd], nrm2[kMaxLd];
   double bnrm2[kMaxLd], rnrm2[kMaxLd];
-  double rz2[2 * kMaxLd];
+  double rz2[2 * kMaxLd], rz_prev[kMaxLd];
   int active[kMaxLd], iters[kMaxLd], flag[kMaxLd];
-  int act2[2 * kMaxLd], bd[kMaxLd];
+  int act2[2 * kMaxLd], bd[kMaxLd], act_prev[kMaxLd], brk[kMaxLd];
 };
 
 struct Work {
@@ -551,18 +551,29 @@ inline unsigned upd_grid(int n_gamma, int ld) {
   return (ch + w - 1) / w;
 }
 
+// Group sums of the grouped and split update launches (one chunk of kRowsE rows
+// per workgroup, kPGroup workgroups per group).
+inline int split_update_groups(int n_gamma, int ld) {
+  return (int)((upd_grid(n_gamma, ld) + kPGroup - 1) / kPGroup);
+}
+
 // CG update launch; the elements per thread follow from the batch width.
+// red: 0 single-level reduction, 1 grouped, 2 split (mode 1; the direction
+// launch k_cg_direction_state finishes the step, see split_update_groups).
 void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, double *x, double *r,
                    double *z, double *p, const double *q, int precond, int *host_nact,
-                   int init_p_is_z, const int *mask, int npq, bool grouped = false) {
+                   int init_p_is_z, const int *mask, int npq, int red = 0) {
   if (c->n_gamma <= 0) return;
   const int cpw = upd_cpw(ld);
   const dim3 g(upd_grid(c->n_gamma, ld)), b(kBlock);
   const int E = std::max(1, cpw * kRowsE * ld / kBlock);
-  grouped = grouped && cpw == 1;
+  if (cpw != 1) red = 0;
 #define DD_UPD(EE)                                                                                        \
-  if (grouped)                                                                                            \
-    hipLaunchKernelGGL((k_cg_update<EE, true>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,   \
+  if (red == 2)                                                                                           \
+    hipLaunchKernelGGL((k_cg_update<EE, 2>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,      \
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p); \
+  else if (red == 1)                                                                                      \
+    hipLaunchKernelGGL((k_cg_update<EE, 1>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,      \
                        r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p); \
   else                                                                                                    \
     hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,         \
@@ -1201,7 +1212,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // interior solve) also written in FP32 for the gathers of the loop below
     if (g32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
-                  dkv, nullptr, 0, tl);
+                  dkv, nullptr, 0, tl ? 1 : 0);
   }
   HIPCHK(c, hipGetLastError());
   if (o.launch == DD_LAUNCH_PERSISTENT && o.apply != DD_APPLY_TRSM && c->n_gamma > 0) {
@@ -1262,10 +1273,14 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
-      launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond, nact_dst,
-                    0, nullptr, c->gamma_parts, tl);
+      launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond,
+                    tl ? nullptr : nact_dst, 0, nullptr, c->gamma_parts, tl ? 2 : 0);
     }
-    if (dk) {
+    if (tl) {        // the split update's state and the direction in one launch
+      unsigned gd = std::min(1024u, grid_for((size_t)c->n_gamma * ld, kBlock));
+      hipLaunchKernelGGL(k_cg_direction_state, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld, w.zG,
+                         pA_, c->red, c->st, split_update_groups(c->n_gamma, ld), nact_dst, c->g32.p);
+    } else if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,
                          w.zG, pA_, c->st, c->g32.p);
@@ -1823,6 +1838,9 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     c->st.rz2 = sb->rz2;
     c->st.act2 = sb->act2;
     c->st.bd = sb->bd;
+    c->st.rz_prev = sb->rz_prev;
+    c->st.act_prev = sb->act_prev;
+    c->st.brk = sb->brk;
     if (hipMemset(sb, 0, sizeof(StateBlock)) != hipSuccess) {
       c->err = "hipMemset failed";
       return bail(DD_EHIP);
