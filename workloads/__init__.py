@@ -415,8 +415,8 @@ def _point_seg_dist2(px, py, ax, ay, bx, by):
 class Partition:
     """Overlapping decomposition and the algebraic interior/interface split."""
     K: int
-    interior: list            # per subdomain: sorted free-node ids of I_k
-    gamma_nodes: np.ndarray   # sorted free-node ids of the interface
+    interior: list            # per subdomain: free-node ids of I_k (2D: in patch order)
+    gamma_nodes: np.ndarray   # free-node ids of the interface (2D: in patch order)
     elem_member: np.ndarray   # (n_interior_elements x K) bool: E in hat-Omega_k
     cuts: tuple               # cut positions (cell units) per axis
     node_free: np.ndarray = None   # (free nodes x K) bool: node of hat-Omega_k
@@ -494,9 +494,23 @@ def partition(spec: Spec, rho: float | None = None) -> Partition:
     free_mask = ((ga > 0) & (ga < n) & (gb > 0) & (gb < n)).reshape(-1)
     free_ext = np.nonzero(free_mask)[0]                # in (b*(n+1)+a) order == free order
     cnt = node_in[free_ext].sum(axis=1)
-    gamma = np.nonzero(cnt >= 2)[0]
-    interior = [np.nonzero((cnt == 1) & node_in[free_ext, k])[0] for k in range(K)]
+    gamma = patch_order(np.nonzero(cnt >= 2)[0], n, spec.ncomp)
+    interior = [patch_order(np.nonzero((cnt == 1) & node_in[free_ext, k])[0], n, spec.ncomp)
+                for k in range(K)]
     return Partition(K, interior, gamma, member, (tuple(cx), tuple(cy)), node_in[free_ext])
+
+
+def patch_order(nodes: np.ndarray, n: int, ncomp: int) -> np.ndarray:
+    """Free-node ids of a 2D set numbered patch by patch: patches of 2 nodes
+    along x and 8 / ncomp along y (16 dofs), patch rows bottom to top, nodes
+    row-major inside a patch.  Sixteen consecutive dofs are then a compact
+    patch whose nonlocal neighbourhoods nearly coincide, which fills the 16x16
+    tiles of the solver's wide-batch products (the ordering of the unknowns is
+    the caller's; the system and its solution are the same)."""
+    nodes = np.asarray(nodes)
+    a, b = nodes % (n - 1), nodes // (n - 1)
+    py = 8 // ncomp
+    return nodes[np.lexsort((a % 2, b % py, a // 2, b // py))]
 
 
 # --------------------------------------------------------------------------
