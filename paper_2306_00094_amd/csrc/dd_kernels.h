@@ -168,10 +168,11 @@ __device__ __forceinline__ void partials_sum2(const double *pa, const double *pb
 // kernel boundary makes them visible; plain loads then hit in every XCD's L2
 // instead of all workgroups of the launch reading the same few lines from
 // memory).
-template <int NC, bool COH = true>
+// B: batches of kWave partials whose loads are issued together (registers:
+// B * NC doubles; the sums do not depend on B).
+template <int NC, bool COH = true, int B = 4>
 __device__ __forceinline__ void partials_sum_cols(const double *part, int P, int ld, int c0, int nc,
                                                   double (&out)[NC]) {
-  constexpr int B = 4;
   double s[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) s[c] = 0.0;
@@ -195,10 +196,9 @@ __device__ __forceinline__ void partials_sum_cols(const double *part, int P, int
   for (int c = 0; c < NC; ++c) out[c] = wave_sum(s[c]);
 }
 
-template <int NC>
+template <int NC, int B = 4>
 __device__ __forceinline__ void partials_sum2_cols(const double *pa, const double *pb, int P, int ld,
                                                    int c0, int nc, double (&ra)[NC], double (&rb)[NC]) {
-  constexpr int B = 4;
   double sa[NC], sb[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) sa[c] = sb[c] = 0.0;
@@ -891,7 +891,9 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     for (int c0 = wv * NC; c0 < ld; c0 += kWavesPerBlock * NC) {
       const int nc = min(NC, ld - c0);
       double pq[NC];
-      partials_sum_cols<NC, false>(red.part3, npq, ld, c0, nc, pq);   // written by the last launch
+      // written by the last launch; one batch of loads (few group sums), which
+      // keeps the registers of this phase low while the element loads are in flight
+      partials_sum_cols<NC, false, 1>(red.part3, npq, ld, c0, nc, pq);
       if (lane < nc) {
         const int c = c0 + lane;
         double pqc = pq[0];
@@ -915,12 +917,18 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     }
     __syncthreads();
   }
-  // element-wise update; products r*z to LDS, r*r kept in registers
-  double rrv[E];
+  // element-wise update; products r*z to LDS, r*r kept in registers.  The new
+  // values stay in registers until this workgroup's partials are published
+  // (flush below): the completion wait before the count then covers only the
+  // partial stores, not the bulk of the vector stores.
+  double rrv[E], xn[E], rn[E], zn[E], pn[E];
+  int wm[E];                                          // 1: x, 2: r, 4: z, 8: p
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int e = threadIdx.x + k * kBlock;
     rrv[k] = 0.0;
+    wm[k] = 0;
+    xn[k] = rn[k] = zn[k] = pn[k] = 0.0;
     if (e < nel) {
       const int lr = e / ld, c = e - lr * ld;
       const int j = row0 + lr;
@@ -929,21 +937,26 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         const size_t o = (size_t)j * ld + c;
         const bool init = mode == 0 || (mode == 2 && mask[c]);
         double rr_ = (mode == 2 && init) ? qv[k] : rv[k];
-        if (mode == 2 && init) r[o] = rr_;
+        if (mode == 2 && init) wm[k] |= 2;
         const bool act = init ? true : (mode == 1 && sact[c] != 0);
         if (mode == 1 && act) {
           const double a = salpha[c];
-          x[o] = fma(a, pv[k], xv[k]);
+          xn[k] = fma(a, pv[k], xv[k]);
           rr_ = fma(-a, qv[k], rr_);
-          r[o] = rr_;
+          wm[k] |= 3;
         }
-        if (init) x[o] = 0.0;
+        if (init) {
+          xn[k] = 0.0;
+          wm[k] |= 1;
+        }
+        rn[k] = rr_;
         double zv = use_precond ? dv[k] * rr_ : rr_;
-        if (act) z[o] = zv;
+        if (act) wm[k] |= 4;
         else zv = z[o];
+        zn[k] = zv;
         if (init) {                                 // direction z, or none yet (beta = 0)
-          p[o] = init_p_is_z ? zv : 0.0;
-          if (p32) p32[o] = init_p_is_z ? (float)zv : 0.f;
+          pn[k] = init_p_is_z ? zv : 0.0;
+          wm[k] |= 8;
         }
         rz = rr_ * zv;
         rrv[k] = rr_ * rr_;
@@ -951,6 +964,22 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       lds[e] = rz;
     }
   }
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (!wm[k]) continue;
+      const int e = threadIdx.x + k * kBlock;
+      const int lr = e / ld, c = e - lr * ld;
+      const size_t o = (size_t)(row0 + lr) * ld + c;
+      if (wm[k] & 1) x[o] = xn[k];
+      if (wm[k] & 2) r[o] = rn[k];
+      if (wm[k] & 4) z[o] = zn[k];
+      if (wm[k] & 8) {
+        p[o] = pn[k];
+        if (p32) p32[o] = (float)pn[k];
+      }
+    }
+  };
   __syncthreads();
   for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
     const int k = t / ld, c = t - k * ld;
@@ -979,7 +1008,9 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     const int grp = blockIdx.x / kPGroup;
     const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
     unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
-    if (!last_of(cnt, (unsigned)members, &lflag)) return;
+    const bool last = last_of(cnt, (unsigned)members, &lflag);
+    flush();
+    if (!last) return;
     double *gs0 = red.part2, *gs1 = red.part2 + (size_t)ngrp * ld;
     group_sums_store(red.part0, nchunks, ld, grp, gs0, wv, kWavesPerBlock);
     group_sums_store(red.part1, nchunks, ld, grp, gs1, wv, kWavesPerBlock);
@@ -991,7 +1022,9 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     fin1 = gs1;
     nfin = ngrp;
   } else {
-    if (!last_block(&red.counter[1], &lflag)) return;
+    const bool last = last_block(&red.counter[1], &lflag);
+    flush();
+    if (!last) return;
   }
   constexpr int NC2 = 4;
   for (int c0 = wv * NC2; c0 < ld; c0 += kWavesPerBlock * NC2) {
