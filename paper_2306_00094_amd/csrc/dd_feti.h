@@ -133,7 +133,7 @@ __global__ void k_pack_sub(int nsub, const T *__restrict__ blocks, const long lo
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
     const int t = (int)(e / 256), pos = (int)(e % 256);
-    const int I = t / nt, J = t % nt, l = pos / 4, s = pos % 4;
+    const int I = t / nt, J = t % nt, l = TileLayout<double>::lane(pos), s = TileLayout<double>::step(pos);
     const int i = I * kT + (l & 15), j = J * kT + 4 * s + (l >> 4);
     const bool keep = i < m && j < m && !pinned[uo[k] + i] && !pinned[uo[k] + j];
     P[e] = keep ? (double)B[(size_t)(o + j) * n + (o + i)] : 0.0;

@@ -100,10 +100,10 @@ struct dd_ctx {
   int *d_ig_ptr = nullptr, *d_ig_col = nullptr;
   int *d_g_ptr = nullptr, *d_g_split = nullptr, *d_g_col = nullptr;
   // wide batches on the matrix cores (built when max_nrhs >= 8 and there are
-  // interiors): 16x16 tiles of K_IG over 16-row blocks of the interior rows, of
-  // [K_GG | K_GI] over 16-row blocks of the interface rows (tiles [ptr, split)
-  // multiply p, [split, ptr+1) multiply w), and the (subdomain, 16-row tile)
-  // work items of the interior solve
+  // interiors): 16x16 tiles of K_IG over blocks of kTileRbI x 16 interior rows,
+  // of [K_GG | K_GI] over blocks of kTileRbG x 16 interface rows (entries
+  // [ptr, split) multiply p, [split, ptr+1) multiply w; t_nI, t_nG count 16x16
+  // tiles), and the (subdomain, 16-row tile) work items of the interior solve
   bool tiles = false;
   int t_nrbI = 0, t_nrbG = 0, n_dit = 0;
   size_t t_nI = 0, t_nG = 0;
@@ -293,24 +293,33 @@ dd_status validate(const dd_problem *p) {
   return DD_OK;
 }
 
-// Block CSR of 16x16 tiles over 16-row blocks.  Row i's entries [ptr[i], mid)
-// (columns in [0, ncol1)) go to the first part of its block, entries
-// [mid, ptr[i+1]) (columns in [0, ncol2)) to the second, mid = split[i] (or
-// ptr[i+1] when split is null).  Within a part the tiles are in increasing
-// column-block order; values are placed in the A-operand order of the
-// 16x16x4 matrix instructions (dd_tiles.h), zeros elsewhere.
+// Block CSR of 16x16 tiles over row blocks of RB x 16 rows.  Row i's entries
+// [ptr[i], mid) (columns in [0, ncol1)) go to the first part of its block,
+// entries [mid, ptr[i+1]) (columns in [0, ncol2)) to the second, mid =
+// split[i] (or ptr[i+1] when split is null).  Within a part the column blocks
+// are in increasing order; an entry (row block, column block) holds RB tiles,
+// one per 16-row slice of the block (zero where the slice has no entry), so
+// that one slice of the multiplied vector serves RB tiles.  Values are placed
+// in the A-operand order of the 16x16x4 matrix instructions (dd_tiles.h),
+// zeros elsewhere.  Returns the number of 16x16 tiles (entries x RB).
 struct TileSet {
   std::vector<int> ptr, split, col;
   std::vector<double> val;
 };
 constexpr int kTileMinLd = 8;     // narrowest batch served by the tiled products
+// 16-row slices per row block: the interface rows (the largest product) share
+// each vector slice between two slices of rows; the interior rows K_IG, with
+// fewer row blocks, keep one (their launch would otherwise fill the chip
+// only half).
+constexpr int kTileRbG = 2, kTileRbI = 1;
 
 size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, const double *val,
-                   int ncol1, int ncol2, TileSet *ts) {
-  const int nrb = (nrows + kT - 1) / kT;
+                   int ncol1, int ncol2, int RB, TileSet *ts) {
+  const int H = RB * kT;
+  const int nrb = (nrows + H - 1) / H;
   std::vector<int> slot1((ncol1 + kT - 1) / kT + 1, -1), slot2((ncol2 + kT - 1) / kT + 1, -1);
   std::vector<int> cb1, cb2;
-  size_t ntiles = 0;
+  size_t nent = 0;
   if (ts) {
     ts->ptr.assign(nrb + 1, 0);
     ts->split.assign(nrb, 0);
@@ -318,7 +327,7 @@ size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, 
     ts->val.clear();
   }
   for (int rb = 0; rb < nrb; ++rb) {
-    const int i0 = rb * kT, i1 = std::min(nrows, i0 + kT);
+    const int i0 = rb * H, i1 = std::min(nrows, i0 + H);
     cb1.clear();
     cb2.clear();
     for (int i = i0; i < i1; ++i) {
@@ -334,30 +343,31 @@ size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, 
     }
     std::sort(cb1.begin(), cb1.end());
     std::sort(cb2.begin(), cb2.end());
-    const size_t base = ntiles;
+    const size_t base = nent;
     for (size_t t = 0; t < cb1.size(); ++t) slot1[cb1[t]] = (int)(base + t);
     for (size_t t = 0; t < cb2.size(); ++t) slot2[cb2[t]] = (int)(base + cb1.size() + t);
-    ntiles += cb1.size() + cb2.size();
+    nent += cb1.size() + cb2.size();
     if (ts) {
       for (int cb : cb1) ts->col.push_back(cb);
       ts->split[rb] = (int)ts->col.size();
       for (int cb : cb2) ts->col.push_back(cb);
       ts->ptr[rb + 1] = (int)ts->col.size();
-      ts->val.resize(ntiles * 256, 0.0);
+      ts->val.resize(nent * RB * 256, 0.0);
       for (int i = i0; i < i1; ++i) {
         const int mid = split ? split[i] : ptr[i + 1];
+        const int h = (i - i0) / kT, ii = (i - i0) % kT;
         for (int a = ptr[i]; a < ptr[i + 1]; ++a) {
           const int t = a < mid ? slot1[col[a] / kT] : slot2[col[a] / kT];
-          const int ii = i - i0, kk = col[a] % kT;
-          // T[ii][kk] is held by lane (kk % 4) * 16 + ii at step kk / 4
-          ts->val[(size_t)t * 256 + 4 * ((kk % 4) * kT + ii) + kk / 4] += val[a];
+          const int kk = col[a] % kT;
+          // T[ii][kk] of slice h is held by lane (kk % 4) * 16 + ii at step kk / 4
+          ts->val[((size_t)t * RB + h) * 256 + TileLayout<double>::pos((kk % 4) * kT + ii, kk / 4)] += val[a];
         }
       }
     }
     for (int cb : cb1) slot1[cb] = -1;
     for (int cb : cb2) slot2[cb] = -1;
   }
-  return ntiles;
+  return nent * RB;
 }
 
 // Tiles of a problem (interior rows x interface columns, interface rows x
@@ -380,7 +390,7 @@ void count_problem_tiles(const dd_problem *p, size_t *nI, size_t *nG) {
       iptr.push_back((int)icol.size());
     }
   }
-  *nI = build_tiles(NI, iptr.data(), nullptr, icol.data(), nullptr, p->n_gamma, 1, nullptr);
+  *nI = build_tiles(NI, iptr.data(), nullptr, icol.data(), nullptr, p->n_gamma, 1, kTileRbI, nullptr);
   std::vector<int> gptr(1, 0), gsplit, gcol;
   for (int j = 0; j < p->n_gamma; ++j) {
     for (int a = p->kgg_rowptr[j]; a < p->kgg_rowptr[j + 1]; ++a) gcol.push_back(p->kgg_col[a]);
@@ -389,7 +399,7 @@ void count_problem_tiles(const dd_problem *p, size_t *nI, size_t *nG) {
     gptr.push_back((int)gcol.size());
   }
   *nG = build_tiles(p->n_gamma, gptr.data(), gsplit.data(), gcol.data(), nullptr, p->n_gamma,
-                    std::max(1, NI), nullptr);
+                    std::max(1, NI), kTileRbG, nullptr);
 }
 
 size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
@@ -414,7 +424,8 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
   if (max_nrhs >= kTileMinLd && p->n_sub > 0 && p->n_gamma > 0) {    // tiles of the wide batches
     size_t tI = 0, tG = 0;
     count_problem_tiles(p, &tI, &tG);
-    const size_t nrbI = (NI + kT - 1) / kT, nrbG = (p->n_gamma + kT - 1) / kT;
+    const size_t nrbI = (NI + kT * kTileRbI - 1) / (kT * kTileRbI),
+                 nrbG = (p->n_gamma + kT * kTileRbG - 1) / (kT * kTileRbG);
     b += (tI + tG) * (4 + 256 * 8) + (nrbI + 1) * 4 + (2 * nrbG + 1) * 4 + NI * 8 / kT + 64;
     if (prec == DD_MIXED) b += (tI + tG) * 256 * 4;
     size_t kp = 0;                       // packed K_II (FP64) and K_II^{-1} (T)
@@ -692,16 +703,22 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // two tiles in flight per wave: three or four measured slower on the
   // peridynamic 32-column batch (148, 155, 166 us per interface launch)
-  if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
-    hipExtLaunchKernelGGL((k_tile_rows<VT, NCB, DOT, 2>), g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr,
-                          split, col, val, x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
-  else
-    hipLaunchKernelGGL((k_tile_rows<VT, NCB, DOT, 2>), g, b, 0, c->stream, nrb, nrows, ptr, split, col, val,
-                       x1, c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
+  auto launch = [&](auto kern) {
+    if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
+      hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr, split, col, val, x1,
+                            c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
+    else
+      hipLaunchKernelGGL(kern, g, b, 0, c->stream, nrb, nrows, ptr, split, col, val, x1, c->n_gamma, x2, n2,
+                         ld, base, c1, c2, out, c->red);
+  };
+  if (interface_rows) launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbG>);
+  else launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbI>);
 }
 
 // out = base + c1 * (tiled K_IG or K_GG) x1 + c2 * (tiled K_GI) x2 with the
-// coupling values of `prec` (interface_rows: [K_GG | K_GI], else K_IG).
+// coupling values of `prec` (interface_rows: [K_GG | K_GI], else K_IG).  With
+// both parts c2 must be c1 or -c1 (the kernel sums both parts in one
+// accumulator).
 template <bool DOT>
 void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const double *x2, int ld,
                const double *base, double c1, double c2, double *out) {
@@ -955,9 +972,9 @@ dd_status factor_impl(dd_ctx *c, int pi) {
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_g, c->d_g_val64,
                        (float *)o.g_val);
     if (c->tiles) {
-      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nI * 256, c->d_tI_val64,
+      hipLaunchKernelGGL(k_tiles_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nI, c->d_tI_val64,
                          (float *)o.tI_val);
-      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nG * 256, c->d_tG_val64,
+      hipLaunchKernelGGL(k_tiles_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nG, c->d_tG_val64,
                          (float *)o.tG_val);
     }
     HIPCHK(c, hipGetLastError());
@@ -1751,11 +1768,11 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
   // tiles of the wide-batch products (matrix cores)
   if (c->ldmax >= kTileMinLd && c->n_sub > 0 && c->n_gamma > 0 && !getenv("DD_NO_TILES")) {
     TileSet ti, tg;
-    c->t_nI = build_tiles(NI, igptr.data(), nullptr, igcol.data(), igval.data(), c->n_gamma, 1, &ti);
+    c->t_nI = build_tiles(NI, igptr.data(), nullptr, igcol.data(), igval.data(), c->n_gamma, 1, kTileRbI, &ti);
     c->t_nG = build_tiles(c->n_gamma, gptr.data(), gsplit.data(), gcol.data(), gval.data(), c->n_gamma,
-                          std::max(1, NI), &tg);
-    c->t_nrbI = (NI + kT - 1) / kT;
-    c->t_nrbG = (c->n_gamma + kT - 1) / kT;
+                          std::max(1, NI), kTileRbG, &tg);
+    c->t_nrbI = (NI + kT * kTileRbI - 1) / (kT * kTileRbI);
+    c->t_nrbG = (c->n_gamma + kT * kTileRbG - 1) / (kT * kTileRbG);
     // Interior-solve work items (subdomain, 16-row tile).  Workgroup b runs on
     // XCD b % 8: every subdomain's items go to one XCD (its slices of y are then
     // cached in one L2), subdomains by decreasing work to the least loaded XCD,
@@ -1783,7 +1800,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     for (TileSet *t : {&ti, &tg})          // uploads need at least one element
       if (t->col.empty()) {
         t->col.push_back(0);
-        t->val.assign(256, 0.0);
+        t->val.assign((size_t)kTileRbG * 256, 0.0);
       }
     if ((s = upload(c, &c->d_tI_ptr, ti.ptr.data(), ti.ptr.size())) != DD_OK) return bail(s);
     if ((s = upload(c, &c->d_tI_col, ti.col.data(), ti.col.size())) != DD_OK) return bail(s);

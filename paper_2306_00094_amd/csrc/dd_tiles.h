@@ -28,25 +28,52 @@ namespace dd {
 
 constexpr int kT = 16;   // tile edge
 
-// Tile storage: 256 values per tile, lane l of the wave holding
-// T[l % 16][4 s + l / 16] at position 4 l + s (s = 0..3), i.e. the A operand
-// of step s of the 16x16x4 instruction; one 32-byte (FP64) or 16-byte (FP32)
-// load per lane brings a lane's four steps.
+// Tile storage: 256 values per tile; lane l of the wave holds
+// T[l % 16][4 s + l / 16], the A operand of step s (s = 0..3) of the 16x16x4
+// instruction.  FP64 tiles keep steps 0-1 of lane l at 2l, 2l+1 and steps 2-3
+// at 128 + 2l, 128 + 2l + 1, so that each of a wave's two 16-byte loads reads
+// 1 KB contiguous (whole cache lines); FP32 tiles keep the four steps of lane
+// l at 4l .. 4l+3, one 16-byte load per lane.
+template <typename T> struct TileLayout;
+template <> struct TileLayout<double> {
+  static __host__ __device__ constexpr int pos(int l, int s) { return (s >> 1) * 128 + 2 * l + (s & 1); }
+  static __host__ __device__ constexpr int lane(int p) { return (p & 127) >> 1; }
+  static __host__ __device__ constexpr int step(int p) { return ((p >> 7) << 1) | (p & 1); }
+};
+template <> struct TileLayout<float> {
+  static __host__ __device__ constexpr int pos(int l, int s) { return 4 * l + s; }
+  static __host__ __device__ constexpr int lane(int p) { return p >> 2; }
+  static __host__ __device__ constexpr int step(int p) { return p & 3; }
+};
+
+// A operand of a streamed coupling tile (nontemporal loads) as doubles.
 template <typename VT> struct TileA;
 template <> struct TileA<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ void load(const double *p, double (&a)[4]) {
-    const v4 v = __builtin_nontemporal_load((const v4 *)p);
-    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(const double *tile, int lane, double (&a)[4]) {
+    const v2 u = __builtin_nontemporal_load((const v2 *)(tile + 2 * lane));
+    const v2 v = __builtin_nontemporal_load((const v2 *)(tile + 128 + 2 * lane));
+    a[0] = u[0]; a[1] = u[1]; a[2] = v[0]; a[3] = v[1];
   }
 };
 template <> struct TileA<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ void load(const float *p, double (&a)[4]) {
-    const v4 v = __builtin_nontemporal_load((const v4 *)p);
+  static __device__ __forceinline__ void load(const float *tile, int lane, double (&a)[4]) {
+    const v4 v = __builtin_nontemporal_load((const v4 *)(tile + 4 * lane));
     a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
   }
 };
+
+// FP64 tiles -> FP32 tiles (the mixed path's copies), layout converted.
+__global__ void k_tiles_to_f32(size_t ntiles, const double *__restrict__ in, float *__restrict__ out) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * 256;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = e / 256;
+    const int p = (int)(e % 256);
+    const int l = TileLayout<float>::lane(p), s = TileLayout<float>::step(p);
+    out[e] = (float)in[t * 256 + TileLayout<double>::pos(l, s)];
+  }
+}
 
 // Columns of the vector slices: with NCB column blocks of 16 (ld = 16 NCB for
 // NCB >= 2) lane l holds the NCB consecutive columns NCB (l % 16) + q, q < NCB,
@@ -96,40 +123,51 @@ __device__ __forceinline__ void tile_mma(const double (&a)[4], const double (&xv
     for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], xv[s][q], acc[q]);
 }
 
-// acc[q] += T * X over the tiles t0, t0 + st, t0 + 2 st, ... (< t1) of one row
-// block, in that order (t0, t1, st uniform over the wave).  The tiles' column
-// blocks are fetched 64 at a time, one per lane, and broadcast by readlane; D
-// register buffers hold the operands of the next D tiles while a tile's
-// instructions run (the last loads of a wave repeat its last tile and are not
-// used).  Scheduling barriers keep every group of loads in program order, so
-// that the instructions of one buffer wait only for that buffer's loads, the
-// other buffers' staying in flight.
-template <typename VT, int NCB, int D>
+// acc[h][q] += T_h * X over the entries t0, t0 + st, t0 + 2 st, ... (< t1) of
+// one row block, in that order (t0, t1, st uniform over the wave); entry t holds
+// the RB tiles T_h (16-row slice h of the block) at tval + (t RB + h) 256, all
+// multiplying the same 16-row slice of x, which is loaded once.  The entries'
+// column blocks are fetched 64 at a time, one per lane, and broadcast by
+// readlane; D register buffers hold the operands of the next D entries while an
+// entry's instructions run (the last loads of a wave repeat its last entry and
+// are not used).  Scheduling barriers keep every group of loads in program
+// order, so that the instructions of one buffer wait only for that buffer's
+// loads, the other buffers' staying in flight.
+template <typename VT, int NCB, int D, int RB>
 __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *__restrict__ tcol,
                                              const VT *__restrict__ tval, const double *__restrict__ x,
-                                             int n, int ld, dbl4 (&acc)[NCB]) {
+                                             int n, int ld, double sgn, dbl4 (&acc)[RB][NCB]) {
   const int cnt = t0 < t1 ? (t1 - t0 + st - 1) / st : 0;
   const int lane = lane_id();
   for (int base = 0; base < cnt; base += kWave) {
     const int nb = min(kWave, cnt - base);
     const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
-    const VT *tv = tval + (size_t)(t0 + base * st) * 256 + 4 * lane;
-    const size_t tstride = (size_t)st * 256;
-    double a[D][4], xs[D][4][NCB];
+    const VT *tv = tval + (size_t)(t0 + base * st) * RB * 256;
+    const size_t tstride = (size_t)st * RB * 256;
+    double a[D][RB][4], xs[D][4][NCB];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int jd = min(d, nb - 1);
-      TileA<VT>::load(tv + jd * tstride, a[d]);
+#pragma unroll
+      for (int h = 0; h < RB; ++h) TileA<VT>::load(tv + jd * tstride + h * 256, lane, a[d][h]);
       load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jd), xs[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
     for (int j = 0; j < nb; j += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        if (j + d < nb) tile_mma<NCB>(a[d], xs[d], acc);
+        if (j + d < nb) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)              // sgn = +-1: exact
+#pragma unroll
+            for (int q = 0; q < NCB; ++q) xs[d][s][q] *= sgn;
+#pragma unroll
+          for (int h = 0; h < RB; ++h) tile_mma<NCB>(a[d][h], xs[d], acc[h]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         const int jn = min(j + d + D, nb - 1);
-        TileA<VT>::load(tv + jn * tstride, a[d]);
+#pragma unroll
+        for (int h = 0; h < RB; ++h) TileA<VT>::load(tv + jn * tstride + h * 256, lane, a[d][h]);
         load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), xs[d]);
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -157,51 +195,64 @@ __device__ __forceinline__ int wave_uniform() {
 constexpr int kTW = 4;
 
 // One workgroup per block of 16 rows of a tiled matrix:
-//   out = base + sum over waves w of (c1 * (tiles [ptr, split) of wave w applied to x1)
-//                                     + c2 * (tiles [split, ptr+1) of wave w applied to x2))
-// (split == nullptr: one part, tiles [ptr, ptr+1) applied to x1; base may be
-// nullptr; a part whose coefficient is 0 is skipped).  x1 has n1 rows, x2 n2
-// rows, out nrows rows; all three DD layout with leading dimension ld.  Wave w
-// takes tiles b + w, b + w + kTW, ...; the wave sums are added in wave order.
-// With DOT the workgroup also writes x1^T out over its 16 rows (rows in order)
-// per column to red.part2, and the last of every kPGroup consecutive
-// workgroups the group sum to red.part3, which the update kernel reduces (the
-// step length of the CG iteration, from p^T S p).
-template <typename VT, int NCB, bool DOT, int D = 2>
+//   out = base + sum over waves w of (c1 * (entries [ptr, split) of wave w applied to x1)
+//                                     + c2 * (entries [split, ptr+1) of wave w applied to x2))
+// (split == nullptr: one part, entries [ptr, ptr+1) applied to x1; base may be
+// nullptr; a part whose coefficient is 0 is skipped) for the RB x 16 rows of
+// one row block.  x1 has n1 rows, x2 n2 rows, out nrows rows; all three DD
+// layout with leading dimension ld.  Wave w takes entries b + w, b + w + kTW,
+// ...; the wave sums are added in wave order.  With DOT the workgroup also
+// writes x1^T out over its rows (rows in order) per column to red.part2, and
+// the last of every kPGroup consecutive workgroups the group sum to red.part3,
+// which the update kernel reduces (the step length of the CG iteration, from
+// p^T S p).
+template <typename VT, int NCB, bool DOT, int D, int RB>
 __global__ void __launch_bounds__(kTW * kWave)
 k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
             const int *__restrict__ tcol, const VT *__restrict__ tval, const double *__restrict__ x1,
             int n1, const double *__restrict__ x2, int n2, int ld, const double *__restrict__ base,
             double c1, double c2, double *__restrict__ out, RedBuf red) {
+  constexpr int H = RB * kT;                     // rows of a block
   const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const int rb = xcd_item(blockIdx.x, nrb);
-  dbl4 acc1[NCB], acc2[NCB];
+  // one accumulator: with both parts, the second part's products enter the
+  // same sums with x2 negated when c2 = -c1 (exact), and the total is scaled by
+  // c1; a lone part is scaled by its own coefficient.  Only c2 = +-c1 is
+  // served with both parts.
+  dbl4 acc[RB][NCB];
 #pragma unroll
-  for (int q = 0; q < NCB; ++q)
+  for (int h = 0; h < RB; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc1[q][r] = acc2[q][r] = 0.0;
+    for (int q = 0; q < NCB; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[h][q][r] = 0.0;
   const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
-  if (c1 != 0.0) tile_row_acc<VT, NCB, D>(b + wv, s, kTW, tcol, tval, x1, n1, ld, acc1);
-  if (split && c2 != 0.0) tile_row_acc<VT, NCB, D>(s + wv, e, kTW, tcol, tval, x2, n2, ld, acc2);
-  __shared__ double part[kTW * kT * kT * NCB];   // ld <= 16 NCB
+  if (c1 != 0.0) tile_row_acc<VT, NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
+  if (split && c2 != 0.0)
+    tile_row_acc<VT, NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, (c1 != 0.0 && c2 == -c1) ? -1.0 : 1.0, acc);
+  const double cf = c1 != 0.0 ? c1 : c2;
+  __shared__ double part[kTW * H * kT * NCB];    // ld <= 16 NCB
 #pragma unroll
-  for (int q = 0; q < NCB; ++q) {
-    const int col = NCB * l16 + q;
+  for (int h = 0; h < RB; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lr = g + 4 * r;                  // row of the tile held in register r
-      if (col < ld) part[(wv * kT + lr) * ld + col] = c1 * acc1[q][r] + c2 * acc2[q][r];
+    for (int q = 0; q < NCB; ++q) {
+      const int col = NCB * l16 + q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lr = h * kT + g + 4 * r;       // row of the block held in register r
+        if (col < ld) part[(wv * H + lr) * ld + col] = cf * acc[h][q][r];
+      }
     }
-  }
   __syncthreads();
-  const int nel = kT * ld;
-  double fin[kMaxLd * kT / (kTW * kWave)];       // this thread's elements (at most 4)
+  const int nel = H * ld;
+  constexpr int NF = kMaxLd * H / (kTW * kWave);
+  double fin[NF];                                // this thread's elements
 #pragma unroll
-  for (int u = 0; u < kMaxLd * kT / (kTW * kWave); ++u) {
+  for (int u = 0; u < NF; ++u) {
     const int el = threadIdx.x + u * kTW * kWave;
     fin[u] = 0.0;
     if (el < nel) {
-      const int lr = el / ld, col = el - lr * ld, row = rb * kT + lr;
+      const int lr = el / ld, col = el - lr * ld, row = rb * H + lr;
       double v = part[el];
 #pragma unroll
       for (int w = 1; w < kTW; ++w) v += part[w * nel + el];
@@ -216,7 +267,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
   if (!DOT) return;
   __syncthreads();                               // every wave read its part: reuse it
 #pragma unroll
-  for (int u = 0; u < kMaxLd * kT / (kTW * kWave); ++u) {
+  for (int u = 0; u < NF; ++u) {
     const int el = threadIdx.x + u * kTW * kWave;
     if (el < nel) part[el] = fin[u];
   }
@@ -224,7 +275,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
   if ((int)threadIdx.x < ld) {
     const int c = threadIdx.x;
     double sm = 0.0;
-    for (int lr = 0; lr < kT; ++lr) sm += part[lr * ld + c];
+    for (int lr = 0; lr < H; ++lr) sm += part[lr * ld + c];
     store_partial(red.part2 + (size_t)rb * ld + c, sm);
   }
   const int grp = rb / kPGroup;
@@ -258,18 +309,20 @@ template <> struct DenseAcc<float> {
   static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
 };
 
+// A operand of a packed interior-block tile (layout of TileLayout<MT>).
 template <typename MT> struct TileAT;
 template <> struct TileAT<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ void load(const double *p, double (&a)[4]) {
-    const v4 v = *(const v4 *)p;
-    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(const double *tile, int lane, double (&a)[4]) {
+    const v2 u = *(const v2 *)(tile + 2 * lane);
+    const v2 v = *(const v2 *)(tile + 128 + 2 * lane);
+    a[0] = u[0]; a[1] = u[1]; a[2] = v[0]; a[3] = v[1];
   }
 };
 template <> struct TileAT<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ void load(const float *p, float (&a)[4]) {
-    const v4 v = *(const v4 *)p;
+  static __device__ __forceinline__ void load(const float *tile, int lane, float (&a)[4]) {
+    const v4 v = *(const v4 *)(tile + 4 * lane);
     a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
   }
 };
@@ -286,7 +339,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
   const int k = item.x, r0 = item.y * kT;
   const int n = ni[k], i0 = ioff[k];
   const int nt = (n + kT - 1) / kT;
-  const MT *A = packed + toff[k] + (size_t)item.y * nt * 256 + 4 * lane;
+  const MT *A = packed + toff[k] + (size_t)item.y * nt * 256;
   // y rows past the block (the next subdomain's, or the last row repeated at
   // the end of y) meet the zero padding of the packed tiles
   const double *yb = y + slice_col0<NCB>(l16, ld);
@@ -297,7 +350,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[q][r] = (MT)0;
   auto load = [&](int J, MT (&a)[4], MT (&b)[4][NCB]) {
-    TileAT<MT>::load(A + (size_t)J * 256, a);
+    TileAT<MT>::load(A + (size_t)J * 256, lane, a);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double v[NCB];
@@ -356,7 +409,8 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
 
 // Packs column-major dense blocks (n_k x n_k at koff[k]) into the tile order
 // of k_dense_tiles: tile (I, J) of block k at toff[k] + (I * nt + J) * 256,
-// lane l holding B[16 I + l % 16][16 J + 4 s + l / 16] at position 4 l + s.
+// lane l holding B[16 I + l % 16][16 J + 4 s + l / 16] at position
+// TileLayout<T>::pos(l, s).
 template <typename T>
 __global__ void k_pack_tiles(int nsub, const T *__restrict__ blocks, const long long *__restrict__ koff,
                              const long long *__restrict__ toff, const int *__restrict__ ni,
@@ -370,7 +424,7 @@ __global__ void k_pack_tiles(int nsub, const T *__restrict__ blocks, const long 
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
     const int t = (int)(e / 256), pos = (int)(e % 256);
-    const int I = t / nt, J = t % nt, l = pos / 4, s = pos % 4;
+    const int I = t / nt, J = t % nt, l = TileLayout<T>::lane(pos), s = TileLayout<T>::step(pos);
     const int i = I * kT + (l & 15), j = J * kT + 4 * s + (l >> 4);
     P[e] = (i < n && j < n) ? B[(size_t)j * n + i] : (T)0;
   }
