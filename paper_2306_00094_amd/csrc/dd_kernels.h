@@ -105,6 +105,44 @@ __device__ __forceinline__ double chunk64_sum(const double *lds, int ld, int c) 
   return wave_sum(lds[lane_id() * ld + c]);
 }
 
+// chunk64_sum of two dots for a whole chunk held in registers: element
+// threadIdx.x + k * kBlock of a chunk of width ld = 4 E (E >= 4) is row
+// threadIdx.x / ld + (64 / E) k, column threadIdx.x % ld, with a[k] and b[k]
+// its terms of the two dots.  The butterfly pairs rows m and m + 32 first,
+// then m and m + 16, ..., m and m + 1; the levels of distance 64 / E and more
+// pair values of one thread (k and k + h) and are added in registers, the
+// rest by one thread per (column, dot) from LDS, in the same pairs, so every
+// sum has the bits of chunk64_sum.  The sums go to outa[c] and outb[c] by
+// device-coherent stores (not waited for).  lds: 2 kBlock doubles.
+template <int E>
+__device__ __forceinline__ void chunk64_sums2(double (&a)[E], double (&b)[E], double *lds, double *outa,
+                                              double *outb) {
+  static_assert(E >= 4 && (E & (E - 1)) == 0, "one chunk of 16 or more columns per workgroup");
+  constexpr int LD = 4 * E, R = 64 / E;
+#pragma unroll
+  for (int h = E / 2; h >= 1; h /= 2)
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      a[k] += a[k + h];
+      b[k] += b[k + h];
+    }
+  lds[threadIdx.x] = a[0];
+  lds[kBlock + threadIdx.x] = b[0];
+  __syncthreads();
+  if (threadIdx.x < 2 * LD) {
+    const int t = threadIdx.x / LD, c = threadIdx.x % LD;
+    const double *s = lds + t * kBlock + c;
+    double u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = s[r * LD];
+#pragma unroll
+    for (int h = R / 2; h >= 1; h /= 2)
+#pragma unroll
+      for (int r = 0; r < h; ++r) u[r] += u[r + h];
+    __hip_atomic_store((t ? outb : outa) + c, u[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Chunk partials cross workgroups (and XCDs, whose L2 caches are not kept
 // coherent with each other).  They are written with device-coherent (sc1)
 // stores and read with device-coherent loads; the writing thread waits for
@@ -262,7 +300,7 @@ __device__ __forceinline__ bool last_of(unsigned *counter, unsigned members, int
 // single wait for completion (one memory round trip per pass, not one load and
 // one store round trip per column).
 __device__ __forceinline__ void group_sums_store(const double *part, int P, int ld, int g,
-                                                 double *out, int wv, int nw) {
+                                                 double *out, int wv, int nw, bool wait = true) {
   constexpr int NC = 8;
   const int m = g * kPGroup + lane_id();
   for (int c0 = wv * NC; c0 < ld; c0 += nw * NC) {
@@ -280,7 +318,7 @@ __device__ __forceinline__ void group_sums_store(const double *part, int P, int 
         if (c0 + u < ld)
           __hip_atomic_store(out + (size_t)g * ld + c0 + u, v[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the group sums are stored
+  if (wait) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the group sums are stored
 }
 
 // Sum of chunk partials g*kPGroup .. g*kPGroup+63 (those < P) of column c.
@@ -841,8 +879,9 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 // group finishes the column state from the group sums -- the load of the final
 // sum spread over the groups instead of one workgroup reducing every chunk of
 // every column.
-// RED = 2 (split; mode 1 only): as RED = 1, but the launch ends with the group
-// sums; k_cg_direction_state reduces them and finishes the column state.
+// RED = 2 (split; mode 1 only): the launch ends with the chunk partials (no
+// completion count); k_cg_direction_state reduces them, in the tree of RED = 1,
+// and finishes the column state.
 // Workgroup 0 records the state this step started from (r.z, active) and its
 // step length and breakdown marks for it.
 template <int E, int RED = 0>
@@ -921,12 +960,12 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
   // values stay in registers until this workgroup's partials are published
   // (flush below): the completion wait before the count then covers only the
   // partial stores, not the bulk of the vector stores.
-  double rrv[E], xn[E], rn[E], zn[E], pn[E];
+  double rzv[E], rrv[E], xn[E], rn[E], zn[E], pn[E];
   int wm[E];                                          // 1: x, 2: r, 4: z, 8: p
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int e = threadIdx.x + k * kBlock;
-    rrv[k] = 0.0;
+    rzv[k] = rrv[k] = 0.0;
     wm[k] = 0;
     xn[k] = rn[k] = zn[k] = pn[k] = 0.0;
     if (e < nel) {
@@ -961,7 +1000,8 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         rz = rr_ * zv;
         rrv[k] = rr_ * rr_;
       }
-      lds[e] = rz;
+      rzv[k] = rz;
+      if constexpr (E < 4) lds[e] = rz;
     }
   }
   auto flush = [&]() {
@@ -980,30 +1020,38 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       }
     }
   };
-  __syncthreads();
-  for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
-    const int k = t / ld, c = t - k * ld;
-    double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
-    if (lane == 0) __hip_atomic_store(red.part0 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (E >= 4) {                             // (one chunk, ld = 4 E)
+    chunk64_sums2<E>(rzv, rrv, lds, red.part0 + (size_t)chunk0 * ld, red.part1 + (size_t)chunk0 * ld);
+  } else {
+    __syncthreads();
+    for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
+      const int k = t / ld, c = t - k * ld;
+      double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
+      if (lane == 0) __hip_atomic_store(red.part0 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < nel) lds[e] = rrv[k];
+    }
+    __syncthreads();
+    for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
+      const int k = t / ld, c = t - k * ld;
+      double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
+      if (lane == 0) __hip_atomic_store(red.part1 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int e = threadIdx.x + k * kBlock;
-    if (e < nel) lds[e] = rrv[k];
-  }
-  __syncthreads();
-  for (int t = wv; t < nck * ld; t += kWavesPerBlock) {
-    const int k = t / ld, c = t - k * ld;
-    double sm = chunk64_sum(lds + (size_t)k * kRowsE * ld, ld, c);
-    if (lane == 0) __hip_atomic_store(red.part1 + (size_t)(chunk0 + k) * ld + c, sm, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (RED == 2) {                           // the direction launch reduces them
+    flush();
+    return;
   }
   __builtin_amdgcn_s_waitcnt(0x0F70);   // both partial stores complete before the count
   const double *fin0 = red.part0, *fin1 = red.part1;
   int nfin = nchunks;
-  if constexpr (RED >= 1) {
+  if constexpr (RED == 1) {
     const int ngrp = ((int)gridDim.x + kPGroup - 1) / kPGroup;
     const int grp = blockIdx.x / kPGroup;
     const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
@@ -1016,7 +1064,6 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     group_sums_store(red.part1, nchunks, ld, grp, gs1, wv, kWavesPerBlock);
     __syncthreads();
     if (threadIdx.x == 0) reset_counter(cnt);
-    if constexpr (RED == 2) return;
     if (!last_of(&red.counter[1], (unsigned)ngrp, &lflag)) return;
     fin0 = gs0;
     fin1 = gs1;
@@ -1660,53 +1707,118 @@ k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restri
   }
 }
 
-// End of a CG step after the split update (k_cg_update<E, 2>): every workgroup
-// reduces the ngrp group sums of r.z and r.r per column in the same fixed
-// order, decides the column's state from them and from the state the step
-// started from (rz_prev, act_prev, brk, recorded by the update's workgroup 0;
-// the state itself is written here by workgroup 0 and read by no other
-// workgroup of this launch), and forms p = z + beta p for the columns still
-// iterating.  Workgroup 0 also writes the column state (as the last workgroup
-// of the grouped update does) and publishes (active columns + 1) to host_nact.
-__global__ void __launch_bounds__(kBlock)
+// End of a CG step after the split update (k_cg_update<E, 2>).  The column
+// sums of r.z and r.r are formed from the nch chunk partials of the update in
+// one fixed order -- group sums over kPGroup consecutive chunks by the tree of
+// chunk_group_sum (one thread per column, dot and group, the butterfly's pairs
+// added in registers), then the groups in order -- which gives the bits of the
+// grouped update's two levels.  Workgroup b updates the direction
+// p = z + beta p of the still iterating columns for column block b % ncb
+// (kDirCols columns, or ld when narrower) over its share of the rows, and
+// reduces the sums of that block only; workgroup 0 reduces every column and
+// writes the column state (from the sums and the state the step started from:
+// rz_prev, act_prev, brk, recorded by the update's workgroup 0; the state is
+// read by no other workgroup of this launch), and publishes (active columns +
+// 1) to host_nact.  ld: a power of two from 8 to kMaxLd; the grid a multiple
+// of ld / min(ld, kDirCols).
+constexpr int kDirCols = 16;       // 128-byte row segments
+constexpr int kDirBlock = 512;
+constexpr int kDirE = 12;          // direction elements per thread held across the reduction
+
+// tot[t * kMaxLd + c] = sum of dot t (0: r.z, 1: r.r) of column c, c0 <= c < c0 + nc
+// (2 nc dividing kDirBlock); gsum: kDirBlock doubles of LDS.
+__device__ __forceinline__ void direction_sums(const RedBuf &red, int ld, int nch, int c0, int nc, double *gsum,
+                                               double *tot) {
+  const int pairs = 2 * nc, gpp = kDirBlock / pairs;
+  const int ngrp = (nch + kPGroup - 1) / kPGroup;
+  const int q = threadIdx.x % pairs, gi = threadIdx.x / pairs;
+  const int t = q / nc, c = c0 + (q - t * nc);
+  const double *src = (t ? red.part1 : red.part0) + c;
+  double acc = 0.0;                             // (threads q < pairs: the running sum)
+  for (int g0 = 0; g0 < ngrp; g0 += gpp) {
+    const int g = g0 + gi;
+    double s = 0.0;
+    if (g < ngrp) {
+      double u[kPGroup];
+#pragma unroll
+      for (int m = 0; m < kPGroup; ++m) {
+        const int ch = g * kPGroup + m;
+        u[m] = ch < nch ? src[(size_t)ch * ld] : 0.0;
+      }
+#pragma unroll
+      for (int h = kPGroup / 2; h >= 1; h /= 2)
+#pragma unroll
+        for (int m = 0; m < h; ++m) u[m] += u[m + h];
+      s = u[0];
+    }
+    __syncthreads();                            // the last pass's sums are consumed
+    gsum[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < pairs)
+      for (int i = 0; i < gpp && g0 + i < ngrp; ++i) acc += gsum[i * pairs + threadIdx.x];
+  }
+  if (threadIdx.x < pairs) tot[t * kMaxLd + c] = acc;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kDirBlock)
 k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
-                     ColState st, int ngrp, int *__restrict__ host_nact, float *__restrict__ p32 = nullptr) {
+                     ColState st, int nch, int *__restrict__ host_nact, float *__restrict__ p32 = nullptr) {
+  __shared__ double gsum[kDirBlock];
+  __shared__ double tot[2 * kMaxLd];
   __shared__ double sbeta[kMaxLd];
   __shared__ int sact[kMaxLd];
-  const int wv = wave_id(), lane = lane_id();
-  const double *gs0 = red.part2, *gs1 = red.part2 + (size_t)ngrp * ld;
-  // wave w: columns 16 w .. 16 w + 15, one lane each (lanes 16.. idle)
-  {
-    const int c = wv * 16 + lane;
-    if (lane < 16 && c < ld) {
-      double rz = 0.0, rr = 0.0;
-      for (int g = 0; g < ngrp; ++g) {
-        rz += gs0[(size_t)g * ld + c];
-        rr += gs1[(size_t)g * ld + c];
-      }
-      const int act0 = st.act_prev[c], brk = st.brk[c];
-      int act = 0;
-      double beta = 0.0;
+  const int cw = min(ld, kDirCols), ncb = ld / cw;
+  const int cb = blockIdx.x % ncb, rr = blockIdx.x / ncb, nrr = gridDim.x / ncb;
+  const bool all = blockIdx.x == 0;
+  const int c0 = all ? 0 : cb * cw, nc = all ? ld : cw;
+  // rows [j0, j1) of column block cb; the first kDirE elements per thread are
+  // loaded before the sums, so that their loads overlap the reduction
+  const int per = (nrows + nrr - 1) / nrr;
+  const int j0 = min(nrows, rr * per), j1 = min(nrows, j0 + per);
+  const int n = (j1 - j0) * cw;
+  auto offset = [&](int i) {
+    const int jr = i / cw;
+    return (size_t)(j0 + jr) * ld + cb * cw + (i - jr * cw);
+  };
+  double zv[kDirE], pv[kDirE];
+#pragma unroll
+  for (int k = 0; k < kDirE; ++k) {
+    const int i = threadIdx.x + k * kDirBlock;
+    zv[k] = pv[k] = 0.0;
+    if (i < n) {
+      const size_t e = offset(i);
+      zv[k] = z[e];
+      pv[k] = p[e];
+    }
+  }
+  direction_sums(red, ld, nch, c0, nc, gsum, tot);
+  if (threadIdx.x < nc) {
+    const int c = c0 + threadIdx.x;
+    const double rz = tot[c], rr2 = tot[kMaxLd + c];
+    const int act0 = st.act_prev[c], brk = st.brk[c];
+    int act = 0;
+    double beta = 0.0;
+    if (act0 && !brk) {
+      beta = rz / st.rz_prev[c];
+      act = rr2 > st.stop2[c] ? 1 : 0;
+    }
+    sbeta[c] = beta;
+    sact[c] = act;
+    if (all) {
+      if (act0 && brk) st.flag[0] = 1;            // breakdown: p^T q <= 0
       if (act0 && !brk) {
-        beta = rz / st.rz_prev[c];
-        act = rr > st.stop2[c] ? 1 : 0;
+        st.iters[c] += 1;
+        st.beta[c] = beta;
+        st.rz[c] = rz;
       }
-      sbeta[c] = beta;
-      sact[c] = act;
-      if (blockIdx.x == 0) {
-        if (act0 && brk) st.flag[0] = 1;          // breakdown: p^T q <= 0
-        if (act0 && !brk) {
-          st.iters[c] += 1;
-          st.beta[c] = beta;
-          st.rz[c] = rz;
-        }
-        st.active[c] = act;
-        st.nrm2[c] = rr;
-      }
+      st.active[c] = act;
+      st.nrm2[c] = rr2;
     }
   }
   __syncthreads();
-  if (blockIdx.x == 0 && wv == 0) {
+  if (all && threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
     int na = lane < ld ? sact[lane] : 0;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
@@ -1716,10 +1828,21 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
       if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
-  const size_t n = (size_t)nrows * ld;
-  for (size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (size_t)gridDim.x * kBlock) {
-    const int c = (int)(e % ld);
+#pragma unroll
+  for (int k = 0; k < kDirE; ++k) {
+    const int i = threadIdx.x + k * kDirBlock;
+    const int c = cb * cw + (i & (cw - 1));
+    if (i < n && sact[c]) {
+      const size_t e = offset(i);
+      const double pn = fma(sbeta[c], pv[k], zv[k]);
+      p[e] = pn;
+      if (p32) p32[e] = (float)pn;
+    }
+  }
+  for (int i = threadIdx.x + kDirE * kDirBlock; i < n; i += kDirBlock) {
+    const int c = cb * cw + (i & (cw - 1));
     if (sact[c]) {
+      const size_t e = offset(i);
       const double pn = fma(sbeta[c], p[e], z[e]);
       p[e] = pn;
       if (p32) p32[e] = (float)pn;

@@ -562,15 +562,19 @@ inline unsigned upd_grid(int n_gamma, int ld) {
   return (ch + w - 1) / w;
 }
 
-// Group sums of the grouped and split update launches (one chunk of kRowsE rows
-// per workgroup, kPGroup workgroups per group).
-inline int split_update_groups(int n_gamma, int ld) {
-  return (int)((upd_grid(n_gamma, ld) + kPGroup - 1) / kPGroup);
+// Workgroups of the direction launch that ends a split update: each reduces
+// the chunk partials of its column block (redundantly), so more of them cost
+// L2 reads and fewer of them leave CUs idle for the direction update.
+constexpr unsigned kDirStateGrid = 256;
+inline unsigned direction_state_grid(int ld) {
+  const unsigned ncb = (unsigned)(ld / std::min(ld, kDirCols));
+  return ncb * std::max(1u, kDirStateGrid / ncb);
 }
 
 // CG update launch; the elements per thread follow from the batch width.
-// red: 0 single-level reduction, 1 grouped, 2 split (mode 1; the direction
-// launch k_cg_direction_state finishes the step, see split_update_groups).
+// red: 0 single-level reduction, 1 grouped, 2 split (mode 1, one chunk per
+// workgroup; the direction launch k_cg_direction_state reduces the chunk
+// partials and finishes the step).
 void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, double *x, double *r,
                    double *z, double *p, const double *q, int precond, int *host_nact,
                    int init_p_is_z, const int *mask, int npq, int red = 0) {
@@ -1294,9 +1298,9 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
                     tl ? nullptr : nact_dst, 0, nullptr, c->gamma_parts, tl ? 2 : 0);
     }
     if (tl) {        // the split update's state and the direction in one launch
-      unsigned gd = std::min(1024u, grid_for((size_t)c->n_gamma * ld, kBlock));
-      hipLaunchKernelGGL(k_cg_direction_state, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld, w.zG,
-                         pA_, c->red, c->st, split_update_groups(c->n_gamma, ld), nact_dst, c->g32.p);
+      hipLaunchKernelGGL(k_cg_direction_state, dim3(direction_state_grid(ld)), dim3(kDirBlock), 0, c->stream,
+                         c->n_gamma, ld, w.zG,
+                         pA_, c->red, c->st, (int)upd_grid(c->n_gamma, ld), nact_dst, c->g32.p);
     } else if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,

@@ -22,6 +22,8 @@
 // a column's result does not depend on the batch width among the widths this
 // path serves; it differs in rounding from the CSR kernels of narrow batches.
 #pragma once
+#include <type_traits>
+
 #include "dd_kernels.h"
 
 namespace dd {
@@ -63,6 +65,13 @@ template <> struct TileA<float> {
     a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
   }
 };
+
+// The same FP32 tile kept in FP32 (operands of v_mfma_f32_16x16x4f32).
+__device__ __forceinline__ void tile_a32(const float *tile, int lane, float (&a)[4]) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = __builtin_nontemporal_load((const v4 *)(tile + 4 * lane));
+  a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+}
 
 // FP64 tiles -> FP32 tiles (the mixed path's copies), layout converted.
 __global__ void k_tiles_to_f32(size_t ntiles, const double *__restrict__ in, float *__restrict__ out) {
@@ -175,6 +184,78 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
   }
 }
 
+// tile_row_acc for FP32 tiles (mixed path) on v_mfma_f32_16x16x4f32: the
+// slice is rounded to FP32, the four steps of an entry accumulate its 16
+// products per output element in FP32, and each entry's sums are added to the
+// FP64 accumulators, so FP32 rounding enters only within one entry.  The
+// accumulators hold rows in the FP32 instruction's order (row 4 (l / 16) + r
+// of lane l, register r).
+template <int NCB, int D, int RB>
+__device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const int *__restrict__ tcol,
+                                                 const float *__restrict__ tval, const double *__restrict__ x,
+                                                 int n, int ld, double sgn, dbl4 (&acc)[RB][NCB]) {
+  const int cnt = t0 < t1 ? (t1 - t0 + st - 1) / st : 0;
+  const int lane = lane_id();
+  const float fs = (float)sgn;
+  for (int base = 0; base < cnt; base += kWave) {
+    const int nb = min(kWave, cnt - base);
+    const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
+    const float *tv = tval + (size_t)(t0 + base * st) * RB * 256;
+    const size_t tstride = (size_t)st * RB * 256;
+    float a[D][RB][4];
+    double xs[D][4][NCB];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int jd = min(d, nb - 1);
+#pragma unroll
+      for (int h = 0; h < RB; ++h) tile_a32(tv + jd * tstride + h * 256, lane, a[d][h]);
+      load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jd), xs[d]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int j = 0; j < nb; j += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        if (j + d < nb) {
+          flt4 c32[RB][NCB];
+#pragma unroll
+          for (int h = 0; h < RB; ++h)
+#pragma unroll
+            for (int q = 0; q < NCB; ++q)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) c32[h][q][r] = 0.0f;
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int q = 0; q < NCB; ++q) {
+              const float xf = fs * (float)xs[d][s][q];        // sgn = +-1: exact
+#pragma unroll
+              for (int h = 0; h < RB; ++h) c32[h][q] = mfma16x16x4(a[d][h][s], xf, c32[h][q]);
+            }
+#pragma unroll
+          for (int h = 0; h < RB; ++h)
+#pragma unroll
+            for (int q = 0; q < NCB; ++q)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[h][q][r] += (double)c32[h][q][r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int jn = min(j + d + D, nb - 1);
+#pragma unroll
+        for (int h = 0; h < RB; ++h) tile_a32(tv + jn * tstride + h * 256, lane, a[d][h]);
+        load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), xs[d]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// Row of a 16-row slice held in accumulator register r of lane group g: the
+// FP64 instruction's order (g + 4 r) or the FP32 one's (4 g + r).
+template <typename VT>
+__device__ __forceinline__ int acc_row(int g, int r) {
+  return std::is_same<VT, float>::value ? 4 * g + r : g + 4 * r;
+}
+
 // Workgroup b runs on XCD b % 8 (round-robin dispatch; each XCD has its own
 // L2).  Workgroup b takes item xcd_item(b, n) so that every XCD works through
 // one contiguous eighth of the items: neighbouring row blocks, which multiply
@@ -227,9 +308,14 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[h][q][r] = 0.0;
   const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
-  if (c1 != 0.0) tile_row_acc<VT, NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
-  if (split && c2 != 0.0)
-    tile_row_acc<VT, NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, (c1 != 0.0 && c2 == -c1) ? -1.0 : 1.0, acc);
+  const double sg2 = (c1 != 0.0 && c2 == -c1) ? -1.0 : 1.0;
+  if constexpr (std::is_same<VT, float>::value) {
+    if (c1 != 0.0) tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
+    if (split && c2 != 0.0) tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
+  } else {
+    if (c1 != 0.0) tile_row_acc<VT, NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
+    if (split && c2 != 0.0) tile_row_acc<VT, NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
+  }
   const double cf = c1 != 0.0 ? c1 : c2;
   __shared__ double part[kTW * H * kT * NCB];    // ld <= 16 NCB
 #pragma unroll
@@ -239,18 +325,18 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
       const int col = NCB * l16 + q;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int lr = h * kT + g + 4 * r;       // row of the block held in register r
+        const int lr = h * kT + acc_row<VT>(g, r);   // row of the block held in register r
         if (col < ld) part[(wv * H + lr) * ld + col] = cf * acc[h][q][r];
       }
     }
   __syncthreads();
   const int nel = H * ld;
   constexpr int NF = kMaxLd * H / (kTW * kWave);
-  double fin[NF];                                // this thread's elements
+  double fin[NF], vo[NF];                        // this thread's elements
 #pragma unroll
   for (int u = 0; u < NF; ++u) {
     const int el = threadIdx.x + u * kTW * kWave;
-    fin[u] = 0.0;
+    fin[u] = vo[u] = 0.0;
     if (el < nel) {
       const int lr = el / ld, col = el - lr * ld, row = rb * H + lr;
       double v = part[el];
@@ -259,12 +345,23 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
       if (row < nrows) {
         const size_t o = (size_t)row * ld + col;
         v += base ? base[o] : 0.0;
-        out[o] = v;
-        fin[u] = DOT ? v * x1[o] : 0.0;
+        vo[u] = v;
+        if (DOT) fin[u] = v * x1[o];
+        else out[o] = v;
       }
     }
   }
   if (!DOT) return;
+  // (the output is stored after this workgroup has counted itself done: the
+  // completion wait before the count then covers the partial only)
+  auto store_out = [&]() {
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int el = threadIdx.x + u * kTW * kWave;
+      const int lr = el / ld, row = rb * H + lr;
+      if (el < nel && row < nrows) out[(size_t)row * ld + (el - lr * ld)] = vo[u];
+    }
+  };
   __syncthreads();                               // every wave read its part: reuse it
 #pragma unroll
   for (int u = 0; u < NF; ++u) {
@@ -282,8 +379,11 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
   const int members = min(kPGroup, (int)gridDim.x - grp * kPGroup);
   __shared__ int lflag;
   unsigned *cnt = red.gcount + (size_t)grp * kCounterStride;
-  if (!last_of(cnt, (unsigned)members, &lflag)) return;
-  group_sums_store(red.part2, gridDim.x, ld, grp, red.part3, wv, kTW);
+  const bool last = last_of(cnt, (unsigned)members, &lflag);
+  store_out();
+  if (!last) return;
+  // (read by the next launch: no completion wait)
+  group_sums_store(red.part2, gridDim.x, ld, grp, red.part3, wv, kTW, false);
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(cnt);
 }
