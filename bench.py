@@ -61,13 +61,13 @@ WORKLOADS = {
 # (sha256 prefix of the file holding the kernel) and the workload named;
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    # 2D constant kernel, 1 rhs: median over the CG iterations' launches
-    "k_gamma_rows<float>": dict(src="dd_kernels.h", sha="c0c496399d23931e", workload="cfg2",
-                                fetch_kib=23326.8, write_kib=221.8,
-                                fetch_scale=262144.0 / 131085.4, write_scale=262144.0 / 262149.4),
-    "k_gamma_rows<double>": dict(src="dd_kernels.h", sha="c0c496399d23931e", workload="cfg2",
-                                 fetch_kib=34253.9, write_kib=221.8,
-                                 fetch_scale=262144.0 / 131085.4, write_scale=262144.0 / 262149.4),
+    # 2D peridynamics h = 1/160, 32 rhs: medians over the CG iterations' launches
+    "k_tile_rows<double,2,true>": dict(src="dd_tiles.h", sha="dceec5e55a4ce359", workload="cfg4",
+                                       fetch_kib=195408.8, write_kib=9624.3,
+                                       fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262150.8),
+    "k_tile_rows<float,2,true>": dict(src="dd_tiles.h", sha="dceec5e55a4ce359", workload="cfg4",
+                                      fetch_kib=101529.9, write_kib=9624.3,
+                                      fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262150.8),
 }
 
 
@@ -103,6 +103,29 @@ def gamma_kernel_bytes(dd, nrhs_pad: int, value_bytes: int, gamma_vectors: int =
     ng = dd.n_gamma
     return (nnz * (value_bytes + 4) + (2 * ng + 1) * 4
             + 8.0 * nrhs_pad * (gamma_vectors * ng + ni))
+
+
+def tile_format_bytes(dd, nrhs_pad: int, value_bytes: int) -> float:
+    """HBM bytes one tiled interface launch streams in its storage format:
+    every entry of [K_GG | K_GI] in blocks of 32 interface rows x 16 columns
+    (two 16x16 tiles per entry, zeros included; K_GI columns numbered by the
+    interiors one subdomain after the other), its int32 column block, the row
+    and split pointers, and the vectors as in gamma_kernel_bytes (p and w
+    read, q written)."""
+    import numpy as np
+    kgg = dd.kgg.tocoo()
+    keys = [np.unique((kgg.row.astype(np.int64) // 32) << 32 | (kgg.col.astype(np.int64) // 16))]
+    off = 0
+    for k, m in enumerate(dd.i_maps):
+        kig = dd.kig[k].tocoo()
+        g = np.asarray(dd.g_maps[k])[kig.col].astype(np.int64)
+        keys.append(np.unique((g // 32) << 32 | ((off + kig.row.astype(np.int64)) // 16) | (1 << 62)))
+        off += len(m)
+    ent = len(np.unique(np.concatenate(keys)))
+    nrb = (dd.n_gamma + 31) // 32
+    ni = sum(len(m) for m in dd.i_maps)
+    return (ent * (2 * 256 * value_bytes + 4) + (2 * nrb + 1) * 4
+            + 8.0 * nrhs_pad * (2 * dd.n_gamma + ni))
 
 
 def iteration_bytes(dd, nrhs_pad: int, value_bytes: int) -> float:
@@ -358,9 +381,15 @@ def path_roofline(dd, wl, solver, bt, prec, opts, tuned, r, ld, workload, steps,
         return None
     avg = ms / launches * 1e-3
     ach = algo / avg / 1e9
-    return dict(bound="hbm", kernel=kname, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(key, workload),
-                algo_bytes_per_launch=algo, avg_launch_us=1e6 * avg, launches=launches, timing=how)
+    out = dict(bound="hbm", kernel=kname, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(key, workload),
+               algo_bytes_per_launch=algo, avg_launch_us=1e6 * avg, launches=launches, timing=how)
+    if tiles:
+        fb = tile_format_bytes(wl.dd, ld, vb)
+        out.update(format_bytes_per_launch=fb, format_gbs=fb / avg / 1e9,
+                   format_note="bytes the 32x16-entry tile format streams (zeros of partly filled "
+                               "tiles included); achieved/frac use the nonzeros only")
+    return out
 
 
 def solve_leg(dd, torch, wl, b, tol, steps, warmup, launch, workload):
