@@ -890,7 +890,9 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
             double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
             double *__restrict__ p, const double *__restrict__ q, RedBuf red, ColState st,
             int use_precond, int *__restrict__ host_nact, int init_p_is_z,
-            const int *__restrict__ mask, int npq, int cpw, float *__restrict__ p32 = nullptr) {
+            const int *__restrict__ mask, int npq, int cpw, float *__restrict__ p32,
+            const int *__restrict__ run) {
+  if (run && *run == 0) return;                       // every column has stopped (see k_tile_rows)
   __shared__ double lds[kRowsE * kMaxLd];
   __shared__ double salpha[kMaxLd];
   __shared__ int sact[kMaxLd];
@@ -1720,7 +1722,10 @@ k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restri
 // rz_prev, act_prev, brk, recorded by the update's workgroup 0; the state is
 // read by no other workgroup of this launch), and publishes (active columns +
 // 1) to host_nact.  ld: a power of two from 8 to kMaxLd; the grid a multiple
-// of ld / min(ld, kDirCols).
+// of ld / min(ld, kDirCols).  run: as in k_tile_rows; it is st.flag + 1,
+// which workgroup 0 of this launch rewrites.  A workgroup that reads the new
+// value 0 has no active column to update either, so either value gives the
+// same result.
 constexpr int kDirCols = 16;       // 128-byte row segments
 constexpr int kDirBlock = 512;
 constexpr int kDirE = 12;          // direction elements per thread held across the reduction
@@ -1763,7 +1768,13 @@ __device__ __forceinline__ void direction_sums(const RedBuf &red, int ld, int nc
 
 __global__ void __launch_bounds__(kDirBlock)
 k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
-                     ColState st, int nch, int *__restrict__ host_nact, float *__restrict__ p32 = nullptr) {
+                     ColState st, int nch, int *__restrict__ host_nact, float *__restrict__ p32,
+                     const int *__restrict__ run) {
+  if (run && *run == 0) {              // every column had stopped: nothing changes, report none active
+    if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
+      __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
   __shared__ double gsum[kDirBlock];
   __shared__ double tot[2 * kMaxLd];
   __shared__ double sbeta[kMaxLd];

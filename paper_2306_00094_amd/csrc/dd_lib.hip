@@ -577,7 +577,7 @@ inline unsigned direction_state_grid(int ld) {
 // partials and finishes the step).
 void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, double *x, double *r,
                    double *z, double *p, const double *q, int precond, int *host_nact,
-                   int init_p_is_z, const int *mask, int npq, int red = 0) {
+                   int init_p_is_z, const int *mask, int npq, int red = 0, const int *run = nullptr) {
   if (c->n_gamma <= 0) return;
   const int cpw = upd_cpw(ld);
   const dim3 g(upd_grid(c->n_gamma, ld)), b(kBlock);
@@ -586,13 +586,13 @@ void launch_update(dd_ctx *c, int mode, int ld, int nrhs, const double *dinv, do
 #define DD_UPD(EE)                                                                                        \
   if (red == 2)                                                                                           \
     hipLaunchKernelGGL((k_cg_update<EE, 2>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,      \
-                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p); \
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p, run); \
   else if (red == 1)                                                                                      \
     hipLaunchKernelGGL((k_cg_update<EE, 1>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,      \
-                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p); \
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p, run); \
   else                                                                                                    \
     hipLaunchKernelGGL((k_cg_update<EE>), g, b, 0, c->stream, mode, c->n_gamma, ld, nrhs, dinv, x,         \
-                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p)
+                       r, z, p, q, c->red, c->st, precond, host_nact, init_p_is_z, mask, npq, cpw, c->g32.p, run)
   switch (E) {
     case 1: DD_UPD(1); break;
     case 2: DD_UPD(2); break;
@@ -694,7 +694,7 @@ void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const doub
 template <typename VT, int NCB, bool DOT>
 void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const double *x1,
                         const double *x2, int ld, const double *base, double c1, double c2,
-                        double *out) {
+                        double *out, const int *run) {
   const int nrb = interface_rows ? c->t_nrbG : c->t_nrbI;
   const int nrows = interface_rows ? c->n_gamma : c->NI;
   if (nrb <= 0) return;
@@ -710,10 +710,10 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   auto launch = [&](auto kern) {
     if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
       hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr, split, col, val, x1,
-                            c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red);
+                            c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red, run);
     else
       hipLaunchKernelGGL(kern, g, b, 0, c->stream, nrb, nrows, ptr, split, col, val, x1, c->n_gamma, x2, n2,
-                         ld, base, c1, c2, out, c->red);
+                         ld, base, c1, c2, out, c->red, run);
   };
   if (interface_rows) launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbG>);
   else launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbI>);
@@ -725,16 +725,16 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
 // accumulator).
 template <bool DOT>
 void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const double *x2, int ld,
-               const double *base, double c1, double c2, double *out) {
+               const double *base, double c1, double c2, double *out, const int *run = nullptr) {
   // FP64 values straight from the setup copies: the FP64 residual of the mixed
   // path runs on contexts whose FP64 operators were never formed
   const void *v = prec == DD_FP64 ? (interface_rows ? (const void *)c->d_tG_val64 : (const void *)c->d_tI_val64)
                                   : (interface_rows ? c->op[prec].tG_val : c->op[prec].tI_val);
 #define DD_TR(NCB)                                                                                     \
   if (prec == DD_FP64)                                                                                 \
-    launch_tile_rows_t<double, NCB, DOT>(c, interface_rows, (const double *)v, x1, x2, ld, base, c1, c2, out); \
+    launch_tile_rows_t<double, NCB, DOT>(c, interface_rows, (const double *)v, x1, x2, ld, base, c1, c2, out, run); \
   else                                                                                                 \
-    launch_tile_rows_t<float, NCB, DOT>(c, interface_rows, (const float *)v, x1, x2, ld, base, c1, c2, out)
+    launch_tile_rows_t<float, NCB, DOT>(c, interface_rows, (const float *)v, x1, x2, ld, base, c1, c2, out, run)
   if (ld <= 16) { DD_TR(1); }
   else if (ld <= 32) { DD_TR(2); }
   else { DD_TR(4); }
@@ -744,12 +744,12 @@ void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const
 // w = base + sign * B y for the dense interior blocks B (kinv of `prec`, or the
 // FP64 blocks K_II themselves when kii is set).
 void dense_tiles(dd_ctx *c, int prec, bool kii, const double *y, int ld, const double *base, double sign,
-                 double *w) {
+                 double *w, const int *run = nullptr) {
   if (c->n_dit <= 0) return;
   const dim3 g(c->n_dit), b(kTW * kWave);
 #define DD_DT(MT, NCB, BLK)                                                                                \
   hipLaunchKernelGGL((k_dense_tiles<MT, NCB>), g, b, 0, c->stream, c->NI, c->d_dit, (const MT *)(BLK),   \
-                     c->d_toff, c->d_ioff, c->d_ni, y, ld, base, sign, w)
+                     c->d_toff, c->d_ioff, c->d_ni, y, ld, base, sign, w, run)
   if (kii || prec == DD_FP64) {
     const void *blk = kii ? (const void *)c->d_kii_t : c->op[DD_FP64].kinv_t;
     if (ld <= 16) DD_DT(double, 1, blk);
@@ -1259,7 +1259,11 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   int observed = 0;       // last iteration whose result the host has seen
   bool stop = c->n_gamma == 0;
   // one CG iteration (S p, alpha, updates, beta); nact_dst receives
-  // (active columns + 1) from the update kernel when non-null
+  // (active columns + 1) from the update kernel when non-null.  The tiled
+  // iteration's launches do nothing once no column iterates (the flag the
+  // last direction launch, or the initialisation, left in st.flag[1]): the
+  // host enqueues up to check_every iterations past the last one needed.
+  const int *run = tl ? c->st.flag + 1 : nullptr;
   auto iteration = [&](double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
     const bool dk = dkv != 0;
@@ -1272,13 +1276,13 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     if (tl) {
       {
         PhaseTimer t(c, DD_PHASE_KIG);
-        tile_rows<false>(c, prec, false, pA_, nullptr, ld, nullptr, 1.0, 0.0, w.yI);
+        tile_rows<false>(c, prec, false, pA_, nullptr, ld, nullptr, 1.0, 0.0, w.yI, run);
       }
       {
         PhaseTimer t(c, DD_PHASE_INTERIOR);
-        dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, w.wI);
+        dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, w.wI, run);
       }
-      tile_rows<true>(c, prec, true, pA_, w.wI, ld, nullptr, 1.0, -1.0, w.qG);
+      tile_rows<true>(c, prec, true, pA_, w.wI, ld, nullptr, 1.0, -1.0, w.qG, run);
     } else {
       {
         PhaseTimer t(c, DD_PHASE_KIG);
@@ -1295,12 +1299,12 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     {
       PhaseTimer t(c, DD_PHASE_UPDATE);
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond,
-                    tl ? nullptr : nact_dst, 0, nullptr, c->gamma_parts, tl ? 2 : 0);
+                    tl ? nullptr : nact_dst, 0, nullptr, c->gamma_parts, tl ? 2 : 0, run);
     }
     if (tl) {        // the split update's state and the direction in one launch
       hipLaunchKernelGGL(k_cg_direction_state, dim3(direction_state_grid(ld)), dim3(kDirBlock), 0, c->stream,
                          c->n_gamma, ld, w.zG,
-                         pA_, c->red, c->st, (int)upd_grid(c->n_gamma, ld), nact_dst, c->g32.p);
+                         pA_, c->red, c->st, (int)upd_grid(c->n_gamma, ld), nact_dst, c->g32.p, run);
     } else if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,

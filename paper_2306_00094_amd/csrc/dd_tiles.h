@@ -286,13 +286,16 @@ constexpr int kTW = 4;
 // writes x1^T out over its rows (rows in order) per column to red.part2, and
 // the last of every kPGroup consecutive workgroups the group sum to red.part3,
 // which the update kernel reduces (the step length of the CG iteration, from
-// p^T S p).
+// p^T S p).  run (may be nullptr): the CG loop's flag of columns still
+// iterating; when it reads 0 the launch does nothing (the loop's host runs a
+// few iterations ahead of the device).
 template <typename VT, int NCB, bool DOT, int D, int RB>
 __global__ void __launch_bounds__(kTW * kWave)
 k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
             const int *__restrict__ tcol, const VT *__restrict__ tval, const double *__restrict__ x1,
             int n1, const double *__restrict__ x2, int n2, int ld, const double *__restrict__ base,
-            double c1, double c2, double *__restrict__ out, RedBuf red) {
+            double c1, double c2, double *__restrict__ out, RedBuf red, const int *__restrict__ run) {
+  if (run && *run == 0) return;                  // every column of the CG loop has stopped
   constexpr int H = RB * kT;                     // rows of a block
   const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const int rb = xcd_item(blockIdx.x, nrb);
@@ -432,7 +435,9 @@ __global__ void __launch_bounds__(kTW * kWave)
 k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ packed,
               const long long *__restrict__ toff, const int *__restrict__ ioff,
               const int *__restrict__ ni, const double *__restrict__ y, int ld,
-              const double *__restrict__ base, double sign, double *__restrict__ w) {
+              const double *__restrict__ base, double sign, double *__restrict__ w,
+              const int *__restrict__ run) {
+  if (run && *run == 0) return;                  // every column of the CG loop has stopped
   const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const int2 item = items[blockIdx.x];
   if (item.x < 0) return;                        // padding of a short XCD list
