@@ -107,24 +107,24 @@ def gamma_kernel_bytes(dd, nrhs_pad: int, value_bytes: int, gamma_vectors: int =
 
 def tile_format_bytes(dd, nrhs_pad: int, value_bytes: int) -> float:
     """HBM bytes one tiled interface launch streams in its storage format:
-    every entry of [K_GG | K_GI] in blocks of 32 interface rows x 16 columns
-    (two 16x16 tiles per entry, zeros included; K_GI columns numbered by the
+    every entry of [K_GG | K_GI] in blocks of 32 interface rows x 8 columns
+    (two 16x8 units per entry, zeros included; K_GI columns numbered by the
     interiors one subdomain after the other), its int32 column block, the row
     and split pointers, and the vectors as in gamma_kernel_bytes (p and w
     read, q written)."""
     import numpy as np
     kgg = dd.kgg.tocoo()
-    keys = [np.unique((kgg.row.astype(np.int64) // 32) << 32 | (kgg.col.astype(np.int64) // 16))]
+    keys = [np.unique((kgg.row.astype(np.int64) // 32) << 32 | (kgg.col.astype(np.int64) // 8))]
     off = 0
     for k, m in enumerate(dd.i_maps):
         kig = dd.kig[k].tocoo()
         g = np.asarray(dd.g_maps[k])[kig.col].astype(np.int64)
-        keys.append(np.unique((g // 32) << 32 | ((off + kig.row.astype(np.int64)) // 16) | (1 << 62)))
+        keys.append(np.unique((g // 32) << 32 | ((off + kig.row.astype(np.int64)) // 8) | (1 << 62)))
         off += len(m)
     ent = len(np.unique(np.concatenate(keys)))
     nrb = (dd.n_gamma + 31) // 32
     ni = sum(len(m) for m in dd.i_maps)
-    return (ent * (2 * 256 * value_bytes + 4) + (2 * nrb + 1) * 4
+    return (ent * (2 * 128 * value_bytes + 4) + (2 * nrb + 1) * 4
             + 8.0 * nrhs_pad * (2 * dd.n_gamma + ni))
 
 
@@ -361,7 +361,7 @@ def path_roofline(dd, wl, solver, bt, prec, opts, tuned, r, ld, workload, steps,
     if tiles:
         ncb = 1 if ld <= 16 else (2 if ld <= 32 else 4)
         key = f"k_tile_rows<{vt},{ncb},true>"
-        kname = key + " (16x16 tiles of [K_GG | K_GI] on MFMA: q = K_GG p - K_GI w, p^T q)"
+        kname = key + " (16x8 units of [K_GG | K_GI] on MFMA: q = K_GG p - K_GI w, p^T q)"
         algo = gamma_kernel_bytes(wl.dd, ld, vb, 2)
     else:
         key = f"k_gamma_rows<{vt}>"
@@ -387,7 +387,7 @@ def path_roofline(dd, wl, solver, bt, prec, opts, tuned, r, ld, workload, steps,
     if tiles:
         fb = tile_format_bytes(wl.dd, ld, vb)
         out.update(format_bytes_per_launch=fb, format_gbs=fb / avg / 1e9,
-                   format_note="bytes the 32x16-entry tile format streams (zeros of partly filled "
+                   format_note="bytes the 32x8-entry unit format streams (zeros of partly filled "
                                "tiles included); achieved/frac use the nonzeros only")
     return out
 

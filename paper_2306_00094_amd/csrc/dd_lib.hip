@@ -43,8 +43,8 @@ struct Ops {
   void *g_val = nullptr;   // [K_GG | K_GI] values (T)
   double *diag = nullptr;  // diag(S)
   double *dinv = nullptr;  // 1 / diag(S)
-  void *tI_val = nullptr;  // 16x16 tiles of K_IG (T), wide batches
-  void *tG_val = nullptr;  // 16x16 tiles of [K_GG | K_GI] (T), wide batches
+  void *tI_val = nullptr;  // 16x8 units of K_IG (T), wide batches
+  void *tG_val = nullptr;  // 16x8 units of [K_GG | K_GI] (T), wide batches
   void *kinv_t = nullptr;  // K_II^{-1} packed into 16x16 tiles (T), wide batches
   bool ready = false;
 };
@@ -100,10 +100,10 @@ struct dd_ctx {
   int *d_ig_ptr = nullptr, *d_ig_col = nullptr;
   int *d_g_ptr = nullptr, *d_g_split = nullptr, *d_g_col = nullptr;
   // wide batches on the matrix cores (built when max_nrhs >= 8 and there are
-  // interiors): 16x16 tiles of K_IG over blocks of kTileRbI x 16 interior rows,
+  // interiors): 16x8 units of K_IG over blocks of kTileRbI x 16 interior rows,
   // of [K_GG | K_GI] over blocks of kTileRbG x 16 interface rows (entries
-  // [ptr, split) multiply p, [split, ptr+1) multiply w; t_nI, t_nG count 16x16
-  // tiles), and the (subdomain, 16-row tile) work items of the interior solve
+  // [ptr, split) multiply p, [split, ptr+1) multiply w; t_nI, t_nG count 16x8
+  // units), and the (subdomain, 16-row tile) work items of the interior solve
   bool tiles = false;
   int t_nrbI = 0, t_nrbG = 0, n_dit = 0;
   size_t t_nI = 0, t_nG = 0;
@@ -293,15 +293,16 @@ dd_status validate(const dd_problem *p) {
   return DD_OK;
 }
 
-// Block CSR of 16x16 tiles over row blocks of RB x 16 rows.  Row i's entries
-// [ptr[i], mid) (columns in [0, ncol1)) go to the first part of its block,
-// entries [mid, ptr[i+1]) (columns in [0, ncol2)) to the second, mid =
-// split[i] (or ptr[i+1] when split is null).  Within a part the column blocks
-// are in increasing order; an entry (row block, column block) holds RB tiles,
-// one per 16-row slice of the block (zero where the slice has no entry), so
-// that one slice of the multiplied vector serves RB tiles.  Values are placed
-// in the A-operand order of the 16x16x4 matrix instructions (dd_tiles.h),
-// zeros elsewhere.  Returns the number of 16x16 tiles (entries x RB).
+// Block CSR of 16x8 units over row blocks of RB x 16 rows and column blocks of
+// kTU = 8 columns.  Row i's entries [ptr[i], mid) (columns in [0, ncol1)) go
+// to the first part of its block, entries [mid, ptr[i+1]) (columns in [0,
+// ncol2)) to the second, mid = split[i] (or ptr[i+1] when split is null).
+// Within a part the column blocks are in increasing order; an entry (row
+// block, column block) holds RB units, one per 16-row slice of the block (zero
+// where the slice has no entry), so that one slice of the multiplied vector
+// serves RB units.  Values are placed in the A-operand order of two steps of
+// the 16x16x4 matrix instructions (UnitLayout in dd_tiles.h), zeros elsewhere.
+// Returns the number of 16x8 units (entries x RB).
 struct TileSet {
   std::vector<int> ptr, split, col;
   std::vector<double> val;
@@ -317,7 +318,7 @@ size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, 
                    int ncol1, int ncol2, int RB, TileSet *ts) {
   const int H = RB * kT;
   const int nrb = (nrows + H - 1) / H;
-  std::vector<int> slot1((ncol1 + kT - 1) / kT + 1, -1), slot2((ncol2 + kT - 1) / kT + 1, -1);
+  std::vector<int> slot1((ncol1 + kTU - 1) / kTU + 1, -1), slot2((ncol2 + kTU - 1) / kTU + 1, -1);
   std::vector<int> cb1, cb2;
   size_t nent = 0;
   if (ts) {
@@ -333,11 +334,11 @@ size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, 
     for (int i = i0; i < i1; ++i) {
       const int mid = split ? split[i] : ptr[i + 1];
       for (int a = ptr[i]; a < mid; ++a) {
-        const int cb = col[a] / kT;
+        const int cb = col[a] / kTU;
         if (slot1[cb] < 0) { slot1[cb] = 0; cb1.push_back(cb); }
       }
       for (int a = mid; a < ptr[i + 1]; ++a) {
-        const int cb = col[a] / kT;
+        const int cb = col[a] / kTU;
         if (slot2[cb] < 0) { slot2[cb] = 0; cb2.push_back(cb); }
       }
     }
@@ -352,15 +353,15 @@ size_t build_tiles(int nrows, const int *ptr, const int *split, const int *col, 
       ts->split[rb] = (int)ts->col.size();
       for (int cb : cb2) ts->col.push_back(cb);
       ts->ptr[rb + 1] = (int)ts->col.size();
-      ts->val.resize(nent * RB * 256, 0.0);
+      ts->val.resize(nent * RB * kUV, 0.0);
       for (int i = i0; i < i1; ++i) {
         const int mid = split ? split[i] : ptr[i + 1];
         const int h = (i - i0) / kT, ii = (i - i0) % kT;
         for (int a = ptr[i]; a < ptr[i + 1]; ++a) {
-          const int t = a < mid ? slot1[col[a] / kT] : slot2[col[a] / kT];
-          const int kk = col[a] % kT;
-          // T[ii][kk] of slice h is held by lane (kk % 4) * 16 + ii at step kk / 4
-          ts->val[((size_t)t * RB + h) * 256 + TileLayout<double>::pos((kk % 4) * kT + ii, kk / 4)] += val[a];
+          const int t = a < mid ? slot1[col[a] / kTU] : slot2[col[a] / kTU];
+          const int kk = col[a] % kTU;
+          // U[ii][kk] of slice h is held by lane (kk % 4) * 16 + ii at step kk / 4
+          ts->val[((size_t)t * RB + h) * kUV + UnitLayout::pos((kk % 4) * kT + ii, kk / 4)] += val[a];
         }
       }
     }
@@ -426,8 +427,8 @@ size_t footprint_bytes(const dd_problem *p, dd_precision prec, int max_nrhs) {
     count_problem_tiles(p, &tI, &tG);
     const size_t nrbI = (NI + kT * kTileRbI - 1) / (kT * kTileRbI),
                  nrbG = (p->n_gamma + kT * kTileRbG - 1) / (kT * kTileRbG);
-    b += (tI + tG) * (4 + 256 * 8) + (nrbI + 1) * 4 + (2 * nrbG + 1) * 4 + NI * 8 / kT + 64;
-    if (prec == DD_MIXED) b += (tI + tG) * 256 * 4;
+    b += (tI + tG) * (4 + kUV * 8) + (nrbI + 1) * 4 + (2 * nrbG + 1) * 4 + NI * 8 / kT + 64;
+    if (prec == DD_MIXED) b += (tI + tG) * kUV * 4;
     size_t kp = 0;                       // packed K_II (FP64) and K_II^{-1} (T)
     for (int k = 0; k < p->n_sub; ++k) {
       const size_t nt = (p->sub[k].n_i + kT - 1) / kT;
@@ -705,8 +706,6 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   const int n2 = interface_rows ? c->NI : 0;
   if (DOT) c->gamma_parts = (int)((g.x + kPGroup - 1) / kPGroup);   // group sums of p^T q
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  // two tiles in flight per wave: three or four measured slower on the
-  // peridynamic 32-column batch (148, 155, 166 us per interface launch)
   auto launch = [&](auto kern) {
     if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
       hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr, split, col, val, x1,
@@ -715,8 +714,12 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
       hipLaunchKernelGGL(kern, g, b, 0, c->stream, nrb, nrows, ptr, split, col, val, x1, c->n_gamma, x2, n2,
                          ld, base, c1, c2, out, c->red, run);
   };
-  if (interface_rows) launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbG>);
-  else launch(k_tile_rows<VT, NCB, DOT, 2, kTileRbI>);
+  // two entries' operands in flight per wave: three or four measured slower on
+  // the peridynamic 32-column batch (FP64 interface launch 78 -> 81 us with
+  // three; FP32 57 us with two or three, 59 with four)
+  constexpr int kDepth = 2;
+  if (interface_rows) launch(k_tile_rows<VT, NCB, DOT, kDepth, kTileRbG>);
+  else launch(k_tile_rows<VT, NCB, DOT, kDepth, kTileRbI>);
 }
 
 // out = base + c1 * (tiled K_IG or K_GG) x1 + c2 * (tiled K_GI) x2 with the
@@ -976,10 +979,10 @@ dd_status factor_impl(dd_ctx *c, int pi) {
     hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, c->stream, c->nnz_g, c->d_g_val64,
                        (float *)o.g_val);
     if (c->tiles) {
-      hipLaunchKernelGGL(k_tiles_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nI, c->d_tI_val64,
-                         (float *)o.tI_val);
-      hipLaunchKernelGGL(k_tiles_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nG, c->d_tG_val64,
-                         (float *)o.tG_val);
+      hipLaunchKernelGGL(k_units_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nI / kTileRbI, kTileRbI,
+                         c->d_tI_val64, (float *)o.tI_val);
+      hipLaunchKernelGGL(k_units_to_f32, dim3(1024), dim3(256), 0, c->stream, c->t_nG / kTileRbG, kTileRbG,
+                         c->d_tG_val64, (float *)o.tG_val);
     }
     HIPCHK(c, hipGetLastError());
   }
@@ -1034,8 +1037,8 @@ dd_status ensure_ops(dd_ctx *c, int pi) {
     TRY(al(&o.ig_val, c->nnz_ig * 4));
     TRY(al(&o.g_val, c->nnz_g * 4));
     if (c->tiles) {
-      TRY(al(&o.tI_val, c->t_nI * 256 * 4));
-      TRY(al(&o.tG_val, c->t_nG * 256 * 4));
+      TRY(al(&o.tI_val, c->t_nI * kUV * 4));
+      TRY(al(&o.tG_val, c->t_nG * kUV * 4));
     }
   }
   return DD_OK;
@@ -1808,7 +1811,7 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     for (TileSet *t : {&ti, &tg})          // uploads need at least one element
       if (t->col.empty()) {
         t->col.push_back(0);
-        t->val.assign((size_t)kTileRbG * 256, 0.0);
+        t->val.assign((size_t)kTileRbG * kUV, 0.0);
       }
     if ((s = upload(c, &c->d_tI_ptr, ti.ptr.data(), ti.ptr.size())) != DD_OK) return bail(s);
     if ((s = upload(c, &c->d_tI_col, ti.col.data(), ti.col.size())) != DD_OK) return bail(s);

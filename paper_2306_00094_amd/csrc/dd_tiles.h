@@ -4,10 +4,14 @@
 // bound by their vector gathers: every nonzero fetches a whole ld-wide slice
 // of the vector it multiplies, so at 32 columns the gathers move about 30
 // times the bytes of the matrix.  Here the coupling matrices are stored as
-// dense 16x16 tiles (block CSR over 16-row blocks) and every tile is applied
-// to a 16-row slice of the multiplied vector by v_mfma_f64_16x16x4f64: a
-// slice is then fetched once per tile instead of once per nonzero, and the
-// matrix bytes stream once per iteration.
+// dense units of 16 rows x 8 columns (block CSR over blocks of 16 or 32 rows
+// and 8 columns: two k-steps of the 16x16x4 matrix instructions) and every
+// unit is applied to an 8-row slice of the multiplied vector by
+// v_mfma_f64_16x16x4f64: a slice is then fetched once per unit instead of
+// once per nonzero, and the matrix bytes stream once per iteration.  (Units 8
+// columns wide leave fewer stored zeros than 16x16 tiles on nonlocal
+// operators: on the peridynamic interface rows 54 % of the values are
+// nonzero against 47 %.)
 //
 // The interior solves w = K_II^-1 y, a dense product per subdomain, use the
 // same instruction on 16x16 tiles of the explicit inverse (FP64), or
@@ -48,39 +52,47 @@ template <> struct TileLayout<float> {
   static __host__ __device__ constexpr int step(int p) { return p & 3; }
 };
 
-// A operand of a streamed coupling tile (nontemporal loads) as doubles.
-template <typename VT> struct TileA;
-template <> struct TileA<double> {
-  typedef double v2 __attribute__((ext_vector_type(2)));
-  static __device__ __forceinline__ void load(const double *tile, int lane, double (&a)[4]) {
-    const v2 u = __builtin_nontemporal_load((const v2 *)(tile + 2 * lane));
-    const v2 v = __builtin_nontemporal_load((const v2 *)(tile + 128 + 2 * lane));
-    a[0] = u[0]; a[1] = u[1]; a[2] = v[0]; a[3] = v[1];
-  }
-};
-template <> struct TileA<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ void load(const float *tile, int lane, double (&a)[4]) {
-    const v4 v = __builtin_nontemporal_load((const v4 *)(tile + 4 * lane));
-    a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
-  }
+// Coupling units: 16 rows x kTU = 8 columns, kUV = 128 values; lane l holds
+// U[l % 16][4 s + l / 16], the A operand of step s (s = 0, 1), at 2 l + s (one
+// 16-byte load per lane in FP64).
+constexpr int kTU = 8, kUV = kT * kTU;
+struct UnitLayout {
+  static __host__ __device__ constexpr int pos(int l, int s) { return 2 * l + s; }
 };
 
-// The same FP32 tile kept in FP32 (operands of v_mfma_f32_16x16x4f32).
-__device__ __forceinline__ void tile_a32(const float *tile, int lane, float (&a)[4]) {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  const v4 v = __builtin_nontemporal_load((const v4 *)(tile + 4 * lane));
-  a[0] = v[0]; a[1] = v[1]; a[2] = v[2]; a[3] = v[3];
+// A operand of a streamed FP64 coupling unit (nontemporal loads).
+__device__ __forceinline__ void unit_a(const double *unit, int lane, double (&a)[2]) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 u = __builtin_nontemporal_load((const v2 *)(unit + 2 * lane));
+  a[0] = u[0];
+  a[1] = u[1];
 }
 
-// FP64 tiles -> FP32 tiles (the mixed path's copies), layout converted.
-__global__ void k_tiles_to_f32(size_t ntiles, const double *__restrict__ in, float *__restrict__ out) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < ntiles * 256;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const size_t t = e / 256;
-    const int p = (int)(e % 256);
-    const int l = TileLayout<float>::lane(p), s = TileLayout<float>::step(p);
-    out[e] = (float)in[t * 256 + TileLayout<double>::pos(l, s)];
+// FP32 copies (mixed path) interleave the RB units of an entry per lane --
+// lane l holds slice h, step s at RB (2 l) + 2 h + s -- so that a lane loads
+// its operands of a two-slice entry with one 16-byte load, as the FP64 units
+// do per slice.
+template <int RB>
+__device__ __forceinline__ void entry_a32(const float *entry, int lane, float (&a)[RB][2]) {
+  typedef float vt __attribute__((ext_vector_type(2 * RB)));
+  const vt u = __builtin_nontemporal_load((const vt *)(entry + 2 * RB * lane));
+#pragma unroll
+  for (int h = 0; h < RB; ++h) {
+    a[h][0] = u[2 * h];
+    a[h][1] = u[2 * h + 1];
+  }
+}
+
+// FP64 units (entries of RB units, UnitLayout each) -> the interleaved FP32
+// copies read by entry_a32.
+__global__ void k_units_to_f32(size_t nent, int RB, const double *__restrict__ in, float *__restrict__ out) {
+  const size_t per = (size_t)RB * kUV;
+  for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < nent * per;
+       o += (size_t)gridDim.x * blockDim.x) {
+    const size_t t = o / per;
+    const int r = (int)(o - t * per);
+    const int l = r / (2 * RB), h = (r >> 1) % RB, st = r & 1;
+    out[o] = (float)in[(t * RB + h) * kUV + UnitLayout::pos(l, st)];
   }
 }
 
@@ -107,58 +119,50 @@ __device__ __forceinline__ void slice_row(const double *__restrict__ p, double (
   }
 }
 
-// One 16-row slice of x (rows cb*16 .. cb*16+15, DD layout with leading
-// dimension ld) in the B-operand order: lane l takes row cb*16 + 4 s + l/16 for
+// One 8-row slice of x (rows cb*8 .. cb*8+7, DD layout with leading
+// dimension ld) in the B-operand order: lane l takes row cb*8 + 4 s + l/16 for
 // step s, its columns as above.  Rows past the last row n - 1 read row n - 1
-// (the tile entries they meet are zero).  The loads are unconditional, so the
+// (the unit entries they meet are zero).  The loads are unconditional, so the
 // compiler can count them when it waits for a buffer.
 template <int NCB>
 __device__ __forceinline__ void load_slice(const double *__restrict__ x, int n, int ld, int cb,
-                                           double (&xv)[4][NCB]) {
+                                           double (&xv)[2][NCB]) {
   const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const double *p = x + slice_col0<NCB>(l16, ld);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int row = min(cb * kT + 4 * s + g, n - 1);
+  for (int s = 0; s < 2; ++s) {
+    const int row = min(cb * kTU + 4 * s + g, n - 1);
     slice_row<NCB>(p + (size_t)row * ld, xv[s]);
   }
 }
 
-template <int NCB>
-__device__ __forceinline__ void tile_mma(const double (&a)[4], const double (&xv)[4][NCB], dbl4 (&acc)[NCB]) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
-    for (int q = 0; q < NCB; ++q) acc[q] = mfma16x16x4(a[s], xv[s][q], acc[q]);
-}
-
-// acc[h][q] += T_h * X over the entries t0, t0 + st, t0 + 2 st, ... (< t1) of
+// acc[h][q] += U_h * X over the entries t0, t0 + st, t0 + 2 st, ... (< t1) of
 // one row block, in that order (t0, t1, st uniform over the wave); entry t holds
-// the RB tiles T_h (16-row slice h of the block) at tval + (t RB + h) 256, all
-// multiplying the same 16-row slice of x, which is loaded once.  The entries'
+// the RB units U_h (16-row slice h of the block) at tval + (t RB + h) kUV, all
+// multiplying the same 8-row slice of x, which is loaded once.  The entries'
 // column blocks are fetched 64 at a time, one per lane, and broadcast by
 // readlane; D register buffers hold the operands of the next D entries while an
 // entry's instructions run (the last loads of a wave repeat its last entry and
 // are not used).  Scheduling barriers keep every group of loads in program
 // order, so that the instructions of one buffer wait only for that buffer's
 // loads, the other buffers' staying in flight.
-template <typename VT, int NCB, int D, int RB>
+template <int NCB, int D, int RB>
 __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *__restrict__ tcol,
-                                             const VT *__restrict__ tval, const double *__restrict__ x,
+                                             const double *__restrict__ tval, const double *__restrict__ x,
                                              int n, int ld, double sgn, dbl4 (&acc)[RB][NCB]) {
   const int cnt = t0 < t1 ? (t1 - t0 + st - 1) / st : 0;
   const int lane = lane_id();
   for (int base = 0; base < cnt; base += kWave) {
     const int nb = min(kWave, cnt - base);
     const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
-    const VT *tv = tval + (size_t)(t0 + base * st) * RB * 256;
-    const size_t tstride = (size_t)st * RB * 256;
-    double a[D][RB][4], xs[D][4][NCB];
+    const double *tv = tval + (size_t)(t0 + base * st) * RB * kUV;
+    const size_t tstride = (size_t)st * RB * kUV;
+    double a[D][RB][2], xs[D][2][NCB];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int jd = min(d, nb - 1);
 #pragma unroll
-      for (int h = 0; h < RB; ++h) TileA<VT>::load(tv + jd * tstride + h * 256, lane, a[d][h]);
+      for (int h = 0; h < RB; ++h) unit_a(tv + jd * tstride + h * kUV, lane, a[d][h]);
       load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jd), xs[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -167,16 +171,20 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
       for (int d = 0; d < D; ++d) {
         if (j + d < nb) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s)              // sgn = +-1: exact
+          for (int s = 0; s < 2; ++s)              // sgn = +-1: exact
 #pragma unroll
             for (int q = 0; q < NCB; ++q) xs[d][s][q] *= sgn;
 #pragma unroll
-          for (int h = 0; h < RB; ++h) tile_mma<NCB>(a[d][h], xs[d], acc[h]);
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int h = 0; h < RB; ++h)
+#pragma unroll
+              for (int q = 0; q < NCB; ++q) acc[h][q] = mfma16x16x4(a[d][h][s], xs[d][s][q], acc[h][q]);
         }
         __builtin_amdgcn_sched_barrier(0);
         const int jn = min(j + d + D, nb - 1);
 #pragma unroll
-        for (int h = 0; h < RB; ++h) TileA<VT>::load(tv + jn * tstride + h * 256, lane, a[d][h]);
+        for (int h = 0; h < RB; ++h) unit_a(tv + jn * tstride + h * kUV, lane, a[d][h]);
         load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), xs[d]);
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -184,12 +192,12 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
   }
 }
 
-// tile_row_acc for FP32 tiles (mixed path) on v_mfma_f32_16x16x4f32: the
-// slice is rounded to FP32, the four steps of an entry accumulate its 16
-// products per output element in FP32, and each entry's sums are added to the
-// FP64 accumulators, so FP32 rounding enters only within one entry.  The
-// accumulators hold rows in the FP32 instruction's order (row 4 (l / 16) + r
-// of lane l, register r).
+// tile_row_acc for FP32 units (mixed path, entries interleaved as read by
+// entry_a32) on v_mfma_f32_16x16x4f32: the slice is rounded to FP32, the two
+// steps of an entry accumulate its 8 products per output element in FP32, and
+// each entry's sums are added to the FP64 accumulators, so FP32 rounding
+// enters only within one entry.  The accumulators hold rows in the FP32
+// instruction's order (row 4 (l / 16) + r of lane l, register r).
 template <int NCB, int D, int RB>
 __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const int *__restrict__ tcol,
                                                  const float *__restrict__ tval, const double *__restrict__ x,
@@ -200,15 +208,14 @@ __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const i
   for (int base = 0; base < cnt; base += kWave) {
     const int nb = min(kWave, cnt - base);
     const int mycol = lane < nb ? tcol[t0 + (base + lane) * st] : 0;
-    const float *tv = tval + (size_t)(t0 + base * st) * RB * 256;
-    const size_t tstride = (size_t)st * RB * 256;
-    float a[D][RB][4];
-    double xs[D][4][NCB];
+    const float *tv = tval + (size_t)(t0 + base * st) * RB * kUV;
+    const size_t tstride = (size_t)st * RB * kUV;
+    float a[D][RB][2];
+    double xs[D][2][NCB];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int jd = min(d, nb - 1);
-#pragma unroll
-      for (int h = 0; h < RB; ++h) tile_a32(tv + jd * tstride + h * 256, lane, a[d][h]);
+      entry_a32<RB>(tv + jd * tstride, lane, a[d]);
       load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jd), xs[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -224,7 +231,7 @@ __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const i
 #pragma unroll
               for (int r = 0; r < 4; ++r) c32[h][q][r] = 0.0f;
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
+          for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int q = 0; q < NCB; ++q) {
               const float xf = fs * (float)xs[d][s][q];        // sgn = +-1: exact
@@ -240,8 +247,7 @@ __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const i
         }
         __builtin_amdgcn_sched_barrier(0);
         const int jn = min(j + d + D, nb - 1);
-#pragma unroll
-        for (int h = 0; h < RB; ++h) tile_a32(tv + jn * tstride + h * 256, lane, a[d][h]);
+        entry_a32<RB>(tv + jn * tstride, lane, a[d]);
         load_slice<NCB>(x, n, ld, __builtin_amdgcn_readlane(mycol, jn), xs[d]);
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -316,8 +322,8 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
     if (c1 != 0.0) tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
     if (split && c2 != 0.0) tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
   } else {
-    if (c1 != 0.0) tile_row_acc<VT, NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
-    if (split && c2 != 0.0) tile_row_acc<VT, NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
+    if (c1 != 0.0) tile_row_acc<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
+    if (split && c2 != 0.0) tile_row_acc<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
   }
   const double cf = c1 != 0.0 ? c1 : c2;
   __shared__ double part[kTW * H * kT * NCB];    // ld <= 16 NCB
