@@ -13,10 +13,11 @@ subdomains from jittered cuts (+-30 % widths), 32 seeded right-hand sides in
 one batch, relative residual 1e-9 (the largest tolerance at which every
 column stays within 1e-8 relative error of the monolithic FP64 solution).
 
-Prints ONE JSON line.  `value` is the mixed-precision path's solves/s (right-
-hand-side columns solved per second); the FP64 path is reported beside it
-under "fp64", each with its largest per-solve error against the oracle's
-monolithic solution (computed in the CPU-baseline leg).
+Prints ONE JSON line.  `value` is the solves/s (right-hand-side columns
+solved per second) of the faster of the two paths, mixed precision or plain
+FP64 (named in config.path); both are reported under "mixed" and "fp64", each
+with its largest per-solve error against the oracle's monolithic solution
+(computed in the CPU-baseline leg).
 """
 from __future__ import annotations
 
@@ -62,12 +63,12 @@ WORKLOADS = {
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
     # 2D peridynamics h = 1/160, 32 rhs: medians over the CG iterations' launches
-    "k_tile_rows<double,2,true>": dict(src="dd_tiles.h", sha="dceec5e55a4ce359", workload="cfg4",
-                                       fetch_kib=195408.8, write_kib=9624.3,
-                                       fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262150.8),
-    "k_tile_rows<float,2,true>": dict(src="dd_tiles.h", sha="dceec5e55a4ce359", workload="cfg4",
-                                      fetch_kib=101529.9, write_kib=9624.3,
-                                      fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262150.8),
+    "k_tile_rows<double,2,true>": dict(src="dd_tiles.h", sha="e563bf29598e3106", workload="cfg4",
+                                       fetch_kib=159886.3, write_kib=9624.3,
+                                       fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262148.2),
+    "k_tile_rows<float,2,true>": dict(src="dd_tiles.h", sha="e563bf29598e3106", workload="cfg4",
+                                      fetch_kib=84672.4, write_kib=9624.3,
+                                      fetch_scale=262144.0 / 131087.1, write_scale=262144.0 / 262148.2),
 }
 
 
@@ -700,32 +701,37 @@ def main():
             head[name]["error_vs_oracle"] = solve_errors(sols[name], uref)
     del sols
 
+    # the headline is the faster of the two paths (both meet the same residual
+    # and error gates); the other is reported beside it
+    best = "mixed" if mixed["value"] >= fp64["value"] else "fp64"
+    other = "fp64" if best == "mixed" else "mixed"
+    top = head[best]
     line = {
         "metric": METRIC,
-        "value": mixed["value"],
+        "value": top["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": mixed["ms_per_step"],
+        "ms_per_step": top["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if best == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["desc"], "name": args.workload, "rel_resid": tol,
+        "config": {"workload": cfg["desc"], "name": args.workload, "path": best, "rel_resid": tol,
                    "rel_resid_note": "tighter than the metric's 1e-8 so that every column stays within "
                                      "1e-8 relative error of the oracle's monolithic solution",
                    "nrhs": nrhs, "n_dof": wl.dd.n_dof, "n_gamma": wl.dd.n_gamma,
                    "subdomains": wl.dd.n_sub},
-        "p50_ms": mixed["p50_ms"],
-        "p99_ms": mixed["p99_ms"],
+        "p50_ms": top["p50_ms"],
+        "p99_ms": top["p99_ms"],
         "latency_note": "per batch solve (all nrhs columns), host clock from call to return",
         "mixed": mixed,
         "fp64": fp64,
         "mixed_vs_fp64": head["mixed_vs_fp64"],
         "error_vs_oracle": {k: head[k].get("error_vs_oracle") for k in ("mixed", "fp64")},
-        "roofline": dict(mixed["roofline"] or {}, fp64=fp64["roofline"]),
+        "roofline": dict(top["roofline"] or {}, **{other: head[other]["roofline"]}),
         "paper_context": "14.6x FETI vs Jacobi-CG solve time, fractional kernel, 48x48 subdomains, "
                          "16M dofs, 2304 Broadwell ranks (different method and machine)",
     }
