@@ -369,9 +369,10 @@ def path_roofline(dd, wl, solver, bt, prec, opts, tuned, r, ld, workload, steps,
         kname = key + " (CSR rows of [K_GG | K_GI]: q = K_GG p - K_GI w)"
         algo = gamma_kernel_bytes(wl.dd, ld, vb)
     how = f"events on every {TIMING_EVERY}th solve of the timed region"
-    if r["gamma_launches"] > 0:
+    graph = tuned.get("launch") == dd.DD_LAUNCH_GRAPH
+    if r["gamma_launches"] > 0 and not graph:
         ms, launches = r["gamma_ms"], r["gamma_launches"]
-    else:
+    else:                 # (a graph schedule times only the launches outside its replays)
         o2 = dd.dd_default_opts(tol=opts.tol, launch=dd.DD_LAUNCH_KERNELS, apply=dd.DD_APPLY_INV,
                                 tiles=1 if tiles else 0)
         r2 = time_path(solver, dd, bt, prec, o2, max(3, steps // 4), 1, torch, timing_every=1)
