@@ -1714,15 +1714,16 @@ k_cg_direction(int nrows, int ld, const double *__restrict__ z, double *__restri
 // one fixed order -- group sums over kPGroup consecutive chunks by the tree of
 // chunk_group_sum (one thread per column, dot and group, the butterfly's pairs
 // added in registers), then the groups in order -- which gives the bits of the
-// grouped update's two levels.  Workgroup b updates the direction
-// p = z + beta p of the still iterating columns for column block b % ncb
+// grouped update's two levels.  Workgroup b >= 1 updates the direction
+// p = z + beta p of the still iterating columns for column block (b - 1) % ncb
 // (kDirCols columns, or ld when narrower) over its share of the rows, and
 // reduces the sums of that block only; workgroup 0 reduces every column and
 // writes the column state (from the sums and the state the step started from:
 // rz_prev, act_prev, brk, recorded by the update's workgroup 0; the state is
 // read by no other workgroup of this launch), and publishes (active columns +
-// 1) to host_nact.  ld: a power of two from 8 to kMaxLd; the grid a multiple
-// of ld / min(ld, kDirCols).  run: as in k_tile_rows; it is st.flag + 1,
+// 1) to host_nact; it updates no rows, so its longer reduction runs beside
+// the others' row work.  ld: a power of two from 8 to kMaxLd; the grid 1 plus
+// a multiple of ld / min(ld, kDirCols).  run: as in k_tile_rows; it is st.flag + 1,
 // which workgroup 0 of this launch rewrites.  A workgroup that reads the new
 // value 0 has no active column to update either, so either value gives the
 // same result.
@@ -1780,14 +1781,17 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
   __shared__ double sbeta[kMaxLd];
   __shared__ int sact[kMaxLd];
   const int cw = min(ld, kDirCols), ncb = ld / cw;
-  const int cb = blockIdx.x % ncb, rr = blockIdx.x / ncb, nrr = gridDim.x / ncb;
+  // workgroup 0: every column's sums and state, no direction rows; workgroup
+  // b >= 1: column block (b - 1) % ncb over row share (b - 1) / ncb
   const bool all = blockIdx.x == 0;
+  const int wb = all ? 0 : (int)blockIdx.x - 1;
+  const int cb = wb % ncb, rr = wb / ncb, nrr = ((int)gridDim.x - 1) / ncb;
   const int c0 = all ? 0 : cb * cw, nc = all ? ld : cw;
   // rows [j0, j1) of column block cb; the first kDirE elements per thread are
   // loaded before the sums, so that their loads overlap the reduction
   const int per = (nrows + nrr - 1) / nrr;
   const int j0 = min(nrows, rr * per), j1 = min(nrows, j0 + per);
-  const int n = (j1 - j0) * cw;
+  const int n = all ? 0 : (j1 - j0) * cw;
   auto offset = [&](int i) {
     const int jr = i / cw;
     return (size_t)(j0 + jr) * ld + cb * cw + (i - jr * cw);

@@ -565,11 +565,14 @@ inline unsigned upd_grid(int n_gamma, int ld) {
 
 // Workgroups of the direction launch that ends a split update: each reduces
 // the chunk partials of its column block (redundantly), so more of them cost
-// L2 reads and fewer of them leave CUs idle for the direction update.
+// L2 reads and fewer of them leave CUs idle for the direction update.  (Its
+// 512-thread workgroups run one per CU.)
 constexpr unsigned kDirStateGrid = 256;
 inline unsigned direction_state_grid(int ld) {
   const unsigned ncb = (unsigned)(ld / std::min(ld, kDirCols));
-  return ncb * std::max(1u, kDirStateGrid / ncb);
+  // workgroup 0 (the column state) and the row workgroups together fill at
+  // most one workgroup per CU: one more would wait for a second round
+  return 1 + ncb * std::max(1u, (kDirStateGrid - 1) / ncb);
 }
 
 // CG update launch; the elements per thread follow from the batch width.

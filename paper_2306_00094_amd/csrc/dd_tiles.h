@@ -318,6 +318,18 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
       for (int r = 0; r < 4; ++r) acc[h][q][r] = 0.0;
   const int b = ptr[rb], e = ptr[rb + 1], s = split ? split[rb] : e;
   const double sg2 = (c1 != 0.0 && c2 == -c1) ? -1.0 : 1.0;
+  const int nel = H * ld;
+  constexpr int NF = kMaxLd * H / (kTW * kWave);
+  // this thread's output elements; with DOT, their x1 values are loaded now, so
+  // that the loads are done when the block's sums are (the dot product then
+  // costs no memory round trip after the product)
+  double xd[NF];
+#pragma unroll
+  for (int u = 0; u < NF; ++u) {
+    const int el = threadIdx.x + u * kTW * kWave;
+    const int lr = el / ld, row = rb * H + lr;
+    xd[u] = (DOT && el < nel && row < nrows) ? x1[(size_t)row * ld + (el - lr * ld)] : 0.0;
+  }
   if constexpr (std::is_same<VT, float>::value) {
     if (c1 != 0.0) tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
     if (split && c2 != 0.0) tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
@@ -339,9 +351,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
       }
     }
   __syncthreads();
-  const int nel = H * ld;
-  constexpr int NF = kMaxLd * H / (kTW * kWave);
-  double fin[NF], vo[NF];                        // this thread's elements
+  double fin[NF], vo[NF];
 #pragma unroll
   for (int u = 0; u < NF; ++u) {
     const int el = threadIdx.x + u * kTW * kWave;
@@ -355,7 +365,7 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
         const size_t o = (size_t)row * ld + col;
         v += base ? base[o] : 0.0;
         vo[u] = v;
-        if (DOT) fin[u] = v * x1[o];
+        if (DOT) fin[u] = v * xd[u];
         else out[o] = v;
       }
     }
