@@ -353,9 +353,12 @@ void dd_destroy(dd_ctx *ctx);
  *   a dense window of (2R+1)^2 doubles (4 (2R+1)^2 for kernel 2) for nodes
  *   (a+da, b+db), |da|, |db| <= R, at (db+R)(2R+1) + (da+R) (kernel 2:
  *   [row component][window][column component]).  Collar nodes are included.
- * R >= ceil(delta n) + 2; the window of one row must fit in 64 KiB.
- * Launched on hip_stream; returns without waiting.  The last bits of an
- * entry may vary between runs (window entries are summed with atomics).
+ * ceil(delta n) + 2 <= R <= 63.  The kernel keeps four copies of the nodes
+ * of one row's window within distance delta n + 1.5 (node units) of its node
+ * (the only ones the row reaches; three values each for kernel 2), which
+ * must fit in 64 KiB: about delta n <= 23 (kernel 2: 13).
+ * Launched on hip_stream; returns without waiting.  Every entry is summed in
+ * a fixed order: the same arguments give the same bits on every run.
  * Errors: DD_EINVAL (message from dd_last_error(NULL)), DD_EHIP. */
 dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel, double phi,
                          double s, int32_t R, double *win_dev, void *hip_stream);

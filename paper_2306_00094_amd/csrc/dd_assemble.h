@@ -27,12 +27,20 @@
 // |da|, |db| <= R, at (db + R)(2R + 1) + (da + R); for the peridynamic kernel
 // each entry is a 2x2 block stored [row component][window][column component].
 //
-// One workgroup per row: the window accumulates in LDS; the threads take the
-// (E, F) candidates of the row in a fixed stride and integrate each pair into
-// registers.  The shares of F's vertices go to the window with LDS atomics;
-// those of E's three vertices, which every pair of E touches, are summed in
-// registers first.  The summation order -- and the last bits -- vary between
-// runs.
+// One workgroup per row.  The partner triangles F of the search squares of
+// the elements E holding the row's node are spread over the threads in a
+// fixed stride; each thread integrates its pair into registers.  Every sum
+// has a fixed order, so the windows are the same bits from run to run:
+//  - each wave accumulates into its own copy of the window in LDS.  In one
+//    step of a wave its lanes hold consecutive triangles of at most two
+//    squares; within one square and one triangle type (lower right / upper
+//    left) the cells differ, and so does the node at any given vertex index.
+//    The shares of F's vertices outside E are added in twelve steps (square,
+//    type, vertex index) without two lanes touching one entry;
+//  - the shares of E's three vertices, which every pair of E touches, are
+//    summed per thread (one register set for even, one for odd elements),
+//    then over the wave by a fixed butterfly once the wave has passed E;
+//  - the copies are added in wave order when the window is stored.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,13 +52,41 @@ namespace dd {
 constexpr int kAsmBlock = 256;
 constexpr int kKerConst = 0, kKerFrac = 1, kKerPD = 2;
 
+constexpr int kAsmMaxW = 128;   // widest window (2R + 1) a launch takes
+
 struct AsmProblem {
   int n, c, N;         // cells per side, collar cells, N = n + 2c
   int R, W, R1;        // window half width, 2R + 1, partner search radius in cells
   int kernel;
   double h, phi, s;
   long long thr;       // barycentre test: squared distance in (h/3)^2 units <= thr
+  // Nodes a row can reach: (da, db) with da^2 + db^2 <= rr (node units).  In
+  // LDS the window keeps only those, row db + R from disk[db + R] - L(db) to
+  // disk[db + R] + L(db), L(db) the largest |da| in the row (asm_disk).
+  long long rr;
+  int WC;              // nodes kept
+  int disk[kAsmMaxW];
 };
+
+// The reachable disk of the window (host).  A partner F of an element E
+// holding the node m passes the barycentre test when its barycentre is
+// within delta of E's; a vertex of a right triangle with legs h lies within
+// sqrt(5)/3 h of the barycentre, so every vertex of F is within
+// delta + 2 sqrt(5)/3 h < delta + 1.5 h of m.
+inline void asm_disk(AsmProblem &P, double delta) {
+  const double rho = delta / P.h + 1.5;
+  P.rr = (long long)std::ceil(rho * rho);
+  int acc = 0;
+  for (int db = -P.R; db <= P.R; ++db) {
+    P.disk[db + P.R] = acc;                // (a row out of reach keeps no node)
+    if ((long long)db * db > P.rr) continue;
+    int L = 0;
+    while (L < P.R && (long long)(L + 1) * (L + 1) + (long long)db * db <= P.rr) ++L;
+    P.disk[db + P.R] = acc + L;
+    acc += 2 * L + 1;
+  }
+  P.WC = acc;
+}
 
 // Quadrature rules on the reference triangle: barycentric points and weights
 // (summing to 1), {l0, l1, l2, w} per point; rows 0-6 the 7-point rule,
@@ -159,7 +195,7 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
       for (int u = 0; u < 6; ++u) {
         if (u >= nu) break;
         const double dn = u < 3 ? au[u] - lx[u < 3 ? u : 0] : au[u];
-        if constexpr (KER == kKerPD) {     // (the [1][0] entry is copied from [0][1] at the end)
+        if constexpr (KER == kKerPD) {     // ([1][0] equals [0][1]: the window copies it)
           acc[4 * u + 0] += dn * b00;
           acc[4 * u + 1] += dn * b01;
           acc[4 * u + 3] += dn * b11;
@@ -169,24 +205,39 @@ __device__ __forceinline__ void asm_pair(const AsmProblem &P, const double Ex[3]
       }
     }
   }
-  if constexpr (KER == kKerPD) {
-#pragma unroll
-    for (int u = 0; u < 6; ++u) acc[4 * u + 2] = acc[4 * u + 1];
-  }
 }
 
+// Window entries per node pair (NC) and distinct values among them (NV: the
+// peridynamic 2x2 block is symmetric, [1][0] equals [0][1]); a workgroup
+// holds kAsmWaves copies of NV values per reachable node in LDS.
+constexpr int kAsmWaves = kAsmBlock / 64;
+// Per kernel, measured on the benchmark systems (h = 1/128, 1/96, 1/160):
+// kPad lays each element's candidates out in multiples of 64, so that a wave
+// step stays in one element and its data is uniform over the wave (fewer
+// registers, some idle lanes); kWaves is the occupancy the register
+// allocation must allow (three for the fractional and peridynamic kernels,
+// at the price of a few spilled registers, beats two).
+template <int KER> struct AsmShape {
+  static constexpr int NC = KER == kKerPD ? 4 : 1;
+  static constexpr int NV = KER == kKerPD ? 3 : 1;
+  static constexpr bool kPad = KER != kKerFrac;
+  static constexpr int kWaves = KER == kKerConst ? 1 : 3;
+};
+
 // One workgroup per free node: its window, accumulated in LDS (dynamic size
-// W^2 or 4 W^2 doubles), then stored.
+// kAsmWaves * NV * WC doubles), then stored (zeros outside the disk).
 template <int KER>
-__global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double *__restrict__ win) {
+__global__ void __launch_bounds__(kAsmBlock, AsmShape<KER>::kWaves) k_assemble_2d(AsmProblem P, double *__restrict__ win) {
+  constexpr int NC = AsmShape<KER>::NC, NV = AsmShape<KER>::NV;
   extern __shared__ double sw[];
   __shared__ int se[6][2][3];       // elements holding the node: vertex coordinates
   __shared__ int nE;
-  constexpr int NC = KER == kKerPD ? 4 : 1;
-  const int WW = P.W * P.W * NC;
+  __shared__ int disk[kAsmMaxW];
+  const int W2 = P.W * P.W, WV = P.WC * NV;
   const int row = blockIdx.x;
   const int ma = P.c + 1 + row % (P.n - 1), mb = P.c + 1 + row / (P.n - 1);
-  for (int i = threadIdx.x; i < WW; i += kAsmBlock) sw[i] = 0.0;
+  for (int i = threadIdx.x; i < kAsmWaves * WV; i += kAsmBlock) sw[i] = 0.0;
+  if (threadIdx.x < P.W) disk[threadIdx.x] = P.disk[threadIdx.x];
   if (threadIdx.x == 0) {
     int k = 0;
     for (int ca = ma - 1; ca <= ma; ++ca)
@@ -209,48 +260,70 @@ __global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double 
   __syncthreads();
   const int span = 2 * P.R1 + 1;
   const int per_e = span * span * 2;            // partner candidates of one element
-  const int items = nE * per_e;
+  // Candidates per element as laid out over the steps: at least 64, so that
+  // one wave step spans at most two elements; padded, a multiple of 64, so
+  // that it spans one.
+  constexpr bool kPad = AsmShape<KER>::kPad;
+  const int per_p = kPad ? (per_e + 63) & ~63 : (per_e >= 64 ? per_e : 64);
+  const int items = nE * per_p;
   const double off = P.c * P.h;
-  // E's three vertices receive a share of every pair: their sums stay in
-  // registers while this thread's items belong to the same E (ecur) and go
-  // to the window when it changes (LDS atomics on those few entries would
-  // serialise)
-  const int W2 = P.W * P.W;
-  auto add = [&](int a, int b, const double *v) {
-    const int wi = (b - mb + P.R) * P.W + (a - ma + P.R);
-    if constexpr (KER == kKerPD) {
-      atomicAdd(&sw[(0 * W2 + wi) * 2 + 0], v[0]);
-      atomicAdd(&sw[(0 * W2 + wi) * 2 + 1], v[1]);
-      atomicAdd(&sw[(1 * W2 + wi) * 2 + 0], v[2]);
-      atomicAdd(&sw[(1 * W2 + wi) * 2 + 1], v[3]);
-    } else {
-      atomicAdd(&sw[wi], v[0]);
+  const int lane = threadIdx.x & 63;
+  double *mine = sw + (threadIdx.x >> 6) * WV;  // this wave's copy
+  constexpr int comp[3] = {0, 1, 3};            // acc's [0][0], [0][1], [1][1] of a 2x2 block
+  // shares of the vertices of E, per thread, for the elements of even and odd index
+  double es[2][3 * NV];
+  for (int k = 0; k < 3 * NV; ++k) es[0][k] = es[1][k] = 0.0;
+  // element k's sums: butterfly over the wave, then lane 0 adds to the copy
+  auto flush = [&](int k) {
+    const int par = kPad ? 0 : k & 1;
+#pragma unroll
+    for (int q = 0; q < 3 * NV; ++q) {
+      double v = par ? es[1][q] : es[0][q];
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) {
+        const int j = q / NV, c = q - j * NV;
+        const int wi = disk[se[k][1][j] - mb + P.R] + (se[k][0][j] - ma);   // (neighbours of m)
+        atomicAdd(&mine[wi * NV + c], v);
+      }
+      if (par) es[1][q] = 0.0;
+      else es[0][q] = 0.0;
     }
   };
-  double esum[3 * NC];
-  for (int j = 0; j < 3 * NC; ++j) esum[j] = 0.0;
-  int ecur = -1;
-  auto flush = [&]() {
-    if (ecur < 0) return;
-    for (int j = 0; j < 3; ++j) add(se[ecur][0][j], se[ecur][1][j], esum + j * NC);
-    for (int j = 0; j < 3 * NC; ++j) esum[j] = 0.0;
-  };
-  for (int it = threadIdx.x; it < items; it += kAsmBlock) {
-    const int e = it / per_e, f = it - e * per_e;
-    if (e != ecur) {
-      flush();
-      ecur = e;
-    }
-    int ea[3], eb[3];
-    for (int j = 0; j < 3; ++j) {
-      ea[j] = se[e][0][j];
-      eb[j] = se[e][1][j];
-    }
-    // cell of E: the lower-left vertex of its triangle
-    const int ca = ea[0], cb = eb[0];
+  int ep = 0;                                   // first element not yet flushed (uniform)
+  // the wave's steps: bases are uniform, so every lane runs every step
+  int ecur = -1, eac[3] = {0, 0, 0}, ebc[3] = {0, 0, 0};   // padded: the wave's element
+  int base0 = (int)threadIdx.x - lane;
+  if constexpr (kPad) base0 = __builtin_amdgcn_readfirstlane(base0);
+  for (int base = base0; base < items; base += kAsmBlock) {
+    const int e0 = base / per_p;                // element of the step's first lane
+    while (ep < e0) flush(ep++);                // the wave is past these elements
+    const int it = base + lane;
+    const int e = kPad ? e0 : it / per_p, f = it - e * per_p;
     const int tf = f & 1, cell = f >> 1;
-    const int fa0 = ca - P.R1 + cell % span, fb0 = cb - P.R1 + cell / span;
-    if (fa0 < 0 || fb0 < 0 || fa0 >= P.N || fb0 >= P.N) continue;
+    const int es_ = e < nE ? e : 0;
+    int ea[3], eb[3];
+    if constexpr (kPad) {
+      if (e0 != ecur && e0 < nE) {
+        ecur = e0;
+        for (int j = 0; j < 3; ++j) {
+          eac[j] = __builtin_amdgcn_readfirstlane(se[e0][0][j]);
+          ebc[j] = __builtin_amdgcn_readfirstlane(se[e0][1][j]);
+        }
+      }
+      for (int j = 0; j < 3; ++j) {
+        ea[j] = eac[j];
+        eb[j] = ebc[j];
+      }
+    } else {
+      for (int j = 0; j < 3; ++j) {
+        ea[j] = se[es_][0][j];
+        eb[j] = se[es_][1][j];
+      }
+    }
+    // the partner square: cells (x0 .. x0 + span - 1, y0 .. y0 + span - 1)
+    // around E's cell (the lower-left vertex of its triangle)
+    const int fa0 = ea[0] - P.R1 + cell % span, fb0 = eb[0] - P.R1 + cell / span;
+    if (it >= items || f >= per_e || fa0 < 0 || fb0 < 0 || fa0 >= P.N || fb0 >= P.N) continue;
     int fa[3], fb[3];
     asm_tri(fa0, fb0, tf, fa, fb);
     // (|dA|, |dB| <= 3 (2 R1 + 2): 32-bit products suffice)
@@ -258,30 +331,29 @@ __global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double 
     const int dB = (eb[0] + eb[1] + eb[2]) - (fb[0] + fb[1] + fb[2]);
     if ((long long)(dA * dA + dB * dB) > P.thr) continue;
     // union of the vertices of E and F: E's three, then F's not in E
-    int inF[6], ua[6], ub[6];
-    for (int j = 3; j < 6; ++j) inF[j] = -1;
+    // (static indices only: the array stays in registers)
+    int inF[6] = {-1, -1, -1, -1, -1, -1};
     int nu = 3;
-    for (int j = 0; j < 3; ++j) {
-      ua[j] = ea[j];
-      ub[j] = eb[j];
-      inF[j] = -1;
-    }
     bool touching = false;
     int mF = -1, mE = 0;
+#pragma unroll
     for (int j = 0; j < 3; ++j)
       if (ea[j] == ma && eb[j] == mb) mE = j;
+#pragma unroll
     for (int j = 0; j < 3; ++j) {
-      int dup = -1;
+      bool dup = false;
+#pragma unroll
       for (int u = 0; u < 3; ++u)
-        if (fa[j] == ea[u] && fb[j] == eb[u]) dup = u;
+        if (fa[j] == ea[u] && fb[j] == eb[u]) {
+          inF[u] = j;
+          dup = true;
+        }
       if (fa[j] == ma && fb[j] == mb) mF = j;
-      if (dup >= 0) {
-        inF[dup] = j;
-        touching = true;
-      } else {
-        ua[nu] = fa[j];
-        ub[nu] = fb[j];
-        inF[nu] = j;
+      touching |= dup;
+      if (!dup) {
+#pragma unroll
+        for (int u = 3; u < 6; ++u)
+          if (u == nu) inF[u] = j;
         ++nu;
       }
     }
@@ -301,21 +373,69 @@ __global__ void __launch_bounds__(kAsmBlock) k_assemble_2d(AsmProblem P, double 
       asm_pair<KER, 0, 7, 0, 7>(P, Ex, Ey, Fx, Fy, mE, mF, nu, inF, 1.0, acc);
     }
     const double wf = mF >= 0 ? 1.0 : 2.0;
-    for (int j = 0; j < 3 * NC; ++j) esum[j] += wf * acc[j];           // E's vertices
+    const bool odd = !kPad && (e & 1);
 #pragma unroll
-    for (int u = 3; u < 6; ++u) {                                       // F's other vertices
+    for (int u = 0; u < 3; ++u)                                     // E's vertices
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        const double v = wf * acc[u * NC + (NC == 1 ? 0 : comp[c])];
+        if (odd) es[1][u * NV + c] += v;
+        else es[0][u * NV + c] += v;
+      }
+    // F's other vertices, by vertex index of F: window node (or -1) and share
+    int wj[3] = {-1, -1, -1};
+    double fv[3 * NV];
+#pragma unroll
+    for (int k = 0; k < 3 * NV; ++k) fv[k] = 0.0;
+#pragma unroll
+    for (int u = 3; u < 6; ++u) {
       if (u >= nu) break;
-      const int da = ua[u] - ma, db = ub[u] - mb;
-      if (da < -P.R || da > P.R || db < -P.R || db > P.R) continue;
-      double v[NC];
-      for (int j = 0; j < NC; ++j) v[j] = wf * acc[u * NC + j];
-      add(ua[u], ub[u], v);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (inF[u] == j) {
+          const int da = fa[j] - ma, db = fb[j] - mb;
+          if (da >= -P.R && da <= P.R && db >= -P.R && db <= P.R && (long long)(da * da + db * db) <= P.rr)
+            wj[j] = disk[db + P.R] + da;
+#pragma unroll
+          for (int c = 0; c < NV; ++c) fv[j * NV + c] = wf * acc[u * NC + (NC == 1 ? 0 : comp[c])];
+        }
     }
+    // twelve steps (element of the step, triangle type, vertex index); in
+    // each, the lanes that add hold distinct window nodes, and a wave's LDS
+    // operations complete in program order (so the adds need not return:
+    // nothing waits for them)
+    const int de = e - e0;
+#pragma unroll
+    for (int d = 0; d < (kPad ? 1 : 2); ++d)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (de == d && tf == t && wj[j] >= 0)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) atomicAdd(&mine[wj[j] * NV + c], fv[j * NV + c]);
   }
-  flush();
+  while (ep < nE) flush(ep++);
   __syncthreads();
+  // the copies in wave order; the 2x2 blocks as [row comp][window][col comp]
+  const int WW = W2 * NC;
   double *out = win + (size_t)row * WW;
-  for (int i = threadIdx.x; i < WW; i += kAsmBlock) out[i] = sw[i];
+  for (int i = threadIdx.x; i < WW; i += kAsmBlock) {
+    int wi = i, c = 0;
+    if constexpr (KER == kKerPD) {
+      const int rc = i / (2 * W2), rest = i - rc * 2 * W2, cc = rest & 1;
+      wi = rest >> 1;
+      c = rc + cc;                              // (0,0) -> 0, (0,1) and (1,0) -> 1, (1,1) -> 2
+    }
+    const int db = wi / P.W - P.R, da = wi - (db + P.R) * P.W - P.R;
+    double v = 0.0;
+    if ((long long)(da * da + db * db) <= P.rr) {
+      const int idx = (disk[db + P.R] + da) * NV + c;
+      v = sw[idx];
+      for (int w = 1; w < kAsmWaves; ++w) v += sw[w * WV + idx];
+    }
+    out[i] = v;
+  }
 }
 
 }  // namespace dd

@@ -2652,8 +2652,10 @@ dd_status dd_assemble_2d(int32_t n, int32_t collar, double delta, int32_t kernel
   P.W = 2 * R + 1;
   const double t = 3.0 * delta / P.h;
   P.thr = (long long)std::floor(t * t);
-  const size_t lds = (size_t)P.W * P.W * (kernel == kKerPD ? 4 : 1) * sizeof(double);
-  if (lds > 65536) return fail(nullptr, DD_EINVAL, "window of more than 64 KiB per row");
+  if (P.W > kAsmMaxW) return fail(nullptr, DD_EINVAL, "window wider than 128 nodes");
+  asm_disk(P, delta);
+  const size_t lds = (size_t)kAsmWaves * P.WC * (kernel == kKerPD ? AsmShape<kKerPD>::NV : 1) * sizeof(double);
+  if (lds > 65536) return fail(nullptr, DD_EINVAL, "window copies of more than 64 KiB per row");
   hipStream_t st = (hipStream_t)hip_stream;
   static double rules[13][4];             // static: the copy below may run after the return
   static bool rules_set = false;

@@ -108,16 +108,17 @@ def test_setup_rejects_bad_batch_width(lib, small):
 
 def test_assemble_rejects_bad_arguments(lib):
     """Device assembly validates its arguments on the host (no device work):
-    unknown kernel, too few cells, a window that misses partners, a window
-    beyond 64 KiB per row."""
+    unknown kernel, too few cells, a window that misses partners, one wider
+    than 128 nodes, window copies beyond 64 KiB per row."""
     dd, L = lib
     fake = ctypes.c_void_p(256)               # never dereferenced: every call fails validation
     cases = [
         ((32, 3, 0.1, 7, 1.0, 0.0, 8), "unknown kernel"),
         ((1, 3, 0.1, 0, 1.0, 0.0, 8), "n < 2"),
         ((32, 3, 0.1, 0, 1.0, 0.0, 5), "misses partners"),      # ceil(0.1 * 32) + 2 = 6
-        ((32, 3, 0.1, 0, 1.0, 0.0, 100), "64 KiB"),
-        ((32, 3, 0.1, 2, 1.0, 0.0, 50), "64 KiB"),
+        ((32, 3, 0.1, 0, 1.0, 0.0, 100), "wider than 128"),
+        ((64, 3, 0.5, 0, 1.0, 0.0, 34), "64 KiB"),      # delta n = 32: about 3 500 nodes x 4 copies
+        ((64, 3, 0.25, 2, 1.0, 0.0, 18), "64 KiB"),     # delta n = 16: about 960 nodes x 3 x 4
     ]
     for args, msg in cases:
         st = L.dd_assemble_2d(*args, fake, None)

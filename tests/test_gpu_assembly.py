@@ -4,8 +4,9 @@ fractional (vertex-sharing pairs on the mean of the mixed rules) and
 peridynamic kernels at small sizes, and the constant (h = 1/128), fractional
 (h = 1/96) and peridynamic (h = 1/160) benchmark systems at full size.
 
-The two sum the same pair integrals in different orders (the device adds the
-window entries with atomics), so an entry agrees to rounding of its sum:
+The two sum the same pair integrals in different orders (the device by
+rounds of partner triangles per element), so an entry agrees to rounding of
+its sum:
 each row sums at most 6 elements x (2 ceil(delta/h) + 3)^2 x 2 partners x 49
 quadrature products, a few 1e5 terms, so |device - generator| <= 1e-11 of the
 largest entry of the row (about 1e5 x 1e-16 with a margin)."""
@@ -62,6 +63,18 @@ def test_device_assembly_matches_generator(name):
     assert err <= 1e-11
     # the same zero pattern: entries of pairs outside the truncation stay zero
     assert np.array_equal(got == 0.0, ref == 0.0)
+
+
+@pytest.mark.parametrize("name", ["2d-const-32", "2d-frac-28", "2d-pd-40", "2d-const-128"])
+def test_device_assembly_is_bit_reproducible(name):
+    """Every window entry is summed in a fixed order: two launches on the same
+    arguments give the same bits."""
+    dd = _dd()
+    spec = CASES[name]()
+    print(f"case assembly repeat {name} n={spec.n} kernel={spec.kernel}", flush=True)
+    a, _ = device_windows(dd, spec)
+    b, _ = device_windows(dd, spec)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
 def test_device_assembly_feeds_the_solver():
