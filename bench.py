@@ -442,6 +442,12 @@ def solve_leg(dd, torch, wl, b, tol, steps, warmup, launch, workload):
                 factor=dict(ms=1e3 * fac, gflop=fl / 1e9, achieved_tflops=fl / fac / 1e12, bound="mfma",
                             peak_tflops=peak, frac=fl / fac / 1e12 / peak,
                             note="whole factorisation (Cholesky, L^-1, K^-1, diag(S)) timed on the host"))
+            if name == "mixed":
+                # the tiled mixed solve with the FP64 factor formed replaces its
+                # recurrence residual by the FP64 one instead of refining (one
+                # outer step per column)
+                out[name]["residual_replacement"] = bool(tuned.get("three_launch", 0) & 4) and \
+                    max(out[name]["refine_steps"]) == 1
             sols[name] = r["u"].cpu().numpy().T[:wl.dd.n_dof, :nrhs].copy()
             log(f"bench: {workload} {name}: {out[name]['ms_per_step']:.3f} ms/step "
                 f"its={out[name]['iters'][:4]} resid={out[name]['rel_resid_max']:.2e}")

@@ -115,7 +115,9 @@ typedef struct {
   int32_t max_refine;    /* DD_MIXED: outer refinement steps */
   double inner_tol;      /* DD_MIXED: inner CG stops at ||r_in|| <= max(inner_tol ||r_outer||,
                             tol ||b|| / 2); 0 = automatic (the autotuned value for this
-                            batch width, else 1e-5) */
+                            batch width, else 1e-5).  With residual replacement (`reliable`
+                            below): the reduction of a column's residual after which it is
+                            due for the next replacement; 0 = the autotuned value, else 1e-2 */
   int32_t fp64_fallback; /* DD_MIXED: 1 = finish stalled columns with the FP64 path */
   int32_t apply;         /* dd_apply */
   int32_t launch;        /* dd_launch */
@@ -132,6 +134,20 @@ typedef struct {
                             -1 = automatic (the autotuned schedule, else off), 0 = off,
                             1 = on (ignored below 8 columns, with the triangular-sweep apply,
                             the persistent launch, or a context set up for fewer than 8) */
+  int32_t reliable;      /* DD_MIXED on the tiled path (tiles above) with the FP64 factor also
+                            formed (dd_factor(ctx, DD_FP64)): residual replacement.  The FP32
+                            operators form the search directions; condensation, back
+                            substitution and the interface residual g - S x use the FP64
+                            operators.  Every `reliable` CG iterations, a column whose
+                            residual fell by the factor inner_tol (0: the autotuned value, else
+                            1e-2) since its last
+                            replacement has the recurrence residual replaced by the FP64
+                            one.  One Krylov space
+                            then reaches the tolerance (refinement steps, which restart it,
+                            only follow if the final FP64 check fails).  -1 = automatic
+                            (every 4 iterations), 0 = off (plain refinement), N > 0 = every N
+                            iterations (rounded up to a multiple of the graph length with
+                            DD_LAUNCH_GRAPH).  Ignored elsewhere. */
 } dd_solve_opts;
 
 typedef struct {
@@ -145,7 +161,7 @@ typedef struct {
 
 /* Fill opts with defaults: tol 1e-10, max_it 1000, precond 1, max_refine 8,
  * inner_tol 0 (automatic), fp64_fallback 1, AUTO apply/launch, check_every 0, verify 1,
- * gather32 -1 (automatic), tiles -1 (automatic). */
+ * gather32 -1 (automatic), tiles -1 (automatic), reliable -1 (automatic). */
 void dd_default_opts(dd_solve_opts *opts);
 
 /* Device bytes a context for `prob` would hold: the blocks of eq.
@@ -238,7 +254,9 @@ typedef struct {
   int32_t check_every;       /* polling lag (kernels) or iterations per graph (graph) */
   double ms_per_solve;       /* measured time of one solve of the batch with this schedule */
   int32_t candidates;        /* schedules timed */
-  double inner_tol;          /* DD_MIXED: inner tolerance chosen (0 for DD_FP64) */
+  double inner_tol;          /* DD_MIXED: inner tolerance chosen, or for a schedule that
+                                replaces residuals (dd_solve_opts.reliable) its drop factor
+                                (0 for DD_FP64) */
   int32_t three_launch;      /* bit 0 set: three launches per CG iteration (update fused
                                 into the K_IG launch, direction recurrence in the interior
                                 solve), clear: four (K_IG, interior solve, interface rows,

@@ -61,7 +61,8 @@ class dd_solve_opts(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("fp64_fallback", ctypes.c_int32),
                 ("apply", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("verify", ctypes.c_int32),
-                ("gather32", ctypes.c_int32), ("tiles", ctypes.c_int32)]
+                ("gather32", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("reliable", ctypes.c_int32)]
 
 
 class dd_solve_info(ctypes.Structure):

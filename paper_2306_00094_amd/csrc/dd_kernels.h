@@ -65,7 +65,8 @@ struct ColState {
   double *nrm2;     // scratch norms
   int *active;      // 1 while the column iterates
   int *iters;       // iterations taken
-  int *flag;        // [0]: breakdown (p^T S p <= 0) seen; [1]: iterate (persistent launch)
+  int *flag;        // [0]: breakdown (p^T S p <= 0) seen; [1]: iterate (persistent launch);
+                    // [2], [3]: residual replacement (below)
   // three-launch iteration: values of iteration k in slot k & 1 (a launch
   // reads the previous iteration's slot while its workgroup 0 writes the
   // current one), and the per-column breakdown marks of the step length
@@ -77,7 +78,13 @@ struct ColState {
   double *rz_prev;  // kMaxLd
   int *act_prev;    // kMaxLd
   int *brk;         // kMaxLd
+  // residual replacement (mixed tiled solve): r.r at the start or at the last
+  // replacement, and whether the column is due for the next one; flag[2]:
+  // some column is due, flag[3]: this step replaced
+  double *ref2;     // kMaxLd
+  int *due;         // kMaxLd
 };
+
 
 // Partial-sum buffers and completion counters of the reductions.
 struct RedBuf {
@@ -867,6 +874,14 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 // mode 2 (masked init): columns with mask[c] != 0 restart from the residual
 //                  given in q (mode 0 for those columns), the others keep
 //                  their state.
+// mode 3 (residual replacement; RED = 2 only, after a mode-1 launch of the
+//                  same step): the columns that stepped (act_prev and no
+//                  breakdown) and are due for a replacement (st.due, from the
+//                  last direction launch) take the residual given in q, recomputed from x
+//                  with more accurate operators, as r, and z = D^{-1} r; x and
+//                  p are kept.  The chunk partials of r.z and r.r are those of
+//                  the new residual, so the direction launch that follows
+//                  forms beta, the convergence test and p from it.
 // The last workgroup then updates the column state:
 //   init:   rz = r.z, active = (r.r > stop2) for c < nrhs, iters = 0
 //   update: iters += 1; converged when r.r <= stop2; beta = r.z / rz_old
@@ -925,6 +940,11 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       }
     }
   }
+  if (mode == 3) {
+    for (int c = threadIdx.x; c < ld; c += kBlock) sact[c] = st.act_prev[c] && !st.brk[c] && st.due[c];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.flag[3] = 1;    // read by the direction launch
+    __syncthreads();
+  }
   if (mode == 1) {
     // wave wv takes the columns c0 .. c0+7 of every group of 32 (the loads of a
     // wave's columns overlap; each column's sum is that of partials_sum)
@@ -977,9 +997,10 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
       if (j < nrows) {
         const size_t o = (size_t)j * ld + c;
         const bool init = mode == 0 || (mode == 2 && mask[c]);
-        double rr_ = (mode == 2 && init) ? qv[k] : rv[k];
-        if (mode == 2 && init) wm[k] |= 2;
-        const bool act = init ? true : (mode == 1 && sact[c] != 0);
+        const bool act = init ? true : ((mode == 1 || mode == 3) && sact[c] != 0);
+        const bool repl = (mode == 2 && init) || (mode == 3 && act);
+        double rr_ = repl ? qv[k] : rv[k];
+        if (repl) wm[k] |= 2;
         if (mode == 1 && act) {
           const double a = salpha[c];
           xn[k] = fma(a, pv[k], xv[k]);
@@ -1096,6 +1117,8 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         st.rz[c] = rz;
         st.iters[c] = 0;
         st.beta[c] = 0.0;
+        st.ref2[c] = rr;
+        st.due[c] = 0;
         active = ((mode == 2 || c < nrhs) && rr > s2) ? 1 : 0;
       } else if (mode == 1) {
         st.alpha[c] = salpha[c];
@@ -1120,7 +1143,11 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
     if (lane == 0) {
-      if (mode == 0) st.flag[0] = 0;     // a new solve starts without breakdown
+      if (mode == 0) {                   // a new solve starts without breakdown or replacement
+        st.flag[0] = 0;
+        st.flag[2] = 0;
+        st.flag[3] = 0;
+      }
       if (st.flag[0]) na = 0;            // breakdown ends the loop
       st.flag[1] = na > 0 ? 1 : 0;       // loop decision for the persistent launch
       if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1770,7 +1797,7 @@ __device__ __forceinline__ void direction_sums(const RedBuf &red, int ld, int nc
 __global__ void __launch_bounds__(kDirBlock)
 k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__restrict__ p, RedBuf red,
                      ColState st, int nch, int *__restrict__ host_nact, float *__restrict__ p32,
-                     const int *__restrict__ run) {
+                     const int *__restrict__ run, double drop2) {
   if (run && *run == 0) {              // every column had stopped: nothing changes, report none active
     if (blockIdx.x == 0 && threadIdx.x == 0 && host_nact)
       __hip_atomic_store(host_nact, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1780,6 +1807,7 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
   __shared__ double tot[2 * kMaxLd];
   __shared__ double sbeta[kMaxLd];
   __shared__ int sact[kMaxLd];
+  __shared__ int sdue[kMaxLd];
   const int cw = min(ld, kDirCols), ncb = ld / cw;
   // workgroup 0: every column's sums and state, no direction rows; workgroup
   // b >= 1: column block (b - 1) % ncb over row share (b - 1) / ncb
@@ -1829,17 +1857,33 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
       }
       st.active[c] = act;
       st.nrm2[c] = rr2;
+      // residual replacement: the reference norm after one, and whether the
+      // column is due for the next
+      double ref = st.ref2[c];
+      if (st.flag[3] && st.due[c] && act0 && !brk) {     // replaced in this step
+        ref = rr2;
+        st.ref2[c] = ref;
+      }
+      const int due = (act && rr2 < drop2 * ref) ? 1 : 0;
+      st.due[c] = due;
+      sdue[c] = due;
     }
   }
   __syncthreads();
   if (all && threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     int na = lane < ld ? sact[lane] : 0;
+    int nd = lane < ld ? sdue[lane] : 0;
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) na += __shfl_xor(na, o, kWave);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      na += __shfl_xor(na, o, kWave);
+      nd += __shfl_xor(nd, o, kWave);
+    }
     if (lane == 0) {
       if (st.flag[0]) na = 0;            // breakdown ends the loop
       st.flag[1] = na > 0 ? 1 : 0;
+      st.flag[2] = (na > 0 && nd > 0) ? 1 : 0;
+      st.flag[3] = 0;
       if (host_nact) __hip_atomic_store(host_nact, na + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }

@@ -56,6 +56,8 @@ struct StateBlock {
   double rz2[2 * kMaxLd], rz_prev[kMaxLd];
   int active[kMaxLd], iters[kMaxLd], flag[kMaxLd];
   int act2[2 * kMaxLd], bd[kMaxLd], act_prev[kMaxLd], brk[kMaxLd];
+  double ref2[kMaxLd];
+  int due[kMaxLd];
 };
 
 struct Work {
@@ -155,6 +157,7 @@ struct dd_ctx {
     int prec, ld, apply, precond, dk, iters, cg3;
     double *x;
     hipGraphExec_t exec;
+    double drop;      // residual replacement: the drop factor the direction launches carry
   };
   std::vector<GraphEntry> graphs;
   bool capturing = false;
@@ -163,6 +166,7 @@ struct dd_ctx {
     bool set = false;
     int apply = 0, launch = 0, dk = 0, check_every = 0, cg3 = 1;
     double ms = 0, inner_tol = 0;
+    double drop = 0;            // mixed, replacing schedule: the replacement drop factor
   };
   int force_cg3 = -1;         // autotuner: -1 schedule decides, else the schedule bits (bit 0 three
                               // launches, bit 1 FP32 gathers)
@@ -1138,6 +1142,8 @@ struct CoreOpts {
   int check_every;
   int launch;
   int cg3;        // bit 0: three launches per CG iteration where possible; bit 1: FP32 gathers (mixed)
+  int reliable = 0;   // DD_MIXED, tiled: iterations between FP64 residual replacements (0: none)
+  double replace_drop = 0.0;   // residual reduction after which a column is due for one
 };
 
 // Untuned solves run three launches per iteration (k_cg_kig) at every batch
@@ -1206,10 +1212,22 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // Wide batches on the matrix cores (schedule bit 2): tiled coupling products
   // and interior solves, the direction kept in memory by its own kernel.
   const bool tl = use_tiles(c, o.cg3, ld, o.apply, o.launch);
+  // Residual replacement (mixed precision on the tiled path, FP64 operators
+  // formed): the directions take S p with the FP32 operators, while the
+  // condensation, the back substitution and, every `rel` iterations, the
+  // residual r = g - S x come from the FP64 ones.  One Krylov space then
+  // reaches the FP64 accuracy, where refinement restarts it per step.
+  const int rel = (tl && prec == DD_MIXED && o.reliable > 0 && c->op[DD_FP64].ready &&
+                   c->op[DD_FP64].kinv_t && c->n_gamma > 0) ? o.reliable : 0;
+  const int cprec = rel ? DD_FP64 : prec;    // operators of condensation and back substitution
+  double *gG = w.r2G;                        // condensed right-hand side g (unused by the tiled loop)
   // condensation (eq. subForcing summed over subdomains): r = bG - K_GI K_II^{-1} bI
   if (tl) {
-    dense_tiles(c, prec, false, bI, ld, nullptr, 1.0, w.wI);
-    tile_rows<false>(c, prec, true, nullptr, w.wI, ld, bG, 0.0, -1.0, w.rG);
+    dense_tiles(c, cprec, false, bI, ld, nullptr, 1.0, w.wI);
+    tile_rows<false>(c, cprec, true, nullptr, w.wI, ld, bG, 0.0, -1.0, w.rG);
+    if (rel)
+      HIPCHK(c, hipMemcpyAsync(gG, w.rG, (size_t)c->n_gamma * ld * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
   } else {
     interior_solve(c, prec, o.apply, bI, w.wI, ld);
     gamma_apply(c, prec, plain(nullptr), w.wI, ld, bG, 0.0, -1.0, w.rG);
@@ -1270,7 +1288,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   // last direction launch, or the initialisation, left in st.flag[1]): the
   // host enqueues up to check_every iterations past the last one needed.
   const int *run = tl ? c->st.flag + 1 : nullptr;
-  auto iteration = [&](double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
+  auto iteration = [&](double *&pA_, double *&pB_, int *nact_dst, bool replace) -> dd_status {
     // direction p = z + beta p_prev, formed where it is gathered (or kept in pA)
     const bool dk = dkv != 0;
     Src P = dk ? plain(pA_) : Src{nullptr, w.zG, pA_, c->st.beta};
@@ -1307,10 +1325,24 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       launch_update(c, 1, ld, nrhs, op.dinv, uG, w.rG, w.zG, dk ? pA_ : pB_, w.qG, o.precond,
                     tl ? nullptr : nact_dst, 0, nullptr, c->gamma_parts, tl ? 2 : 0, run);
     }
+    if (tl && replace) {
+      // the FP64 residual of the new x, q = g - K_GG x + K_GI K_II^{-1} K_IG x
+      // (q, y and w are free until the next step), takes the place of r.  The
+      // launches do nothing unless the last direction launch found a column
+      // whose residual fell by kReplaceDrop since its last replacement
+      // (st.flag[2]).
+      const int *due = c->st.flag + 2;
+      tile_rows<false>(c, DD_FP64, false, uG, nullptr, ld, nullptr, 1.0, 0.0, w.yI, due);
+      dense_tiles(c, DD_FP64, false, w.yI, ld, nullptr, 1.0, w.wI, due);
+      tile_rows<false>(c, DD_FP64, true, uG, w.wI, ld, gG, -1.0, 1.0, w.qG, due);
+      launch_update(c, 3, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA_, w.qG, o.precond, nullptr, 0, nullptr, 0,
+                    2, due);
+    }
     if (tl) {        // the split update's state and the direction in one launch
       hipLaunchKernelGGL(k_cg_direction_state, dim3(direction_state_grid(ld)), dim3(kDirBlock), 0, c->stream,
                          c->n_gamma, ld, w.zG,
-                         pA_, c->red, c->st, (int)upd_grid(c->n_gamma, ld), nact_dst, c->g32.p, run);
+                         pA_, c->red, c->st, (int)upd_grid(c->n_gamma, ld), nact_dst, c->g32.p, run,
+                         o.replace_drop * o.replace_drop);
     } else if (dk) {
       unsigned gd = std::min(4096u, grid_for((size_t)c->n_gamma * ld, kBlock));
       hipLaunchKernelGGL(k_cg_direction, dim3(gd), dim3(kBlock), 0, c->stream, c->n_gamma, ld,
@@ -1322,8 +1354,9 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     return DD_OK;
   };
   // CG iteration k >= 1 in either scheme
-  auto step = [&](int k, double *&pA_, double *&pB_, int *nact_dst) -> dd_status {
-    if (!cg3) return iteration(pA_, pB_, nact_dst);
+  // (replace: this iteration ends with the residual replacement)
+  auto step = [&](int k, double *&pA_, double *&pB_, int *nact_dst, bool replace) -> dd_status {
+    if (!cg3) return iteration(pA_, pB_, nact_dst, replace);
     cg3_iteration(c, prec, k, 1, ld, nrhs, o.precond, uG, nullptr, nact_dst, g32);
     HIPCHK(c, hipGetLastError());
     return DD_OK;
@@ -1332,41 +1365,52 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // G iterations per graph (even, so the direction buffers return to place)
     int G = std::max(2, std::min(32, o.check_every > 0 ? o.check_every : 4));
     G += G & 1;
-    hipGraphExec_t exec = nullptr;
-    for (auto &g : c->graphs)
-      if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
-          g.dk == dkv && g.iters == G && g.x == uG && g.cg3 == sched)
-        exec = g.exec;
-    if (!exec) {
-      if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-      hipStream_t user = c->stream;
-      c->stream = c->cap_stream;     // kernels are recorded, not run
-      hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (eb != hipSuccess) {
+    // with residual replacement, a second graph of G iterations whose last
+    // one replaces the residual, replayed every relG / G launches (relG: the
+    // period rounded up to a multiple of G)
+    const int relG = rel ? (rel + G - 1) / G * G : 0;
+    auto graph_exec = [&](bool rb, hipGraphExec_t &exec) -> dd_status {
+      const int key = sched | (rb ? 8 : 0);
+      exec = nullptr;
+      for (auto &g : c->graphs)
+        if (g.prec == prec && g.ld == ld && g.apply == o.apply && g.precond == o.precond &&
+            g.dk == dkv && g.iters == G && g.x == uG && g.cg3 == key && g.drop == o.replace_drop)
+          exec = g.exec;
+      if (!exec) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;     // kernels are recorded, not run
+        hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (eb != hipSuccess) {
+          c->stream = user;
+          return fail(c, DD_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+        }
+        c->capturing = true;
+        dd_status cs = DD_OK;
+        double *qa = pA, *qb = pB;
+        for (int i = 0; i < G && cs == DD_OK; ++i)     // iterations 1..G (odd k first)
+          cs = step(1 + i, qa, qb, i == G - 1 ? c->h_nact_dev : nullptr, rb && i == G - 1);
+        c->capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
         c->stream = user;
-        return fail(c, DD_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+        if (cs != DD_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return cs;
+        }
+        if (ee != hipSuccess)
+          return fail(c, DD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ee != hipSuccess)
+          return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
+        c->graphs.push_back({prec, ld, o.apply, o.precond, dkv, G, key, uG, exec, o.replace_drop});
       }
-      c->capturing = true;
-      dd_status cs = DD_OK;
-      double *qa = pA, *qb = pB;
-      for (int i = 0; i < G && cs == DD_OK; ++i)     // iterations 1..G (odd k first)
-        cs = step(1 + i, qa, qb, i == G - 1 ? c->h_nact_dev : nullptr);
-      c->capturing = false;
-      hipGraph_t graph = nullptr;
-      hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
-      c->stream = user;
-      if (cs != DD_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cs;
-      }
-      if (ee != hipSuccess)
-        return fail(c, DD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-      ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ee != hipSuccess)
-        return fail(c, DD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ee));
-      c->graphs.push_back({prec, ld, o.apply, o.precond, dkv, G, sched, uG, exec});
-    }
+      return DD_OK;
+    };
+    hipGraphExec_t exec = nullptr, exec_rel = nullptr;
+    TRY(graph_exec(false, exec));
+    if (rel) TRY(graph_exec(true, exec_rel));
     // replay; look at the result of launch n - 1 while launch n runs.  The
     // number of active columns only decreases, so a later value is as good.
     ((volatile int *)c->h_nact)[0] = 0;
@@ -1375,7 +1419,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     while (launches < max_launch) {
       {
         PhaseTimer t(c, DD_PHASE_LOOP);
-        HIPCHK(c, hipGraphLaunch(exec, c->stream));
+        const bool rb = rel && ((launches + 1) * G) % relG == 0;
+        HIPCHK(c, hipGraphLaunch(rb ? exec_rel : exec, c->stream));
       }
       HIPCHK(c, hipEventRecord(c->ev[launches % c->nslots], c->stream));
       ++launches;
@@ -1409,7 +1454,7 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
       ++it;
       int slot = it % c->nslots;
       hn[slot] = 0;
-      TRY(step(it, pA, pB, c->h_nact_dev + slot));
+      TRY(step(it, pA, pB, c->h_nact_dev + slot, rel > 0 && it % rel == 0));
       ring_it[slot] = it;
       // look at iteration it - lag, never more than nslots in flight
       int target = it - lag;
@@ -1427,8 +1472,8 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
   c->g32 = Gather32{};
   // back substitution (eq. backwardSubstitution): uI = K_II^{-1} (bI - K_IG uG)
   if (tl) {
-    tile_rows<false>(c, prec, false, uG, nullptr, ld, bI, -1.0, 0.0, w.yI);
-    dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, uI);
+    tile_rows<false>(c, cprec, false, uG, nullptr, ld, bI, -1.0, 0.0, w.yI);
+    dense_tiles(c, cprec, false, w.yI, ld, nullptr, 1.0, uI);
   } else {
     kig_apply(c, prec, plain(uG), ld, bI, -1.0, w.yI);
     interior_solve(c, prec, o.apply, w.yI, uI, ld);
@@ -1446,6 +1491,17 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
 // FP32 operators limit what one step can gain to about 1e-5..1e-6, and a
 // step that stops there needs two steps for a 1e-9 target instead of three.
 constexpr double kInnerTol = 1e-5;
+// Residual replacement of the mixed tiled solve: every kReplacePeriod
+// iterations the FP64 residual may take the place of the recurrence one; it
+// does when a column's residual has fallen by the factor kReplaceDrop (in
+// the direction launch) since its last replacement.  The recurrence, on FP32
+// operators, drifts from the true residual by about 1e-5 of the residual at
+// the last replacement, so the drift stays a small fraction of the current
+// residual, and the solve stops at kReplaceStop times the target so that the
+// drift since the last replacement stays inside it.
+constexpr int kReplacePeriod = 4;
+constexpr double kReplaceDrop = 1e-2;
+constexpr double kReplaceStop = 0.7;
 inline double resolve_inner_tol(const dd_ctx *c, int prec, int ld, double requested) {
   if (requested > 0.0) return requested;
   int lg = 0;
@@ -1528,6 +1584,7 @@ void dd_default_opts(dd_solve_opts *o) {
   o->verify = 1;
   o->gather32 = -1;
   o->tiles = -1;
+  o->reliable = -1;
 }
 
 const char *dd_last_error(const dd_ctx *ctx) {
@@ -1872,6 +1929,8 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     c->st.rz_prev = sb->rz_prev;
     c->st.act_prev = sb->act_prev;
     c->st.brk = sb->brk;
+    c->st.ref2 = sb->ref2;
+    c->st.due = sb->due;
     if (hipMemset(sb, 0, sizeof(StateBlock)) != hipSuccess) {
       c->err = "hipMemset failed";
       return bail(DD_EHIP);
@@ -1992,7 +2051,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   hipLaunchKernelGGL(k_fill_rhs, dim3(256), dim3(256), 0, c->stream, c->n_dof, nrhs, c->n_dof,
                      0x5eedull, b);
   HIPCHK(c, hipGetLastError());
-  struct Cand { int apply, launch, dk, ce, cg3; };
+  struct Cand { int apply, launch, dk, ce, cg3; double drop = 0.0; };
   std::vector<Cand> cands;
   // three-launch iteration (when there are interiors), then the four-launch
   // one with the direction formed at the gathers or kept by its own kernel
@@ -2013,9 +2072,20 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 2});
   }
   // batches of kTileMinLd or more columns: the tiled matrix-core products
+  // (mixed precision with the FP64 factor formed: they replace residuals,
+  // and each launch mode is timed at three drop factors)
+  const bool can_replace = prec == DD_MIXED && o.reliable != 0 && !(o.inner_tol > 0.0) &&
+                           c->op[DD_FP64].ready && c->op[DD_FP64].kinv_t;
   if (c->tiles && next_pow2(nrhs) >= kTileMinLd) {
-    cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 4});
-    cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 4});
+    if (can_replace) {
+      for (double drop : {1e-2, 3e-3, 1e-3}) {
+        cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 4, drop});
+        cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 4, drop});
+      }
+    } else {
+      cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 4});
+      cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 4});
+    }
   }
   cands.push_back({DD_APPLY_TRSM, DD_LAUNCH_KERNELS, 0, 2, 0});
   // The cooperative persistent launch is timed only on request
@@ -2034,6 +2104,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     oc.apply = cd.apply;
     oc.launch = cd.launch;
     oc.check_every = cd.ce;
+    if (cd.drop > 0.0) oc.inner_tol = cd.drop;
     c->direction_kernel = cd.dk;
     c->force_cg3 = cd.cg3;
     dd_status s = dd_solve(c, prec, b, u, nrhs, c->n_dof, &oc, nullptr);   // warm-up (captures graphs)
@@ -2052,7 +2123,10 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   // mixed precision: the inner tolerance, with the schedule just chosen
   double best_itol = o.inner_tol > 0.0 ? o.inner_tol : kInnerTol;
   int ncand = (int)cands.size();
-  if (prec == DD_MIXED && !(o.inner_tol > 0.0)) {
+  // (not for a tiled schedule that replaces residuals: that solve never
+  // refines, and inner_tol set its replacement points instead)
+  const bool replaces = can_replace && (bc.cg3 & 4);
+  if (prec == DD_MIXED && !(o.inner_tol > 0.0) && !replaces) {
     for (double itol : {1e-4, 1e-5, 1e-6}) {
       dd_solve_opts oc = o;
       oc.apply = bc.apply;
@@ -2079,7 +2153,9 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   c->direction_kernel = saved_dk;
   c->force_cg3 = -1;
   c->err.clear();
+  const double best_drop = replaces ? bc.drop : 0.0;
   auto &t = c->tuned[prec][lg];
+  t.drop = best_drop;
   t.set = true;
   t.apply = bc.apply;
   t.launch = bc.launch;
@@ -2095,7 +2171,7 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
     out->check_every = bc.ce;
     out->ms_per_solve = best;
     out->candidates = ncand;
-    out->inner_tol = t.inner_tol;
+    out->inner_tol = best_drop > 0.0 ? best_drop : t.inner_tol;
     out->three_launch = bc.cg3;
   }
   return DD_OK;
@@ -2446,9 +2522,12 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
   if (!c->op[prec].ready) return fail(c, DD_ESTATE, "dd_factor has not run for this precision");
   if (prec == DD_MIXED && (o.max_refine < 1 || o.inner_tol < 0.0 || o.inner_tol >= 1.0))
     return fail(c, DD_EINVAL, "max_refine < 1 or inner_tol not in [0,1)");
+  if (o.reliable < -1) return fail(c, DD_EINVAL, "reliable < -1");
   const int L = next_pow2(nrhs);
+  const double itol_requested = o.inner_tol;
   if (prec == DD_MIXED) o.inner_tol = resolve_inner_tol(c, prec, L, o.inner_tol);
   int use_cg3 = 1;
+  double tuned_drop = 0.0;
   struct RestoreDk {
     dd_ctx *c;
     int v;
@@ -2467,6 +2546,7 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
         if (o.check_every == 0) o.check_every = t.check_every;
       }
     }
+    if (t.set) tuned_drop = t.drop;
   }
   if (c->force_cg3 >= 0) use_cg3 = c->force_cg3;
   if (c->gather32 || o.gather32 == 1) use_cg3 |= 2;
@@ -2479,6 +2559,11 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
               (o.launch == DD_LAUNCH_PERSISTENT || o.launch == DD_LAUNCH_GRAPH) ? o.launch : DD_LAUNCH_KERNELS,
               use_cg3};
   const bool tl = use_tiles(c, co.cg3, L, co.apply, co.launch);
+  // residual replacement in the mixed solve (tiled path, FP64 operators formed)
+  if (prec == DD_MIXED && o.reliable != 0) co.reliable = o.reliable < 0 ? kReplacePeriod : o.reliable;
+  co.replace_drop = itol_requested > 0.0 ? itol_requested : (tuned_drop > 0.0 ? tuned_drop : kReplaceDrop);
+  const bool replacing = tl && co.reliable > 0 && c->op[DD_FP64].ready && c->op[DD_FP64].kinv_t &&
+                         c->n_gamma > 0;
   Work &w = c->w;
   // gather b into the DD layout (both parts in one launch)
   const int n_all = c->NI + c->n_gamma;
@@ -2539,7 +2624,10 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     int *mask = c->h_mask;
     double *st2 = c->h_stop2;
     {
-      const double f20 = std::max(o.inner_tol * o.inner_tol, 0.25 * o.tol * o.tol);
+      // with residual replacement step 0 aims at the outer tolerance itself
+      // (with a margin for the residual's drift since the last replacement)
+      const double f20 = replacing ? kReplaceStop * kReplaceStop * o.tol * o.tol
+                                   : std::max(o.inner_tol * o.inner_tol, 0.25 * o.tol * o.tol);
       norm2(w.bI, w.bG, w.bnrm2, f20, c->st.stop2);
       dd_status s = core_solve(c, DD_MIXED, w.bI, w.bG, w.uI, w.uG, L, nrhs, co);
       if (s != DD_OK) return s;
