@@ -138,14 +138,16 @@ typedef struct {
                             formed (dd_factor(ctx, DD_FP64)): residual replacement.  The FP32
                             operators form the search directions; condensation, back
                             substitution and the interface residual g - S x use the FP64
-                            operators.  Every `reliable` CG iterations, a column whose
-                            residual fell by the factor inner_tol (0: the autotuned value, else
-                            1e-2) since its last
-                            replacement has the recurrence residual replaced by the FP64
-                            one.  One Krylov space
-                            then reaches the tolerance (refinement steps, which restart it,
-                            only follow if the final FP64 check fails).  -1 = automatic
-                            (every 4 iterations), 0 = off (plain refinement), N > 0 = every N
+                            operators.  Every `reliable` CG iterations, once some column's
+                            residual has fallen by the factor inner_tol (0: the autotuned
+                            value, else 1e-2) since the last replacement, every iterating
+                            column has its recurrence residual replaced by the FP64 one (one
+                            FP64 product serves the batch, so the replacement points depend
+                            on the batch: a column's result is the same in any batch within
+                            the tolerance, not bitwise).  One Krylov space then reaches the
+                            tolerance (refinement steps, which restart it, only follow if
+                            the final FP64 check fails).  -1 = automatic (every 8
+                            iterations), 0 = off (plain refinement), N > 0 = every N
                             iterations (rounded up to a multiple of the graph length with
                             DD_LAUNCH_GRAPH).  Ignored elsewhere. */
 } dd_solve_opts;

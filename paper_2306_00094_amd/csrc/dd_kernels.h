@@ -79,10 +79,10 @@ struct ColState {
   int *act_prev;    // kMaxLd
   int *brk;         // kMaxLd
   // residual replacement (mixed tiled solve): r.r at the start or at the last
-  // replacement, and whether the column is due for the next one; flag[2]:
-  // some column is due, flag[3]: this step replaced
+  // replacement; flag[2]: some column is due for the next one (all iterating
+  // columns are then replaced together: one FP64 product serves the batch),
+  // flag[3]: this step replaced
   double *ref2;     // kMaxLd
-  int *due;         // kMaxLd
 };
 
 
@@ -876,8 +876,7 @@ k_gamma_rows(int nrows, const int *__restrict__ ptr, const int *__restrict__ spl
 //                  their state.
 // mode 3 (residual replacement; RED = 2 only, after a mode-1 launch of the
 //                  same step): the columns that stepped (act_prev and no
-//                  breakdown) and are due for a replacement (st.due, from the
-//                  last direction launch) take the residual given in q, recomputed from x
+//                  breakdown) take the residual given in q, recomputed from x
 //                  with more accurate operators, as r, and z = D^{-1} r; x and
 //                  p are kept.  The chunk partials of r.z and r.r are those of
 //                  the new residual, so the direction launch that follows
@@ -941,7 +940,7 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
     }
   }
   if (mode == 3) {
-    for (int c = threadIdx.x; c < ld; c += kBlock) sact[c] = st.act_prev[c] && !st.brk[c] && st.due[c];
+    for (int c = threadIdx.x; c < ld; c += kBlock) sact[c] = st.act_prev[c] && !st.brk[c];
     if (blockIdx.x == 0 && threadIdx.x == 0) st.flag[3] = 1;    // read by the direction launch
     __syncthreads();
   }
@@ -1118,7 +1117,6 @@ k_cg_update(int mode, int nrows, int ld, int nrhs, const double *__restrict__ di
         st.iters[c] = 0;
         st.beta[c] = 0.0;
         st.ref2[c] = rr;
-        st.due[c] = 0;
         active = ((mode == 2 || c < nrhs) && rr > s2) ? 1 : 0;
       } else if (mode == 1) {
         st.alpha[c] = salpha[c];
@@ -1860,13 +1858,11 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
       // residual replacement: the reference norm after one, and whether the
       // column is due for the next
       double ref = st.ref2[c];
-      if (st.flag[3] && st.due[c] && act0 && !brk) {     // replaced in this step
+      if (st.flag[3] && act0 && !brk) {     // replaced in this step
         ref = rr2;
         st.ref2[c] = ref;
       }
-      const int due = (act && rr2 < drop2 * ref) ? 1 : 0;
-      st.due[c] = due;
-      sdue[c] = due;
+      sdue[c] = (act && rr2 < drop2 * ref) ? 1 : 0;
     }
   }
   __syncthreads();

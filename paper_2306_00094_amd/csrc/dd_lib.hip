@@ -57,7 +57,6 @@ struct StateBlock {
   int active[kMaxLd], iters[kMaxLd], flag[kMaxLd];
   int act2[2 * kMaxLd], bd[kMaxLd], act_prev[kMaxLd], brk[kMaxLd];
   double ref2[kMaxLd];
-  int due[kMaxLd];
 };
 
 struct Work {
@@ -1327,10 +1326,10 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     }
     if (tl && replace) {
       // the FP64 residual of the new x, q = g - K_GG x + K_GI K_II^{-1} K_IG x
-      // (q, y and w are free until the next step), takes the place of r.  The
-      // launches do nothing unless the last direction launch found a column
-      // whose residual fell by kReplaceDrop since its last replacement
-      // (st.flag[2]).
+      // (q, y and w are free until the next step), takes the place of r in
+      // every iterating column.  The launches do nothing unless the last
+      // direction launch found a column whose residual fell by the drop
+      // factor since the last replacement (st.flag[2]).
       const int *due = c->st.flag + 2;
       tile_rows<false>(c, DD_FP64, false, uG, nullptr, ld, nullptr, 1.0, 0.0, w.yI, due);
       dense_tiles(c, DD_FP64, false, w.yI, ld, nullptr, 1.0, w.wI, due);
@@ -1493,13 +1492,13 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
 constexpr double kInnerTol = 1e-5;
 // Residual replacement of the mixed tiled solve: every kReplacePeriod
 // iterations the FP64 residual may take the place of the recurrence one; it
-// does when a column's residual has fallen by the factor kReplaceDrop (in
-// the direction launch) since its last replacement.  The recurrence, on FP32
+// does when some column's residual has fallen by the factor kReplaceDrop (in
+// the direction launch) since the last replacement.  The recurrence, on FP32
 // operators, drifts from the true residual by about 1e-5 of the residual at
 // the last replacement, so the drift stays a small fraction of the current
 // residual, and the solve stops at kReplaceStop times the target so that the
 // drift since the last replacement stays inside it.
-constexpr int kReplacePeriod = 4;
+constexpr int kReplacePeriod = 8;
 constexpr double kReplaceDrop = 1e-2;
 constexpr double kReplaceStop = 0.7;
 inline double resolve_inner_tol(const dd_ctx *c, int prec, int ld, double requested) {
@@ -1930,7 +1929,6 @@ dd_status dd_setup(const dd_problem *p, void *hip_stream, int32_t max_nrhs, dd_c
     c->st.act_prev = sb->act_prev;
     c->st.brk = sb->brk;
     c->st.ref2 = sb->ref2;
-    c->st.due = sb->due;
     if (hipMemset(sb, 0, sizeof(StateBlock)) != hipSuccess) {
       c->err = "hipMemset failed";
       return bail(DD_EHIP);
