@@ -273,22 +273,36 @@ def solve_errors(u, uref):
 
 
 def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000, gather32: int = 1,
-                chunk: int = 1000):
+                chunk: int = 1000, nreq_load: int = 2000, nreq_budget: int = 1000,
+                budget_frac: float = 0.5):
     """Continuous-batching serving run (paper_2306_00094_amd.serving) over
-    six resident systems: the 1D constant kernel at h = 1/1024 and 1/2048,
-    the 2D constant kernel at h = 1/64 and 1/128 (the benchmark system), and
-    the 2D fractional kernel at h = 1/48 and 1/96 (mesh sizes x0.5 to x2 of
-    the three base systems).  Requests carry 1-64 seeded right-hand sides.  First all requests arrive at once (saturated
-    throughput), then Poisson arrivals at 0.8x that request rate (latency
-    under load); more than `chunk` requests run as consecutive chunks of
-    that many.  Mixed precision, with FP32 gathers unless gather32 = 0."""
+    eleven systems drawn from the first three workloads at mesh scales 0.5 to
+    2: the 1D constant kernel at h = 1/512 ... 1/2048 (scales 0.5, 0.75, 1,
+    1.5, 2), the 2D constant kernel at h = 1/64, 1/96, 1/128 and the 2D
+    fractional kernel at h = 1/48, 1/72, 1/96 (scales 0.5, 0.75, 1; their 1.5
+    and 2 scales take 30-60 s of host assembly each and stay out of the
+    default run).  Requests carry 1-64 seeded right-hand sides and pick a
+    system uniformly.  Three phases, mixed precision with FP32 gathers unless
+    gather32 = 0:
+      saturated: nreq requests arriving at once, in chunks of `chunk` (each
+                 drains before the next), every system resident;
+      load:      nreq_load Poisson arrivals at 0.8x the saturated request rate
+                 (latency under load);
+      budget:    nreq_budget requests arriving at once with an HBM budget of
+                 budget_frac of the systems' summed footprint, so that systems
+                 are evicted and set up again as requests for them arrive."""
     import numpy as np
     from paper_2306_00094_amd import serving
     specs = {
+        "1d-const h=1/512": workloads.spec_1d(n=512),
+        "1d-const h=1/768": workloads.spec_1d(n=768),
         "1d-const h=1/1024": workloads.spec_1d(),
+        "1d-const h=1/1536": workloads.spec_1d(n=1536),
         "1d-const h=1/2048": workloads.spec_1d(n=2048),
         "2d-const h=1/64": workloads.scaled(workloads.spec_2d_const, 0.5),
+        "2d-const h=1/96": workloads.scaled(workloads.spec_2d_const, 0.75),
         "2d-frac h=1/48": workloads.scaled(workloads.spec_2d_frac, 0.5),
+        "2d-frac h=1/72": workloads.scaled(workloads.spec_2d_frac, 0.75),
         "2d-frac h=1/96": workloads.spec_2d_frac(),
     }
     systems = {k: workloads.build(sp).dd for k, sp in specs.items()}
@@ -309,35 +323,51 @@ def serving_leg(dd, workloads, wl_main, nreq: int, seed: int = 5000, gather32: i
 
     # long runs go in chunks of `chunk` requests (each drains before the next
     # starts); seconds add up over the chunks
-    def phase(name, arrivals):
+    def phase(srv, name, n_total, arrivals):
         done, secs = [], 0.0
-        for c0 in range(0, nreq, chunk):
-            n = min(chunk, nreq - c0)
+        for c0 in range(0, n_total, chunk):
+            n = min(chunk, n_total - c0)
             t0 = time.perf_counter()
             d = srv.run(requests(arrivals(n, c0), c0), timeout=600, keep_resident=True)
             wall = time.perf_counter() - t0
-            secs += wall if name == "saturated" else serving.summarize(d)["seconds"]
+            secs += wall if name != "load" else serving.summarize(d)["seconds"]
             done += d
-            if nreq > chunk:
-                log(f"bench: serving {name}: {c0 + n}/{nreq} requests, {secs:.1f} s")
+            if n_total > chunk:
+                log(f"bench: serving {name}: {c0 + n}/{n_total} requests, {secs:.1f} s")
         return serving.summarize(done, wall=secs)
 
     opts = dd.dd_default_opts(tol=1e-9, gather32=gather32)
     srv = serving.Server(systems, prec=dd.DD_MIXED, opts=opts, iters_per_step=4)
+    total_fp = sum(srv.footprint.values())
     try:
         # every system resident (factors formed) before anything is timed
         srv.run(requests(np.zeros(len(keys) * 2)), timeout=300, keep_resident=True)
-        burst = phase("saturated", lambda n, c0: np.zeros(n))
+        burst = phase(srv, "saturated", nreq, lambda n, c0: np.zeros(n))
         rate = 0.8 * burst["requests"] / burst["seconds"]
-        load = phase("load", lambda n, c0: serving.poisson_arrivals(n, rate=rate, seed=seed + 1 + c0))
+        load = phase(srv, "load", nreq_load,
+                     lambda n, c0: serving.poisson_arrivals(n, rate=rate, seed=seed + 1 + c0))
     finally:
         srv.shutdown()
+    budget = int(budget_frac * total_fp)
+    srv_b = serving.Server(systems, prec=dd.DD_MIXED, opts=opts, iters_per_step=4, hbm_budget=budget)
+    try:
+        bud = phase(srv_b, "budget", nreq_budget, lambda n, c0: np.zeros(n))
+        evictions = srv_b.evictions
+    finally:
+        srv_b.shutdown()
     return dict(systems=keys, requests=nreq, rhs_per_request="1-64", rel_resid=1e-9, precision="mixed",
                 fp32_gathers=bool(gather32),
                 saturated_solves_per_s=burst["solves_per_s"], saturated_p50_ms=burst["p50_ms"],
                 saturated_p99_ms=burst["p99_ms"], offered_requests_per_s=rate,
+                load_requests=nreq_load,
                 solves_per_s=load["solves_per_s"], p50_ms=load["p50_ms"], p99_ms=load["p99_ms"],
-                fallbacks=load["fallbacks"] + burst["fallbacks"])
+                fallbacks=load["fallbacks"] + burst["fallbacks"] + bud["fallbacks"],
+                budget=dict(requests=nreq_budget, hbm_budget_bytes=budget, footprint_sum_bytes=total_fp,
+                            evictions=evictions, solves_per_s=bud["solves_per_s"], p50_ms=bud["p50_ms"],
+                            p99_ms=bud["p99_ms"]),
+                note="saturated: requests arrive at once (latency includes queueing); load: Poisson "
+                     "arrivals at 0.8x the saturated rate; budget: HBM budget below the summed "
+                     "footprint, systems evicted and set up again")
 
 
 def next_pow2(n: int) -> int:
@@ -645,7 +675,7 @@ def main():
                     help="processes of the CPU baseline (0 = min(16, host CPUs))")
     ap.add_argument("--cpu-max-cols", type=int, default=32,
                     help="columns of the batch the CPU baseline solves (its bounded sample)")
-    ap.add_argument("--serving-requests", type=int, default=200,
+    ap.add_argument("--serving-requests", type=int, default=10000,
                     help="requests of the serving leg (0 = skip it)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the one-rhs leg on the 2D constant-kernel system")
