@@ -2039,6 +2039,20 @@ __global__ void k_scatter2(int nI, int nG, const int *__restrict__ imap, const i
 }
 
 // y += x on the columns with mask[c] != 0, both parts in one launch.
+// Undo of the last correction of the masked columns: y -= x, or y = 0 when
+// the correction was the whole iterate (zero != 0).
+__global__ void k_undo2_masked(size_t nIe, size_t nGe, int ld, const double *__restrict__ xI,
+                               const double *__restrict__ xG, double *__restrict__ yI,
+                               double *__restrict__ yG, const int *__restrict__ mask, int zero) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nIe + nGe;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int c = (int)(e % ld);
+    if (!mask[c]) continue;
+    if (e < nIe) yI[e] = zero ? 0.0 : yI[e] - xI[e];
+    else yG[e - nIe] = zero ? 0.0 : yG[e - nIe] - xG[e - nIe];
+  }
+}
+
 __global__ void k_axpy2_masked(size_t nIe, size_t nGe, int ld, const double *__restrict__ xI,
                                const double *__restrict__ xG, double *__restrict__ yI,
                                double *__restrict__ yG, const int *__restrict__ mask) {

@@ -2632,13 +2632,14 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
     }
     for (int j = 0; j < kMaxLd; ++j) mask[j] = j < nrhs ? 1 : 0;     // columns of the last inner solve
     std::vector<double> prev(kMaxLd, -1.0);
-    std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0);
+    std::vector<int> stall(kMaxLd, 0), done(kMaxLd, 0), need_fb(kMaxLd, 0), undo(kMaxLd, 0);
     for (int j = nrhs; j < kMaxLd; ++j) done[j] = 1;
     for (int step = 1;; ++step) {
       full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       norm2(w.tI, w.tG, w.rnrm2, 0.0, nullptr);
       TRY(fetch_state(c, &h, false));     // inner iterations, ||b||, ||r||: one wait per step
-      bool any = false;
+      bool any = false, undo_any = false;
+      for (int j = 0; j < kMaxLd; ++j) undo[j] = 0;
       for (int j = 0; j < nrhs; ++j) {
         if (mask[j]) {
           its[j] += h.iters[j];
@@ -2647,9 +2648,20 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
         bn2[j] = h.bnrm2[j];
         rn2[j] = h.rnrm2[j];
         if (step == 1) prev[j] = bn2[j];  // the residual before the first step is b
+        const int stepped = mask[j];
         mask[j] = 0;
         if (done[j]) continue;
         if (rn2[j] <= o.tol * o.tol * bn2[j]) { done[j] = 1; conv[j] = 1; continue; }
+        // a step that made the residual larger (operators too inaccurate in
+        // FP32 for this system) is undone, and the column goes to the FP64 path
+        if (stepped && rn2[j] > prev[j]) {
+          undo[j] = 1;
+          undo_any = true;
+          rn2[j] = prev[j];
+          done[j] = 1;
+          need_fb[j] = 1;
+          continue;
+        }
         if (rn2[j] > 0.25 * prev[j]) {    // reduction worse than 0.5 in norm
           if (++stall[j] >= 2) { done[j] = 1; need_fb[j] = 1; continue; }
         }
@@ -2658,6 +2670,17 @@ dd_status dd_solve(dd_ctx *c, dd_precision prec, const double *b_dev, double *u_
         mask[j] = 1;
         st2[j] = inner_stop2(o.inner_tol, o.tol, rn2[j], bn2[j]);
         any = true;
+      }
+      if (undo_any) {
+        // u -= d (step 0 solved into u itself: u = 0), and t = b - A u again
+        // for the columns the FP64 path finishes
+        int *dm = c->d_solve_mask;
+        HIPCHK(c, hipMemcpyAsync(dm, undo.data(), kMaxLd * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        size_t nIe = (size_t)c->NI * L, nGe = (size_t)c->n_gamma * L;
+        hipLaunchKernelGGL(k_undo2_masked, dim3(std::min(4096u, grid_for(nIe + nGe, 256))), dim3(256), 0,
+                           c->stream, nIe, nGe, L, w.dI, w.dG, w.uI, w.uG, dm, step == 1 ? 1 : 0);
+        HIPCHK(c, hipGetLastError());
+        full_residual(c, w.bI, w.bG, w.uI, w.uG, w.tI, w.tG, L, tl);
       }
       if (!any) break;
       for (int j = nrhs; j < kMaxLd; ++j) { mask[j] = 0; st2[j] = 0.0; }

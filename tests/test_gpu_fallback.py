@@ -193,3 +193,30 @@ def test_interface_free_problem():
         assert oracle.rel_err(u, uref).max() <= gate
         assert all(i["iters"] == 0 for i in r.info) or prec == dd.DD_MIXED
     s.close()
+
+
+def test_replacement_on_ill_conditioned_wide_batch():
+    """The wide-batch mixed solve with both factors formed (FP32 directions,
+    FP64 residual replacement) on the system too ill-conditioned for the
+    FP32 operators: whatever the FP32 directions do (slow progress or a
+    breakdown), the final FP64 check, the refinement behind it and the FP64
+    fallback bring every column to the tolerance."""
+    dd = _dd()
+    d2, A2, _, kappa = ill_conditioned()
+    spec, _, _ = base()
+    b = workloads.rhs(spec, nrhs=8)
+    print(f"case replacement ill-conditioned kappa={kappa:.2e}", flush=True)
+    uref = oracle.monolithic_solve(A2, b)
+    s = dd.Solver(d2, max_nrhs=8)
+    s.factor(dd.DD_FP64)
+    s.factor(dd.DD_MIXED)
+    tol = 1e-8
+    r = s.solve(dev(b), prec=dd.DD_MIXED, raise_on_noconv=False,
+                opts=dd.dd_default_opts(tol=tol, max_it=5000, tiles=1))
+    u = r.u.cpu().numpy().T
+    print(f"  info {r.info}", flush=True)
+    assert r.status == dd.DD_OK
+    assert all(i["converged"] == 1 for i in r.info), r.info
+    assert oracle.full_residual(A2, u, b).max() <= tol * 1.01
+    assert oracle.rel_err(u, uref).max() <= kappa * tol
+    s.close()
