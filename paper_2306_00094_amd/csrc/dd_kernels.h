@@ -1844,8 +1844,6 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
       beta = rz / st.rz_prev[c];
       act = rr2 > st.stop2[c] ? 1 : 0;
     }
-    sbeta[c] = beta;
-    sact[c] = act;
     if (all) {
       if (act0 && brk) st.flag[0] = 1;            // breakdown: p^T q <= 0
       if (act0 && !brk) {
@@ -1853,17 +1851,23 @@ k_cg_direction_state(int nrows, int ld, const double *__restrict__ z, double *__
         st.beta[c] = beta;
         st.rz[c] = rz;
       }
-      st.active[c] = act;
-      st.nrm2[c] = rr2;
       // residual replacement: the reference norm after one, and whether the
-      // column is due for the next
+      // column is due for the next.  A replaced residual no smaller than the
+      // one replaced before means the directions make no progress on the
+      // true residual (operators too inaccurate for the system): the column
+      // stops, and the FP64 check of its residual decides what follows.
       double ref = st.ref2[c];
       if (st.flag[3] && act0 && !brk) {     // replaced in this step
+        if (!(rr2 < ref)) act = 0;
         ref = rr2;
         st.ref2[c] = ref;
       }
       sdue[c] = (act && rr2 < drop2 * ref) ? 1 : 0;
+      st.active[c] = act;
+      st.nrm2[c] = rr2;
     }
+    sbeta[c] = beta;
+    sact[c] = act;
   }
   __syncthreads();
   if (all && threadIdx.x < kWave) {
