@@ -378,7 +378,7 @@ void spinv(dd_feti_ctx *f, const double *x, double *out, int ld) {
 #define DD_WT(NCB)                                                                                  \
   hipLaunchKernelGGL((k_dense_tiles<double, NCB>), g, b, 0, f->stream, f->NU, f->d_witems, f->W,      \
                      f->d_wtoff, f->d_wioff, f->d_wni, in, ld, (const double *)nullptr, 1.0, out, \
-                     (const int *)nullptr)
+                     (const int *)nullptr, (float *)nullptr)
   if (ld <= 16) DD_WT(1);
   else if (ld <= 32) DD_WT(2);
   else DD_WT(4);

@@ -701,7 +701,7 @@ void gamma_apply(dd_ctx *c, int prec, Src p, const double *z, int ld, const doub
 template <typename VT, int NCB, bool DOT>
 void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const double *x1,
                         const double *x2, int ld, const double *base, double c1, double c2,
-                        double *out, const int *run) {
+                        double *out, const int *run, const float *x1f, const float *x2f) {
   const int nrb = interface_rows ? c->t_nrbG : c->t_nrbI;
   const int nrows = interface_rows ? c->n_gamma : c->NI;
   if (nrb <= 0) return;
@@ -715,10 +715,10 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
   auto launch = [&](auto kern) {
     if (DOT && kernel_events(c, DD_PHASE_GAMMA, &e0, &e1))
       hipExtLaunchKernelGGL(kern, g, b, 0, c->stream, e0, e1, 0, nrb, nrows, ptr, split, col, val, x1,
-                            c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red, run);
+                            c->n_gamma, x2, n2, ld, base, c1, c2, out, c->red, run, x1f, x2f);
     else
       hipLaunchKernelGGL(kern, g, b, 0, c->stream, nrb, nrows, ptr, split, col, val, x1, c->n_gamma, x2, n2,
-                         ld, base, c1, c2, out, c->red, run);
+                         ld, base, c1, c2, out, c->red, run, x1f, x2f);
   };
   // two entries' operands in flight per wave: three or four measured slower on
   // the peridynamic 32-column batch (FP64 interface launch 78 -> 81 us with
@@ -732,18 +732,22 @@ void launch_tile_rows_t(dd_ctx *c, bool interface_rows, const VT *val, const dou
 // coupling values of `prec` (interface_rows: [K_GG | K_GI], else K_IG).  With
 // both parts c2 must be c1 or -c1 (the kernel sums both parts in one
 // accumulator).
+// (x1f, x2f: FP32 copies of x1, x2 for the FP32 units; nullptr: none)
 template <bool DOT>
 void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const double *x2, int ld,
-               const double *base, double c1, double c2, double *out, const int *run = nullptr) {
+               const double *base, double c1, double c2, double *out, const int *run = nullptr,
+               const float *x1f = nullptr, const float *x2f = nullptr) {
   // FP64 values straight from the setup copies: the FP64 residual of the mixed
   // path runs on contexts whose FP64 operators were never formed
   const void *v = prec == DD_FP64 ? (interface_rows ? (const void *)c->d_tG_val64 : (const void *)c->d_tI_val64)
                                   : (interface_rows ? c->op[prec].tG_val : c->op[prec].tI_val);
 #define DD_TR(NCB)                                                                                     \
   if (prec == DD_FP64)                                                                                 \
-    launch_tile_rows_t<double, NCB, DOT>(c, interface_rows, (const double *)v, x1, x2, ld, base, c1, c2, out, run); \
+    launch_tile_rows_t<double, NCB, DOT>(c, interface_rows, (const double *)v, x1, x2, ld, base, c1, c2, out, run, \
+                                         nullptr, nullptr);                                            \
   else                                                                                                 \
-    launch_tile_rows_t<float, NCB, DOT>(c, interface_rows, (const float *)v, x1, x2, ld, base, c1, c2, out, run)
+    launch_tile_rows_t<float, NCB, DOT>(c, interface_rows, (const float *)v, x1, x2, ld, base, c1, c2, out, run, \
+                                        x1f, x2f)
   if (ld <= 16) { DD_TR(1); }
   else if (ld <= 32) { DD_TR(2); }
   else { DD_TR(4); }
@@ -752,13 +756,14 @@ void tile_rows(dd_ctx *c, int prec, bool interface_rows, const double *x1, const
 
 // w = base + sign * B y for the dense interior blocks B (kinv of `prec`, or the
 // FP64 blocks K_II themselves when kii is set).
+// (w32: also an FP32 copy of w when not nullptr)
 void dense_tiles(dd_ctx *c, int prec, bool kii, const double *y, int ld, const double *base, double sign,
-                 double *w, const int *run = nullptr) {
+                 double *w, const int *run = nullptr, float *w32 = nullptr) {
   if (c->n_dit <= 0) return;
   const dim3 g(c->n_dit), b(kTW * kWave);
 #define DD_DT(MT, NCB, BLK)                                                                                \
   hipLaunchKernelGGL((k_dense_tiles<MT, NCB>), g, b, 0, c->stream, c->NI, c->d_dit, (const MT *)(BLK),   \
-                     c->d_toff, c->d_ioff, c->d_ni, y, ld, base, sign, w, run)
+                     c->d_toff, c->d_ioff, c->d_ni, y, ld, base, sign, w, run, w32)
   if (kii || prec == DD_FP64) {
     const void *blk = kii ? (const void *)c->d_kii_t : c->op[DD_FP64].kinv_t;
     if (ld <= 16) DD_DT(double, 1, blk);
@@ -1243,6 +1248,11 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
                    o.apply != DD_APPLY_TRSM && o.launch != DD_LAUNCH_PERSISTENT &&
                    (cg3 || c->direction_kernel);
   const int sched = (cg3 ? 1 : 0) | (g32 ? 2 : 0) | (tl ? 4 : 0);
+  // tiled mixed path: FP32 copies of p and w for the FP32 unit products
+  // (which round their slices to FP32 anyway: the same sums from half the
+  // slice bytes)
+  const bool s32 = tl && prec == DD_MIXED;
+  float *p32 = s32 ? w.p32 : nullptr, *w32 = s32 ? w.w32 : nullptr;
   struct ResetG32 { dd_ctx *c; ~ResetG32() { c->g32 = Gather32{}; } } reset_g32{c};
   c->tev_cg3_ld = cg3 ? ld : 0;
   // CG init: x = 0, z = D^-1 r, previous direction 0 (beta = 0)
@@ -1255,6 +1265,9 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     // four launches: p (from the init and the direction kernel) and w (from the
     // interior solve) also written in FP32 for the gathers of the loop below
     if (g32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, w.w32, nullptr};
+    // tiled mixed path: p also in FP32 (from the init and the direction
+    // launch), the slices the FP32 unit products load
+    if (s32) c->g32 = Gather32{nullptr, nullptr, nullptr, w.p32, nullptr, nullptr};
     launch_update(c, 0, ld, nrhs, op.dinv, uG, w.rG, w.zG, pA, w.qG, o.precond, nullptr,
                   dkv, nullptr, 0, tl ? 1 : 0);
   }
@@ -1299,13 +1312,13 @@ dd_status core_solve(dd_ctx *c, int prec, const double *bI, const double *bG, do
     if (tl) {
       {
         PhaseTimer t(c, DD_PHASE_KIG);
-        tile_rows<false>(c, prec, false, pA_, nullptr, ld, nullptr, 1.0, 0.0, w.yI, run);
+        tile_rows<false>(c, prec, false, pA_, nullptr, ld, nullptr, 1.0, 0.0, w.yI, run, p32);
       }
       {
         PhaseTimer t(c, DD_PHASE_INTERIOR);
-        dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, w.wI, run);
+        dense_tiles(c, prec, false, w.yI, ld, nullptr, 1.0, w.wI, run, w32);
       }
-      tile_rows<true>(c, prec, true, pA_, w.wI, ld, nullptr, 1.0, -1.0, w.qG, run);
+      tile_rows<true>(c, prec, true, pA_, w.wI, ld, nullptr, 1.0, -1.0, w.qG, run, p32, w32);
     } else {
       {
         PhaseTimer t(c, DD_PHASE_KIG);

@@ -118,6 +118,17 @@ __device__ __forceinline__ void slice_row(const double *__restrict__ p, double (
     for (int q = 0; q < NCB; ++q) v[q] = w[q];
   }
 }
+template <int NCB>
+__device__ __forceinline__ void slice_row(const float *__restrict__ p, float (&v)[NCB]) {
+  if constexpr (NCB == 1) {
+    v[0] = p[0];
+  } else {
+    typedef float vt __attribute__((ext_vector_type(NCB)));
+    const vt w = *(const vt *)p;
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) v[q] = w[q];
+  }
+}
 
 // One 8-row slice of x (rows cb*8 .. cb*8+7, DD layout with leading
 // dimension ld) in the B-operand order: lane l takes row cb*8 + 4 s + l/16 for
@@ -129,6 +140,18 @@ __device__ __forceinline__ void load_slice(const double *__restrict__ x, int n, 
                                            double (&xv)[2][NCB]) {
   const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const double *p = x + slice_col0<NCB>(l16, ld);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int row = min(cb * kTU + 4 * s + g, n - 1);
+    slice_row<NCB>(p + (size_t)row * ld, xv[s]);
+  }
+}
+// (FP32 copy of the vector: the same slices, half the bytes)
+template <int NCB>
+__device__ __forceinline__ void load_slice(const float *__restrict__ x, int n, int ld, int cb,
+                                           float (&xv)[2][NCB]) {
+  const int lane = lane_id(), g = lane >> 4, l16 = lane & 15;
+  const float *p = x + slice_col0<NCB>(l16, ld);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int row = min(cb * kTU + 4 * s + g, n - 1);
@@ -198,9 +221,9 @@ __device__ __forceinline__ void tile_row_acc(int t0, int t1, int st, const int *
 // each entry's sums are added to the FP64 accumulators, so FP32 rounding
 // enters only within one entry.  The accumulators hold rows in the FP32
 // instruction's order (row 4 (l / 16) + r of lane l, register r).
-template <int NCB, int D, int RB>
+template <int NCB, int D, int RB, typename XT>
 __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const int *__restrict__ tcol,
-                                                 const float *__restrict__ tval, const double *__restrict__ x,
+                                                 const float *__restrict__ tval, const XT *__restrict__ x,
                                                  int n, int ld, double sgn, dbl4 (&acc)[RB][NCB]) {
   const int cnt = t0 < t1 ? (t1 - t0 + st - 1) / st : 0;
   const int lane = lane_id();
@@ -211,7 +234,7 @@ __device__ __forceinline__ void tile_row_acc_f32(int t0, int t1, int st, const i
     const float *tv = tval + (size_t)(t0 + base * st) * RB * kUV;
     const size_t tstride = (size_t)st * RB * kUV;
     float a[D][RB][2];
-    double xs[D][2][NCB];
+    XT xs[D][2][NCB];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int jd = min(d, nb - 1);
@@ -294,13 +317,15 @@ constexpr int kTW = 4;
 // which the update kernel reduces (the step length of the CG iteration, from
 // p^T S p).  run (may be nullptr): the CG loop's flag of columns still
 // iterating; when it reads 0 the launch does nothing (the loop's host runs a
-// few iterations ahead of the device).
+// few iterations ahead of the device).  x1f, x2f (FP32 units only; may be
+// nullptr): FP32 copies of x1, x2 whose slices the products load instead.
 template <typename VT, int NCB, bool DOT, int D, int RB>
 __global__ void __launch_bounds__(kTW * kWave)
 k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restrict__ split,
             const int *__restrict__ tcol, const VT *__restrict__ tval, const double *__restrict__ x1,
             int n1, const double *__restrict__ x2, int n2, int ld, const double *__restrict__ base,
-            double c1, double c2, double *__restrict__ out, RedBuf red, const int *__restrict__ run) {
+            double c1, double c2, double *__restrict__ out, RedBuf red, const int *__restrict__ run,
+            const float *__restrict__ x1f, const float *__restrict__ x2f) {
   if (run && *run == 0) return;                  // every column of the CG loop has stopped
   constexpr int H = RB * kT;                     // rows of a block
   const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
@@ -331,8 +356,16 @@ k_tile_rows(int nrb, int nrows, const int *__restrict__ ptr, const int *__restri
     xd[u] = (DOT && el < nel && row < nrows) ? x1[(size_t)row * ld + (el - lr * ld)] : 0.0;
   }
   if constexpr (std::is_same<VT, float>::value) {
-    if (c1 != 0.0) tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
-    if (split && c2 != 0.0) tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
+    // (x1f, x2f: FP32 copies of x1, x2 -- the products round the slices to
+    // FP32 anyway, so the sums are the same bit for bit, from half the bytes)
+    if (c1 != 0.0) {
+      if (x1f) tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1f, n1, ld, 1.0, acc);
+      else tile_row_acc_f32<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
+    }
+    if (split && c2 != 0.0) {
+      if (x2f) tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2f, n2, ld, sg2, acc);
+      else tile_row_acc_f32<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
+    }
   } else {
     if (c1 != 0.0) tile_row_acc<NCB, D, RB>(b + wv, s, kTW, tcol, tval, x1, n1, ld, 1.0, acc);
     if (split && c2 != 0.0) tile_row_acc<NCB, D, RB>(s + wv, e, kTW, tcol, tval, x2, n2, ld, sg2, acc);
@@ -452,7 +485,7 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
               const long long *__restrict__ toff, const int *__restrict__ ioff,
               const int *__restrict__ ni, const double *__restrict__ y, int ld,
               const double *__restrict__ base, double sign, double *__restrict__ w,
-              const int *__restrict__ run) {
+              const int *__restrict__ run, float *__restrict__ w32) {
   if (run && *run == 0) return;                  // every column of the CG loop has stopped
   const int wv = wave_uniform(), lane = lane_id(), g = lane >> 4, l16 = lane & 15;
   const int2 item = items[blockIdx.x];
@@ -523,7 +556,9 @@ k_dense_tiles(int nall, const int2 *__restrict__ items, const MT *__restrict__ p
 #pragma unroll
       for (int u = 1; u < kTW; ++u) v += part[u * nel + el];
       const size_t o = (size_t)(i0 + row) * ld + c;
-      w[o] = (base ? base[o] : 0.0) + sign * v;
+      const double wv2 = (base ? base[o] : 0.0) + sign * v;
+      w[o] = wv2;
+      if (w32) w32[o] = (float)wv2;          // FP32 copy for the FP32 unit products
     }
   }
 }
