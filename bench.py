@@ -63,12 +63,12 @@ WORKLOADS = {
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
     # 2D peridynamics h = 1/160, 32 rhs: medians over the CG iterations' launches
-    "k_tile_rows<double,2,true>": dict(src="dd_tiles.h", sha="ecd2e7e5244ac738", workload="cfg4",
-                                       fetch_kib=160065.4, write_kib=9624.3,
-                                       fetch_scale=262144.0 / 131087.3, write_scale=262144.0 / 262147.4),
-    "k_tile_rows<float,2,true>": dict(src="dd_tiles.h", sha="ecd2e7e5244ac738", workload="cfg4",
-                                      fetch_kib=84628.7, write_kib=9624.3,
-                                      fetch_scale=262144.0 / 131087.3, write_scale=262144.0 / 262147.4),
+    "k_tile_rows<double,2,true>": dict(src="dd_tiles.h", sha="7e9d81ffc6acec94", workload="cfg4",
+                                       fetch_kib=160066.1, write_kib=9624.3,
+                                       fetch_scale=262144.0 / 131086.8, write_scale=262144.0 / 262146.9),
+    "k_tile_rows<float,2,true>": dict(src="dd_tiles.h", sha="7e9d81ffc6acec94", workload="cfg4",
+                                      fetch_kib=82966.3, write_kib=9624.3,
+                                      fetch_scale=262144.0 / 131086.8, write_scale=262144.0 / 262146.9),
 }
 
 
