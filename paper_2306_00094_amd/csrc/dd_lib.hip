@@ -2084,12 +2084,12 @@ dd_status dd_autotune(dd_ctx *c, dd_precision prec, int32_t nrhs, const dd_solve
   }
   // batches of kTileMinLd or more columns: the tiled matrix-core products
   // (mixed precision with the FP64 factor formed: they replace residuals,
-  // and each launch mode is timed at three drop factors)
+  // and each launch mode is timed at four drop factors)
   const bool can_replace = prec == DD_MIXED && o.reliable != 0 && !(o.inner_tol > 0.0) &&
                            c->op[DD_FP64].ready && c->op[DD_FP64].kinv_t;
   if (c->tiles && next_pow2(nrhs) >= kTileMinLd) {
     if (can_replace) {
-      for (double drop : {1e-2, 3e-3, 1e-3}) {
+      for (double drop : {1e-2, 3e-3, 1e-3, 1e-4}) {
         cands.push_back({DD_APPLY_INV, DD_LAUNCH_KERNELS, 1, 2, 4, drop});
         cands.push_back({DD_APPLY_INV, DD_LAUNCH_GRAPH, 1, 4, 4, drop});
       }
